@@ -1,0 +1,426 @@
+/*
+ * lbm_oracle.c -- plain FP64 CPU oracle of the coupled lattice-Boltzmann /
+ * immersed-boundary step of Wu, Xu, Kim & Alber, "Three-dimensional multiscale
+ * model of deformable platelets adhesion to vessel wall in blood flow"
+ * (arXiv:1312.2234).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the independent reference that the GPU
+ * library is checked against.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load it; the product path never does, and
+ * it shares no source, header, table or helper with the GPU library.
+ *
+ * Every routine is the definition from the paper written out with loops, in
+ * double precision, without blocking, fusion or reordering:
+ *   - D3Q19 velocities, weights and numbering: Eq. (21) and the numbering implied
+ *     by the on-site wall equations Eq. (23)-(30) (the velocity figure is absent),
+ *   - density and momentum: Eq. (17)-(18); velocity shift v = u + F dt / 2 rho
+ *     stated beneath Eq. (19),
+ *   - equilibrium: Eq. (20); BGK collision Eq. (16); Guo forced update Eq. (19),
+ *   - immersed-boundary spreading / interpolation: Eq. (33)-(36),
+ *   - spring forces of the membrane network: Eq. (2)-(3),
+ *   - per-step order: Fig. 1 (forces -> spread -> LBM -> interpolate -> move).
+ *
+ * Readings where the paper is silent, garbled or inconsistent (the design notes
+ * list them with reasons):
+ *   R1  Eq. (19) prints "+ c_s^2 I" in the second-order source term; the oracle
+ *       uses "- c_s^2 I" (Guo et al. 2002), without which sum_i S_i != 0 and the
+ *       scheme creates mass.
+ *   R2  Both the equilibrium and the source use the shifted velocity v.
+ *   R3  Eq. (36) prints the zero branch of phi as "|x| <= 2"; read as |x| >= 2.
+ *   R4  Walls: halfway bounce-back with the moving-wall term 6 w_i rho_w c_i.u_w
+ *       (rho_w = 1) on planes y = -1/2 and y = ny - 1/2 (wall normal along y);
+ *       x and z are periodic.  (The paper's own on-site wall of Eq. (23)-(30) is
+ *       a later extension.)
+ *   R5  The interpolated velocity is v^{n+1} = (sum c f^{n+1} + (F_body + g^n)/2)
+ *       / rho^{n+1}, the field after the LBM step (Fig. 1), taken at X^n; stencil
+ *       rows inside a wall take that wall's velocity; spreading drops them.
+ *   R6  Position update: explicit Euler, dt = 1.
+ *   R7  Eq. (3) gives the force on node i as -k(|R|-L)R/|R| with R = X_j - X_i;
+ *       as the negative gradient of Eq. (2) the force on i is +k(|R|-L)R/|R|
+ *       (a stretched spring pulls its ends together).  The oracle follows the
+ *       gradient of the energy.
+ *   R8  Bending stand-in for the finite-element bending of Eq. (6)-(10): the
+ *       dihedral energy E = k_b sum_hinges (1 - cos(theta - theta_0)).
+ *
+ * Units: lattice units, h = dt = rho_0 = 1.  Arrays are SoA, x fastest:
+ * node index n = x + nx*(y + ny*z); populations f[i*N + n] in paper order
+ * i = 1..19 stored at 0..18; vector fields v[d*N + n].
+ *
+ * Build: gcc -O2 -fopenmp -fPIC -shared -o liboracle.so lbm_oracle.c -lm
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define Q 19
+
+/* Eq. (21) weights and the D3Q19 set in the paper's numbering (1..19 -> 0..18).
+ * The numbering is the one fixed by Eq. (23)-(30): c_z = 0 for 1,2,3,4,7,8,11,12,19;
+ * c_z = -1 for 6,10,14,16,18; c_z = +1 for 5,9,13,15,17; opposite pairs from
+ * Eq. (24)-(28); signs of c_x, c_y from Eq. (29)-(30). */
+static const int CV[Q][3] = {
+    {+1, 0, 0}, {-1, 0, 0}, {0, +1, 0}, {0, -1, 0}, {0, 0, +1}, {0, 0, -1},
+    {+1, +1, 0}, {+1, -1, 0}, {+1, 0, +1}, {+1, 0, -1},
+    {-1, +1, 0}, {-1, -1, 0}, {-1, 0, +1}, {-1, 0, -1},
+    {0, +1, +1}, {0, +1, -1}, {0, -1, +1}, {0, -1, -1},
+    {0, 0, 0}};
+static const double WT[Q] = {
+    2.0 / 36, 2.0 / 36, 2.0 / 36, 2.0 / 36, 2.0 / 36, 2.0 / 36,
+    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+    12.0 / 36};
+static const double CS2 = 1.0 / 3.0; /* c_s^2, text under Eq. (20) */
+
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t walls;   /* 1: bounce-back walls normal to y; 0: periodic in y too */
+    double tau;
+    double body[3];  /* constant body force, added to the IB force field */
+    double uw_lo[3]; /* velocity of the wall at y = -1/2 */
+    double uw_hi[3]; /* velocity of the wall at y = ny - 1/2 */
+} orc_params;
+
+/* accessors so that tests can check the tables against the paper */
+void orc_tables(int32_t* c, double* w, int32_t* opp) {
+    for (int i = 0; i < Q; ++i) {
+        for (int d = 0; d < 3; ++d) c[3 * i + d] = CV[i][d];
+        w[i] = WT[i];
+        int o = -1;
+        for (int j = 0; j < Q; ++j)
+            if (CV[j][0] == -CV[i][0] && CV[j][1] == -CV[i][1] && CV[j][2] == -CV[i][2]) o = j;
+        opp[i] = o;
+    }
+}
+
+static int opposite(int i) {
+    for (int j = 0; j < Q; ++j)
+        if (CV[j][0] == -CV[i][0] && CV[j][1] == -CV[i][1] && CV[j][2] == -CV[i][2]) return j;
+    return -1;
+}
+
+static int64_t wrap(int64_t a, int64_t n) { int64_t r = a % n; return r < 0 ? r + n : r; }
+
+/* Eq. (20): f_i^eq(rho, v) = w_i rho [1 + c.v/cs2 + (c.v)^2/(2 cs2^2) - v.v/(2 cs2)] */
+void orc_feq(double rho, const double* v, double* feq) {
+    double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    for (int i = 0; i < Q; ++i) {
+        double cv = CV[i][0] * v[0] + CV[i][1] * v[1] + CV[i][2] * v[2];
+        feq[i] = WT[i] * rho * (1.0 + cv / CS2 + cv * cv / (2.0 * CS2 * CS2) - vv / (2.0 * CS2));
+    }
+}
+
+/* Eq. (19) source term with dt = 1 and reading R1:
+ * S_i = w_i (1 - 1/(2 tau)) [ (F.c_i)/cs2 + (v F^T + F v^T) : (c_i c_i^T - cs2 I) / (2 cs2^2) ] */
+void orc_source(double tau, const double* v, const double* F, double* S) {
+    for (int i = 0; i < Q; ++i) {
+        double Fc = F[0] * CV[i][0] + F[1] * CV[i][1] + F[2] * CV[i][2];
+        double contr = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double A = v[a] * F[b] + F[a] * v[b];
+                double B = (double)CV[i][a] * CV[i][b] - (a == b ? CS2 : 0.0);
+                contr += A * B;
+            }
+        S[i] = WT[i] * (1.0 - 1.0 / (2.0 * tau)) * (Fc / CS2 + contr / (2.0 * CS2 * CS2));
+    }
+}
+
+/* Eq. (36) (reading R3) and the Peskin 4-point kernel (kernel = 1). */
+double orc_phi(int32_t kernel, double r) {
+    double a = fabs(r);
+    if (kernel == 0) {
+        if (a >= 2.0) return 0.0;
+        return 0.25 * (1.0 + cos(M_PI * r / 2.0));
+    }
+    if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a)) / 8.0;
+    if (a <= 2.0) return (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a)) / 8.0;
+    return 0.0;
+}
+
+/* f = f^eq(rho, u) at every node; rho == NULL means 1, u == NULL means 0. */
+void orc_init(const orc_params* p, double* f, const double* rho, const double* u) {
+    int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    for (int64_t n = 0; n < N; ++n) {
+        double r = rho ? rho[n] : 1.0;
+        double v[3] = {u ? u[n] : 0.0, u ? u[N + n] : 0.0, u ? u[2 * N + n] : 0.0};
+        double feq[Q];
+        orc_feq(r, v, feq);
+        for (int i = 0; i < Q; ++i) f[i * N + n] = feq[i];
+    }
+}
+
+/* Eq. (17)-(18) and the shift under Eq. (19):
+ * rho = sum f, v = (sum c f + F/2) / rho with F = F_body + g(x). */
+void orc_moments(const orc_params* p, const double* f, const double* g, double* rho, double* v) {
+    int64_t N = (int64_t)p->nx * p->ny * p->nz;
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        double r = 0.0, j[3] = {0, 0, 0};
+        for (int i = 0; i < Q; ++i) {
+            r += f[i * N + n];
+            for (int d = 0; d < 3; ++d) j[d] += CV[i][d] * f[i * N + n];
+        }
+        rho[n] = r;
+        for (int d = 0; d < 3; ++d) {
+            double F = p->body[d] + (g ? g[d * N + n] : 0.0);
+            v[d * N + n] = (j[d] + 0.5 * F) / r;
+        }
+    }
+}
+
+/* One LBM time step, Eq. (16), (19), (20), (reading R4 at walls):
+ * collide  f*_i(x) = f_i - (f_i - f_i^eq(rho, v))/tau + S_i(v, F),
+ * stream   f_i(x, t+1) = f*_i(x - c_i); across a wall
+ *          f_i(x, t+1) = f*_{opp(i)}(x) + 6 w_i rho_w c_i.u_w. */
+void orc_step(const orc_params* p, const double* f, const double* g, double* fout) {
+    int64_t nx = p->nx, ny = p->ny, nz = p->nz, N = nx * ny * nz;
+    double* fs = (double*)malloc(sizeof(double) * Q * N);
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        double r = 0.0, j[3] = {0, 0, 0}, F[3], v[3], feq[Q], S[Q];
+        for (int i = 0; i < Q; ++i) {
+            r += f[i * N + n];
+            for (int d = 0; d < 3; ++d) j[d] += CV[i][d] * f[i * N + n];
+        }
+        for (int d = 0; d < 3; ++d) {
+            F[d] = p->body[d] + (g ? g[d * N + n] : 0.0);
+            v[d] = (j[d] + 0.5 * F[d]) / r;
+        }
+        orc_feq(r, v, feq);
+        orc_source(p->tau, v, F, S);
+        for (int i = 0; i < Q; ++i)
+            fs[i * N + n] = f[i * N + n] - (f[i * N + n] - feq[i]) / p->tau + S[i];
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                int64_t n = x + nx * (y + ny * z);
+                for (int i = 0; i < Q; ++i) {
+                    int64_t ys = y - CV[i][1];
+                    if (p->walls && (ys < 0 || ys >= ny)) {
+                        const double* uw = ys < 0 ? p->uw_lo : p->uw_hi;
+                        double cu = CV[i][0] * uw[0] + CV[i][1] * uw[1] + CV[i][2] * uw[2];
+                        fout[i * N + n] = fs[opposite(i) * N + n] + 6.0 * WT[i] * 1.0 * cu;
+                    } else {
+                        int64_t xs = wrap(x - CV[i][0], nx);
+                        int64_t zs = wrap(z - CV[i][2], nz);
+                        ys = wrap(ys, ny);
+                        fout[i * N + n] = fs[i * N + xs + nx * (ys + ny * zs)];
+                    }
+                }
+            }
+    free(fs);
+}
+
+/* Eq. (34)-(35) with h = 1: g(x) = sum_m F_m phi(x-X_mx) phi(y-X_my) phi(z-X_mz)
+ * over the 4x4x4 stencil floor(X)-1 .. floor(X)+2; x, z periodic; rows outside
+ * [0, ny) are dropped when walls are present (reading R5), wrapped otherwise. */
+void orc_spread(const orc_params* p, int32_t kernel, int64_t nn, const double* X, const double* Fm,
+                double* g) {
+    int64_t nx = p->nx, ny = p->ny, nz = p->nz, N = nx * ny * nz;
+    memset(g, 0, sizeof(double) * 3 * N);
+    for (int64_t m = 0; m < nn; ++m) {
+        double Xm[3] = {X[m], X[nn + m], X[2 * nn + m]};
+        int64_t b[3];
+        for (int d = 0; d < 3; ++d) b[d] = (int64_t)floor(Xm[d]) - 1;
+        for (int c = 0; c < 4; ++c)
+            for (int bb = 0; bb < 4; ++bb)
+                for (int a = 0; a < 4; ++a) {
+                    int64_t xi = b[0] + a, yi = b[1] + bb, zi = b[2] + c;
+                    double w = orc_phi(kernel, (double)xi - Xm[0]) * orc_phi(kernel, (double)yi - Xm[1]) *
+                               orc_phi(kernel, (double)zi - Xm[2]);
+                    if (p->walls && (yi < 0 || yi >= ny)) continue;
+                    int64_t n = wrap(xi, nx) + nx * (wrap(yi, ny) + ny * wrap(zi, nz));
+                    for (int d = 0; d < 3; ++d) g[d * N + n] += Fm[d * nn + m] * w;
+                }
+    }
+}
+
+/* Eq. (33) with h = 1: U_m = sum_x v(x) phi phi phi over the same stencil;
+ * stencil rows inside a wall contribute that wall's velocity (reading R5). */
+void orc_interp(const orc_params* p, int32_t kernel, int64_t nn, const double* X, const double* v,
+                double* U) {
+    int64_t nx = p->nx, ny = p->ny, nz = p->nz, N = nx * ny * nz;
+#pragma omp parallel for schedule(static)
+    for (int64_t m = 0; m < nn; ++m) {
+        double Xm[3] = {X[m], X[nn + m], X[2 * nn + m]};
+        int64_t b[3];
+        for (int d = 0; d < 3; ++d) b[d] = (int64_t)floor(Xm[d]) - 1;
+        double acc[3] = {0, 0, 0};
+        for (int c = 0; c < 4; ++c)
+            for (int bb = 0; bb < 4; ++bb)
+                for (int a = 0; a < 4; ++a) {
+                    int64_t xi = b[0] + a, yi = b[1] + bb, zi = b[2] + c;
+                    double w = orc_phi(kernel, (double)xi - Xm[0]) * orc_phi(kernel, (double)yi - Xm[1]) *
+                               orc_phi(kernel, (double)zi - Xm[2]);
+                    if (p->walls && (yi < 0 || yi >= ny)) {
+                        const double* uw = yi < 0 ? p->uw_lo : p->uw_hi;
+                        for (int d = 0; d < 3; ++d) acc[d] += uw[d] * w;
+                    } else {
+                        int64_t n = wrap(xi, nx) + nx * (wrap(yi, ny) + ny * wrap(zi, nz));
+                        for (int d = 0; d < 3; ++d) acc[d] += v[d * N + n] * w;
+                    }
+                }
+        for (int d = 0; d < 3; ++d) U[d * nn + m] = acc[d];
+    }
+}
+
+/* Reading R6: X <- X + U (dt = 1). */
+void orc_advance(int64_t nn, double* X, const double* U) {
+    for (int64_t k = 0; k < 3 * nn; ++k) X[k] += U[k];
+}
+
+/* Viscous shear stress at the two wall-adjacent rows, y = 0 and y = ny-1:
+ * sigma_ab = -(1 - 1/(2 tau)) sum_i c_ia c_ib (f_i - f_i^eq(rho, v))
+ *            - (1 - 1/(2 tau)) (F_a v_b + F_b v_a) / 2,
+ * the stress of the Guo-forced BGK scheme (the paper gives no formula).
+ * Output per row: [2][nz][nx] = sigma_xy, sigma_zy. */
+void orc_wall_stress(const orc_params* p, const double* f, const double* g, double* lo, double* hi) {
+    int64_t nx = p->nx, ny = p->ny, nz = p->nz, N = nx * ny * nz;
+    double k = 1.0 - 1.0 / (2.0 * p->tau);
+    for (int side = 0; side < 2; ++side) {
+        int64_t y = side == 0 ? 0 : ny - 1;
+        double* out = side == 0 ? lo : hi;
+        for (int64_t z = 0; z < nz; ++z)
+            for (int64_t x = 0; x < nx; ++x) {
+                int64_t n = x + nx * (y + ny * z);
+                double r = 0.0, j[3] = {0, 0, 0}, F[3], v[3], feq[Q];
+                for (int i = 0; i < Q; ++i) {
+                    r += f[i * N + n];
+                    for (int d = 0; d < 3; ++d) j[d] += CV[i][d] * f[i * N + n];
+                }
+                for (int d = 0; d < 3; ++d) {
+                    F[d] = p->body[d] + (g ? g[d * N + n] : 0.0);
+                    v[d] = (j[d] + 0.5 * F[d]) / r;
+                }
+                orc_feq(r, v, feq);
+                const int comps[2] = {0, 2};
+                for (int q = 0; q < 2; ++q) {
+                    int a = comps[q], b = 1;
+                    double s = 0.0;
+                    for (int i = 0; i < Q; ++i) s += (double)CV[i][a] * CV[i][b] * (f[i * N + n] - feq[i]);
+                    out[q * nz * nx + z * nx + x] = -k * s - k * 0.5 * (F[a] * v[b] + F[b] * v[a]);
+                }
+            }
+    }
+}
+
+/* ---------------------------------------------------------------- membrane forces
+ * Inputs of the coupled step (Fig. 1, first box); X, anchors: [3][n].
+ *  springs  Eq. (2)-(3) (reading R7): edges (i,j), rest length L = |X_j - X_i| of the
+ *           rest shape, U = k/2 (|R| - L)^2, force on i = +k (|R| - L) R/|R|;
+ *  tethers  U = k_t/2 |X - A|^2, force = -k_t (X - A);
+ *  bending  (reading R8) hinges (x0, x1, x2, x3): shared edge x1-x2, triangles
+ *           (x0,x1,x2) and (x3,x2,x1); E = k_b (1 - cos(theta - theta0)). */
+static void sub3(const double* a, const double* b, double* o) { for (int d = 0; d < 3; ++d) o[d] = a[d] - b[d]; }
+static void cross3(const double* a, const double* b, double* o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void getp(const double* X, int64_t nn, int64_t i, double* o) { for (int d = 0; d < 3; ++d) o[d] = X[d * nn + i]; }
+
+/* signed dihedral angle: atan2((nA^ x nB^).e^, nA^.nB^), nA = (x1-x0)x(x2-x0), nB = (x2-x3)x(x1-x3) */
+static double hinge_angle(const double* x0, const double* x1, const double* x2, const double* x3) {
+    double a[3], b[3], nA[3], nB[3], e[3], c[3];
+    sub3(x1, x0, a); sub3(x2, x0, b); cross3(a, b, nA);
+    sub3(x2, x3, a); sub3(x1, x3, b); cross3(a, b, nB);
+    sub3(x2, x1, e);
+    double la = sqrt(dot3(nA, nA)), lb = sqrt(dot3(nB, nB)), le = sqrt(dot3(e, e));
+    cross3(nA, nB, c);
+    return atan2(dot3(c, e) / (la * lb * le), dot3(nA, nB) / (la * lb));
+}
+
+void orc_hinge_angles(int64_t nn, const double* X, int64_t nh, const int32_t* hinges, double* theta) {
+    for (int64_t h = 0; h < nh; ++h) {
+        double x[4][3];
+        for (int k = 0; k < 4; ++k) getp(X, nn, hinges[4 * h + k], x[k]);
+        theta[h] = hinge_angle(x[0], x[1], x[2], x[3]);
+    }
+}
+
+void orc_edge_lengths(int64_t nn, const double* X, int64_t ne, const int32_t* edges, double* len) {
+    for (int64_t e = 0; e < ne; ++e) {
+        double a[3], b[3], r[3];
+        getp(X, nn, edges[2 * e], a); getp(X, nn, edges[2 * e + 1], b); sub3(b, a, r);
+        len[e] = sqrt(dot3(r, r));
+    }
+}
+
+/* Total membrane energy (for finite-difference checks of the forces). */
+double orc_membrane_energy(int64_t nn, const double* X, int64_t ne, const int32_t* edges,
+                           const double* rest_len, double k_spring, int64_t nh, const int32_t* hinges,
+                           const double* rest_theta, double k_bend, const double* anchors, double k_tether) {
+    double E = 0.0;
+    for (int64_t e = 0; e < ne; ++e) {
+        double a[3], b[3], r[3];
+        getp(X, nn, edges[2 * e], a); getp(X, nn, edges[2 * e + 1], b); sub3(b, a, r);
+        double s = sqrt(dot3(r, r)) - rest_len[e];
+        E += 0.5 * k_spring * s * s;
+    }
+    for (int64_t h = 0; h < nh; ++h) {
+        double x[4][3];
+        for (int k = 0; k < 4; ++k) getp(X, nn, hinges[4 * h + k], x[k]);
+        E += k_bend * (1.0 - cos(hinge_angle(x[0], x[1], x[2], x[3]) - rest_theta[h]));
+    }
+    if (anchors)
+        for (int64_t i = 0; i < nn; ++i)
+            for (int d = 0; d < 3; ++d) {
+                double s = X[d * nn + i] - anchors[d * nn + i];
+                E += 0.5 * k_tether * s * s;
+            }
+    return E;
+}
+
+/* F = -grad(E) of the energy above, written out term by term. */
+void orc_membrane_forces(int64_t nn, const double* X, int64_t ne, const int32_t* edges,
+                         const double* rest_len, double k_spring, int64_t nh, const int32_t* hinges,
+                         const double* rest_theta, double k_bend, const double* anchors, double k_tether,
+                         double* F) {
+    memset(F, 0, sizeof(double) * 3 * nn);
+    for (int64_t e = 0; e < ne; ++e) {
+        int64_t i = edges[2 * e], j = edges[2 * e + 1];
+        double a[3], b[3], r[3];
+        getp(X, nn, i, a); getp(X, nn, j, b); sub3(b, a, r);
+        double len = sqrt(dot3(r, r));
+        double s = k_spring * (len - rest_len[e]) / len;
+        for (int d = 0; d < 3; ++d) {
+            F[d * nn + i] += s * r[d];
+            F[d * nn + j] -= s * r[d];
+        }
+    }
+    for (int64_t h = 0; h < nh; ++h) {
+        int64_t id[4];
+        double x[4][3];
+        for (int k = 0; k < 4; ++k) { id[k] = hinges[4 * h + k]; getp(X, nn, id[k], x[k]); }
+        double theta = hinge_angle(x[0], x[1], x[2], x[3]);
+        double dEdth = k_bend * sin(theta - rest_theta[h]);
+        /* gradient of theta with respect to the four vertices */
+        double a[3], b[3], nA[3], nB[3], e[3];
+        sub3(x[1], x[0], a); sub3(x[2], x[0], b); cross3(a, b, nA);
+        sub3(x[2], x[3], a); sub3(x[1], x[3], b); cross3(a, b, nB);
+        sub3(x[2], x[1], e);
+        double L = sqrt(dot3(e, e)), AA = dot3(nA, nA), BB = dot3(nB, nB);
+        double qA[3], qB[3];
+        for (int d = 0; d < 3; ++d) { qA[d] = nA[d] / AA; qB[d] = nB[d] / BB; }
+        double t02[3], t32[3], t01[3], t31[3];
+        sub3(x[0], x[2], t02); sub3(x[3], x[2], t32); sub3(x[0], x[1], t01); sub3(x[3], x[1], t31);
+        double c02 = dot3(t02, e) / L, c32 = dot3(t32, e) / L, c01 = dot3(t01, e) / L, c31 = dot3(t31, e) / L;
+        for (int d = 0; d < 3; ++d) {
+            double g0 = -L * qA[d];
+            double g3 = -L * qB[d];
+            double g1 = -c02 * qA[d] - c32 * qB[d];
+            double g2 = c01 * qA[d] + c31 * qB[d];
+            F[d * nn + id[0]] -= dEdth * g0;
+            F[d * nn + id[1]] -= dEdth * g1;
+            F[d * nn + id[2]] -= dEdth * g2;
+            F[d * nn + id[3]] -= dEdth * g3;
+        }
+    }
+    if (anchors)
+        for (int64_t i = 0; i < nn; ++i)
+            for (int d = 0; d < 3; ++d) F[d * nn + i] -= k_tether * (X[d * nn + i] - anchors[d * nn + i]);
+}

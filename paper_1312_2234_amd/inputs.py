@@ -1,0 +1,275 @@
+"""Seeded synthetic inputs shared by the GPU path and the oracle.
+
+This module holds no arithmetic of the method (no lattice-Boltzmann, delta kernel
+or force law): only the workload geometry that both sides receive as plain arrays.
+
+* Platelet shape: an oblate ellipsoid (section 3.1, the shape equation with aspect
+  ratio lambda), meshed as a subdivided icosahedron (642 / 2562 nodes) or as a
+  Fibonacci point set triangulated by its convex hull (any node count, e.g. 1282).
+* Mesh topology: undirected edges (the cytoskeleton springs of Eq. (2)-(3)) and
+  hinges (pairs of triangles sharing an edge, used by the bending term).
+* Placement: uniform in x and z, centroid height uniform in a band above the lower
+  wall (plane y = -1/2), bounding spheres kept apart by rejection (periodic
+  minimum-image distance in x and z).
+* Random draws: numpy PCG64 seeded per workload.
+
+Positions are returned as float64 arrays of shape [3, n] (SoA, as the library takes
+them); connectivity as int32.
+"""
+from __future__ import annotations
+
+import functools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# ----------------------------------------------------------------------------- meshes
+
+
+def icosphere(level: int):
+    """Unit icosphere: 10*4**level + 2 vertices; triangles oriented outward."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    V = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t),
+         (0, 1, -t), (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    V = [np.array(v, float) / np.linalg.norm(v) for v in V]
+    T = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4),
+         (11, 10, 2), (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8),
+         (3, 8, 9), (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(level):
+        cache = {}
+
+        def mid(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in cache:
+                m = V[a] + V[b]
+                V.append(m / np.linalg.norm(m))
+                cache[key] = len(V) - 1
+            return cache[key]
+
+        T2 = []
+        for a, b, c in T:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            T2 += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        T = T2
+    V = np.array(V)
+    T = np.array(T, dtype=np.int32)
+    return V, _orient_outward(V, T)
+
+
+def fibonacci_sphere(n: int):
+    """n points on the unit sphere (golden-angle spiral), triangulated by the convex hull."""
+    from scipy.spatial import ConvexHull
+
+    i = np.arange(n) + 0.5
+    yv = 1.0 - 2.0 * i / n
+    r = np.sqrt(1.0 - yv * yv)
+    ang = np.pi * (3.0 - 5.0 ** 0.5) * np.arange(n)
+    V = np.stack([r * np.cos(ang), yv, r * np.sin(ang)], axis=1)
+    T = ConvexHull(V).simplices.astype(np.int32)
+    return V, _orient_outward(V, T)
+
+
+def unit_sphere(nodes: int):
+    for lev in range(7):
+        if 10 * 4 ** lev + 2 == nodes:
+            return icosphere(lev)
+    return fibonacci_sphere(nodes)
+
+
+def _orient_outward(V, T):
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    cen = (a + b + c) / 3.0
+    flip = np.einsum("ij,ij->i", np.cross(b - a, c - a), cen) < 0
+    T = T.copy()
+    T[flip, 1], T[flip, 2] = T[flip, 2], T[flip, 1].copy()
+    return T
+
+
+def mesh_edges(T):
+    """Unique undirected edges (i < j) of a triangle mesh."""
+    e = np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]])
+    e = np.sort(e, axis=1)
+    return np.unique(e, axis=0).astype(np.int32)
+
+
+def mesh_hinges(T):
+    """Hinges (x0, x1, x2, x3): triangle (x0,x1,x2) and triangle (x3,x2,x1) share edge x1-x2.
+    One hinge per interior edge of a consistently oriented closed mesh."""
+    directed = {}
+    for t in T:
+        for k in range(3):
+            a, b, c = int(t[k]), int(t[(k + 1) % 3]), int(t[(k + 2) % 3])
+            directed[(b, c)] = a  # directed edge b->c, opposite vertex a
+    H = []
+    for (b, c), a in directed.items():
+        if b < c and (c, b) in directed:
+            H.append((a, b, c, directed[(c, b)]))
+    return np.array(H, dtype=np.int32).reshape(-1, 4)
+
+
+def csr_neighbours(n, edges):
+    """CSR adjacency (both directions) of an undirected edge list: ptr[n+1], idx[nnz]."""
+    src = np.concatenate([edges[:, 0], edges[:, 1]])
+    dst = np.concatenate([edges[:, 1], edges[:, 0]])
+    order = np.lexsort((dst, src))
+    src, dst = src[order], dst[order]
+    ptr = np.zeros(n + 1, np.int64)
+    np.add.at(ptr, src + 1, 1)
+    return np.cumsum(ptr).astype(np.int32), dst.astype(np.int32)
+
+
+def csr_hinges(n, hinges):
+    """CSR incidence node -> (hinge << 2 | role), role 0..3 = position in the hinge tuple."""
+    nh = len(hinges)
+    node = hinges.reshape(-1).astype(np.int64)
+    code = (np.repeat(np.arange(nh, dtype=np.int64), 4) << 2) | np.tile(np.arange(4), nh)
+    order = np.lexsort((code, node))
+    node, code = node[order], code[order]
+    ptr = np.zeros(n + 1, np.int64)
+    np.add.at(ptr, node + 1, 1)
+    return np.cumsum(ptr).astype(np.int32), code.astype(np.int32)
+
+
+# ----------------------------------------------------------------------------- bodies
+
+
+@dataclass
+class Bodies:
+    """Lagrangian nodes of all immersed bodies of one channel (global node numbering)."""
+    X: np.ndarray                 # [3, n] float64 initial positions
+    X_rest: np.ndarray            # [3, n] float64 rest shape (springs / hinges measured on it)
+    edges: np.ndarray             # [ne, 2] int32 spring edges
+    hinges: np.ndarray            # [nh, 4] int32 bending hinges
+    anchors: np.ndarray | None    # [3, n] tether anchors or None
+    k_spring: float = 0.0
+    k_bend: float = 0.0
+    k_tether: float = 0.0
+    body_offsets: list = field(default_factory=list)   # node offset of each body, plus n
+
+    @property
+    def n(self):
+        return self.X.shape[1]
+
+
+@functools.lru_cache(maxsize=None)
+def _topology(nodes):
+    V0, T = unit_sphere(nodes)
+    return V0, T, mesh_edges(T), mesh_hinges(T)
+
+
+def _concat(parts):
+    Xs, edges, hinges, offs, off = [], [], [], [0], 0
+    for V, nodes in parts:
+        _, _, E, H = _topology(nodes)
+        Xs.append(V)
+        edges.append(E + off)
+        hinges.append(H + off)
+        off += len(V)
+        offs.append(off)
+    X = np.ascontiguousarray(np.concatenate(Xs).T)
+    return X, np.concatenate(edges).astype(np.int32), np.concatenate(hinges).astype(np.int32), offs
+
+
+def place_bodies(rng, nx, nz, count, radius, y_lo, y_hi, max_tries=4000):
+    """Centres uniform in x,z and in [y_lo, y_hi]; bounding spheres of `radius` kept apart
+    (periodic minimum image in x and z).  Returns fewer centres if the box is full."""
+    C = []
+    tries = 0
+    while len(C) < count and tries < max_tries * count:
+        tries += 1
+        c = np.array([rng.uniform(0, nx), rng.uniform(y_lo, y_hi), rng.uniform(0, nz)])
+        ok = True
+        for d in C:
+            dx = abs(c[0] - d[0]); dx = min(dx, nx - dx)
+            dz = abs(c[2] - d[2]); dz = min(dz, nz - dz)
+            if dx * dx + (c[1] - d[1]) ** 2 + dz * dz < (2 * radius) ** 2:
+                ok = False
+                break
+        if ok:
+            C.append(c)
+    return np.array(C).reshape(-1, 3)
+
+
+def platelets(rng, nx, ny, nz, count, semi_axes, nodes, y_band, k_spring, k_bend, margin=2.0):
+    """Oblate platelets: unit sphere mesh scaled by semi_axes (x, y, z) (short axis along the
+    wall normal y), centres from place_bodies.  Rest shape = initial shape."""
+    a = np.asarray(semi_axes, float)
+    V0 = _topology(nodes)[0]
+    y_lo = -0.5 + y_band[0]
+    y_hi = min(-0.5 + y_band[1], ny - 0.5 - a[1] - 2.0)
+    cen = place_bodies(rng, nx, nz, count, float(a.max()) + margin, y_lo, y_hi)
+    parts = [(V0 * a[None, :] + c[None, :], nodes) for c in cen]
+    X, edges, hinges, offs = _concat(parts)
+    return Bodies(X=X, X_rest=X.copy(), edges=edges, hinges=hinges, anchors=None,
+                  k_spring=k_spring, k_bend=k_bend, body_offsets=offs)
+
+
+def tethered_sphere(rng, centre, radius, nodes, k_tether, sigma):
+    """Sphere whose nodes are tied to their rest positions; initial positions perturbed by
+    N(0, sigma^2) per component."""
+    V0, T = unit_sphere(nodes)
+    X_rest = np.ascontiguousarray((V0 * radius + np.asarray(centre, float)[None, :]).T)
+    X = X_rest + rng.normal(0.0, sigma, size=X_rest.shape)
+    return Bodies(X=np.ascontiguousarray(X), X_rest=X_rest, edges=np.zeros((0, 2), np.int32),
+                  hinges=np.zeros((0, 4), np.int32), anchors=X_rest.copy(), k_tether=k_tether,
+                  body_offsets=[0, X.shape[1]])
+
+
+# ----------------------------------------------------------------------------- workloads
+
+
+@dataclass
+class Channel:
+    nx: int
+    ny: int
+    nz: int
+    tau: float
+    body: tuple = (0.0, 0.0, 0.0)
+    u_wall_lo: tuple = (0.0, 0.0, 0.0)
+    u_wall_hi: tuple = (0.0, 0.0, 0.0)
+    walls: bool = True
+    init: str = "rest"            # "rest" (u = 0) or "shear" (linear wall-driven profile)
+    bodies: Bodies | None = None
+
+    @property
+    def cells(self):
+        return self.nx * self.ny * self.nz
+
+
+def poiseuille_sphere(seed=0, n=32):
+    """Plain method: 32^3 box, tau = 0.8, walls normal to y, body force 1e-6 along x;
+    one tethered sphere of 642 nodes, radius 4, centred at (16, 10, 16), k = 0.01,
+    rest positions perturbed by N(0, 0.1^2)."""
+    rng = np.random.default_rng(seed)
+    b = tethered_sphere(rng, (n / 2, 10.0, n / 2), 4.0, 642, 0.01, 0.1)
+    return Channel(n, n, n, 0.8, body=(1e-6, 0.0, 0.0), bodies=b)
+
+
+def shear_platelets(seed=0, nx=256, ny=128, nz=128, count=16, nodes=2562, semi_axes=(6.0, 2.0, 6.0),
+                    tau=1.0, u_top=0.05, k_spring=0.005, k_bend=1e-4, y_band=(8.0, 20.0)):
+    """Production shear: moving top wall (u_top along x), resting bottom wall, linear Couette
+    start; `count` oblate platelets with spring network + bending, centroids 8-20 lattice
+    units above the bottom wall."""
+    rng = np.random.default_rng(seed)
+    b = platelets(rng, nx, ny, nz, count, semi_axes, nodes, y_band, k_spring, k_bend)
+    return Channel(nx, ny, nz, tau, u_wall_hi=(u_top, 0.0, 0.0), init="shear", bodies=b)
+
+
+BATCH_SIZES = [(48, 32, 32), (64, 48, 48), (96, 64, 64), (128, 64, 64)]
+
+
+def batched_channels(seed=0, nch=64, sizes=BATCH_SIZES):
+    """Independent channels of uneven size: dims uniform over `sizes`, 1-8 platelets of 642 or
+    2562 nodes, top-wall speed U(0.01, 0.05), tau U(0.7, 1.2)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nch):
+        nx, ny, nz = sizes[rng.integers(len(sizes))]
+        count = int(rng.integers(1, 9))
+        nodes = int(rng.choice([642, 2562]))
+        u = float(rng.uniform(0.01, 0.05))
+        tau = float(rng.uniform(0.7, 1.2))
+        band = (8.0, min(20.0, ny - 10.0))
+        b = platelets(rng, nx, ny, nz, count, (6.0, 2.0, 6.0), nodes, band, 0.005, 1e-4)
+        out.append(Channel(nx, ny, nz, tau, u_wall_hi=(u, 0.0, 0.0), init="shear", bodies=b))
+    return out

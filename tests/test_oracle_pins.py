@@ -1,0 +1,315 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (no GPU).
+
+Each test checks the oracle against something other than itself: closed forms of the
+D3Q19 moments (Eq. (19)-(21)), identities of the delta kernel (Eq. (35)-(36)), exact
+steady states of the scheme (Couette, Poiseuille with its slip term), conservation laws,
+the spread / interpolation adjoint identity (Eq. (33)-(34) use the same weights), the
+textbook shear-wave decay with the viscosity of Eq. (22), the time step the paper prints
+(section 3.3), and finite differences of the membrane energy (Eq. (2)-(3)).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------------------- tables
+def test_d3q19_numbering_matches_wall_equations(orc):
+    """Eq. (23)-(30) fix the numbering (the velocity figure is absent)."""
+    c, w, opp = orc.tables()
+    p = lambda i: c[i - 1]  # paper index -> velocity
+    assert {i for i in range(1, 20) if p(i)[2] == 0} == {1, 2, 3, 4, 7, 8, 11, 12, 19}   # Eq. (23) in-plane
+    assert {i for i in range(1, 20) if p(i)[2] == -1} == {6, 10, 14, 16, 18}             # Eq. (23) doubled
+    assert {i for i in range(1, 20) if p(i)[2] == 1} == {5, 9, 13, 15, 17}                # unknowns at z = 0
+    for a, b in [(5, 6), (9, 14), (13, 10), (15, 18), (17, 16)]:                          # Eq. (24)-(28)
+        assert np.all(p(a) == -p(b))
+    # Eq. (25)-(26): f9 carries +v_x, f13 -v_x; Eq. (27)-(28): f15 +v_y, f17 -v_y
+    assert p(9)[0] == 1 and p(13)[0] == -1 and p(15)[1] == 1 and p(17)[1] == -1
+    # Eq. (29): c_x = +1 in-plane {1,7,8}, -1 {2,11,12}; Eq. (30): c_y = +1 {3,7,11}, -1 {4,8,12}
+    assert {i for i in (1, 2, 3, 4, 7, 8, 11, 12) if p(i)[0] == 1} == {1, 7, 8}
+    assert {i for i in (1, 2, 3, 4, 7, 8, 11, 12) if p(i)[0] == -1} == {2, 11, 12}
+    assert {i for i in (1, 2, 3, 4, 7, 8, 11, 12) if p(i)[1] == 1} == {3, 7, 11}
+    assert {i for i in (1, 2, 3, 4, 7, 8, 11, 12) if p(i)[1] == -1} == {4, 8, 12}
+    assert np.all(c[opp] == -c)
+    # Eq. (21) weights
+    assert np.allclose(w[:6], 2 / 36) and np.allclose(w[6:18], 1 / 36) and np.isclose(w[18], 12 / 36)
+
+
+def test_lattice_isotropy(orc):
+    c, w, _ = orc.tables()
+    c = c.astype(float)
+    I = np.eye(3)
+    assert abs(w.sum() - 1) < 1e-15
+    assert np.abs(np.einsum("i,ia->a", w, c)).max() < 1e-15
+    assert np.abs(np.einsum("i,ia,ib->ab", w, c, c) - I / 3).max() < 1e-15
+    assert np.abs(np.einsum("i,ia,ib,ic->abc", w, c, c, c)).max() < 1e-15
+    four = np.einsum("i,ia,ib,ic,id->abcd", w, c, c, c, c)
+    iso = (np.einsum("ab,cd->abcd", I, I) + np.einsum("ac,bd->abcd", I, I) + np.einsum("ad,bc->abcd", I, I)) / 9
+    assert np.abs(four - iso).max() < 1e-15
+
+
+def test_equilibrium_moments(orc):
+    c, _, _ = orc.tables()
+    c = c.astype(float)
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        rho = 1 + 0.1 * rng.standard_normal()
+        v = 0.1 * rng.standard_normal(3)
+        f = orc.feq(rho, v)
+        assert abs(f.sum() - rho) < 1e-14
+        assert np.abs(c.T @ f - rho * v).max() < 1e-14
+        assert np.abs(np.einsum("ia,ib,i->ab", c, c, f) - rho * (np.outer(v, v) + np.eye(3) / 3)).max() < 1e-14
+
+
+def test_guo_source_moments(orc):
+    """Eq. (19) with the c_s^2 I sign read as minus: zero mass source, momentum source
+    (1 - 1/2tau) F, second moment (1 - 1/2tau)(vF + Fv)."""
+    c, _, _ = orc.tables()
+    c = c.astype(float)
+    rng = np.random.default_rng(1)
+    for tau in (0.6, 0.8, 1.379):
+        k = 1 - 1 / (2 * tau)
+        v = 0.1 * rng.standard_normal(3)
+        F = 1e-3 * rng.standard_normal(3)
+        S = orc.source(tau, v, F)
+        assert abs(S.sum()) < 1e-18
+        assert np.abs(c.T @ S - k * F).max() < 1e-18
+        assert np.abs(np.einsum("ia,ib,i->ab", c, c, S) - k * (np.outer(v, F) + np.outer(F, v))).max() < 1e-18
+
+
+# ----------------------------------------------------------------------------- delta kernel
+@pytest.mark.parametrize("kernel", ["cos", "peskin4"])
+def test_phi_identities(orc, kernel):
+    rng = np.random.default_rng(2)
+    for r in rng.uniform(-3, 3, 50):
+        j = np.arange(-5, 6)
+        ph = orc.phi(r - j, kernel)
+        assert abs(ph.sum() - 1) < 1e-14                         # partition of unity
+        assert abs(ph[j % 2 == 0].sum() - 0.5) < 1e-14           # even / odd split
+        assert abs((ph ** 2).sum() - 3 / 8) < 1e-14              # sum of squares
+        m1 = ((r - j) * ph).sum()
+        if kernel == "peskin4":
+            assert abs(m1) < 1e-14                               # zero first moment
+        else:
+            t = r - math.floor(r)
+            closed = t - 0.5 + (math.cos(math.pi * t / 2) - math.sin(math.pi * t / 2)) / 2
+            assert abs(m1 - closed) < 1e-14
+
+
+@pytest.mark.parametrize("kernel", ["cos", "peskin4"])
+def test_phi_values(orc, kernel):
+    s2 = math.sqrt(2)
+    vals = {0: 0.5, 0.5: (2 + s2) / 8, 1: 0.25, 1.5: (2 - s2) / 8, 2: 0.0, 2.5: 0.0}
+    for r, v in vals.items():
+        assert abs(orc.phi(r, kernel) - v) < 1e-15
+        assert abs(orc.phi(-r, kernel) - v) < 1e-15
+    # the two kernels coincide at half-integers and differ in between
+    assert abs(orc.phi(0.25, "cos") - orc.phi(0.25, "peskin4")) > 1e-3
+
+
+# ----------------------------------------------------------------------------- exact flows
+def test_couette_steady_state_exact(orc):
+    """Halfway bounce-back with a moving top wall: u_x(y) = U (y + 1/2) / ny exactly."""
+    for tau in (0.8, 1.3):
+        ny, U = 16, 0.05
+        L = orc.Lattice(2, ny, 2, tau, walls=True, u_wall_hi=(U, 0, 0))
+        L.init()
+        L.step(int(40 * ny * ny / ((tau - 0.5) / 3)))
+        rho, v = L.moments()
+        y = np.arange(ny)
+        ex = U * (y + 0.5) / ny
+        assert np.abs(v[0, 0, :, 0] - ex).max() < 1e-12
+        assert np.abs(v[1]).max() < 1e-13 and np.abs(v[2]).max() < 1e-13
+        assert np.abs(rho - 1).max() < 1e-12
+        # wall stress of the Guo-forced BGK scheme: sigma_xy = rho nu U / ny
+        lo, hi = L.wall_stress()
+        nu = (tau - 0.5) / 3
+        assert np.abs(lo[0] - nu * U / ny).max() < 1e-12 and np.abs(hi[0] - nu * U / ny).max() < 1e-12
+        assert np.abs(lo[1]).max() < 1e-14
+
+
+def test_poiseuille_steady_state_exact(orc):
+    """Body-force channel: u_x = g/(2 nu) (y+1/2)(ny-1/2-y) + u_s with the BGK bounce-back slip
+    u_s = g (16 t^2 - 3)/(8 t), t = tau - 1/2 (vanishes at tau = 1/2 + sqrt(3)/4); nu from Eq. (22)."""
+    for tau in (0.6, 0.8, 0.5 + math.sqrt(3) / 4, 1.2):
+        ny, g = 16, 1e-5
+        L = orc.Lattice(1, ny, 1, tau, walls=True, body=(g, 0, 0))
+        L.init()
+        t = tau - 0.5
+        nu = t / 3
+        L.step(int(60 * ny * ny / nu))
+        _, v = L.moments()
+        y = np.arange(ny)
+        ex = g / (2 * nu) * (y + 0.5) * (ny - 0.5 - y) + g * (16 * t * t - 3) / (8 * t)
+        assert np.abs(v[0, 0, :, 0] - ex).max() < 1e-12 * ex.max() * 1e3
+
+
+def test_shear_wave_decay(orc):
+    """Periodic box, u_x = A sin(2 pi y / L): decays as exp(-nu k^2 t), nu = (tau - 1/2)/3."""
+    Ly, tau, A = 64, 0.8, 1e-4
+    L = orc.Lattice(1, Ly, 1, tau, walls=False)
+    y = np.arange(Ly)
+    u = np.zeros((3, 1, Ly, 1))
+    u[0, 0, :, 0] = A * np.sin(2 * np.pi * y / Ly)
+    L.init(u=u)
+    L.step(50)
+    _, v0 = L.moments()
+    a0 = (v0[0, 0, :, 0] * np.sin(2 * np.pi * y / Ly)).sum() * 2 / Ly
+    n = 2000
+    L.step(n)
+    _, v1 = L.moments()
+    a1 = (v1[0, 0, :, 0] * np.sin(2 * np.pi * y / Ly)).sum() * 2 / Ly
+    nu = (tau - 0.5) / 3
+    k = 2 * np.pi / Ly
+    rate = -math.log(a1 / a0) / n
+    assert abs(rate / (nu * k * k) - 1) < 2e-3
+
+
+# ----------------------------------------------------------------------------- conservation
+def test_mass_conserved_with_walls_and_forces(orc):
+    rng = np.random.default_rng(3)
+    L = orc.Lattice(12, 10, 8, 0.9, walls=True, body=(1e-5, 0, 2e-6), u_wall_lo=(0.01, 0, -0.02),
+                    u_wall_hi=(0.03, 0, 0.01))
+    L.init()
+    X = np.stack([rng.uniform(0, 12, 40), rng.uniform(2, 7, 40), rng.uniform(0, 8, 40)])
+    F = 1e-3 * rng.standard_normal((3, 40))
+    L.spread(X, F)
+    m0 = L.f.sum()
+    L.step(30)
+    assert abs(L.f.sum() - m0) < 1e-12 * m0
+
+
+def test_momentum_balance_periodic(orc):
+    """Fully periodic: total momentum grows by N F_body + sum_m F_m per step."""
+    rng = np.random.default_rng(4)
+    nx, ny, nz = 10, 9, 8
+    body = np.array([1e-5, -2e-6, 3e-6])
+    L = orc.Lattice(nx, ny, nz, 0.7, walls=False, body=tuple(body))
+    u = 1e-3 * rng.standard_normal((3, nz, ny, nx))
+    L.init(u=u)
+    X = np.stack([rng.uniform(0, nx, 30), rng.uniform(0, ny, 30), rng.uniform(0, nz, 30)])
+    F = 1e-3 * rng.standard_normal((3, 30))
+    L.spread(X, F)
+    c, _, _ = orc.tables()
+    j = lambda: np.einsum("ia,izyx->a", c.astype(float), L.f)
+    j0 = j()
+    L.step(5)
+    expect = 5 * (nx * ny * nz * body + F.sum(axis=1))
+    assert np.abs(j() - j0 - expect).max() < 1e-13
+
+
+# ----------------------------------------------------------------------------- spread / interp
+@pytest.mark.parametrize("kernel", ["cos", "peskin4"])
+def test_spread_interp_adjoint(orc, kernel):
+    rng = np.random.default_rng(5)
+    nx, ny, nz = 11, 9, 10
+    L = orc.Lattice(nx, ny, nz, 0.8, walls=False, kernel=kernel)
+    n = 25
+    X = np.stack([rng.uniform(-5, 20, n), rng.uniform(0, ny, n), rng.uniform(0, nz, n)])
+    F = rng.standard_normal((3, n))
+    L.spread(X, F)
+    v = rng.standard_normal((3, nz, ny, nx))
+    U = L.interp_field(X, v)
+    assert abs((L.g * v).sum() - (F * U).sum()) < 1e-12
+    assert np.abs(L.g.sum(axis=(1, 2, 3)) - F.sum(axis=1)).max() < 1e-12      # partition of unity
+    const = np.broadcast_to(np.array([0.3, -0.2, 0.7])[:, None, None, None], (3, nz, ny, nx)).copy()
+    assert np.abs(L.interp_field(X, const) - np.array([0.3, -0.2, 0.7])[:, None]).max() < 1e-14
+
+
+@pytest.mark.parametrize("kernel", ["cos", "peskin4"])
+def test_interp_linear_field(orc, kernel):
+    """u(x) = x interpolates to X (Peskin) or X + (1/2 - t + (sin - cos)(pi t/2)/2) (cosine)."""
+    nx = ny = nz = 16
+    L = orc.Lattice(nx, ny, nz, 0.8, walls=False, kernel=kernel)
+    xs = np.arange(nx, dtype=float)
+    v = np.zeros((3, nz, ny, nx))
+    v[0] = xs[None, None, :]
+    rng = np.random.default_rng(6)
+    X = np.stack([rng.uniform(4, 11, 30), rng.uniform(4, 11, 30), rng.uniform(4, 11, 30)])
+    U = L.interp_field(X, v)[0]
+    t = X[0] - np.floor(X[0])
+    corr = 0.5 - t + (np.sin(np.pi * t / 2) - np.cos(np.pi * t / 2)) / 2 if kernel == "cos" else 0 * t
+    assert np.abs(U - (X[0] + corr)).max() < 1e-13
+
+
+def test_spread_drops_wall_rows(orc):
+    """Stencil rows beyond the wall are dropped: sum_x g = F * sum of phi over rows y >= 0."""
+    L = orc.Lattice(8, 8, 8, 0.8, walls=True)
+    X = np.array([[3.3], [0.2], [4.7]])
+    F = np.array([[1.0], [2.0], [-1.0]])
+    L.spread(X, F)
+    rows = np.arange(-1, 3)
+    frac = sum(orc.phi(r - 0.2) for r in rows if r >= 0)
+    assert np.abs(L.g.sum(axis=(1, 2, 3)) - F[:, 0] * frac).max() < 1e-14
+    U = L.interp_field(X, np.zeros((3, 8, 8, 8)))
+    assert np.abs(U).max() == 0.0  # walls at rest contribute zero velocity
+
+
+def test_coupled_step_moves_node_with_force(orc):
+    """Fig. 1 order: a pushed node drags the fluid, and the interpolated velocity moves it
+    along the force."""
+    L = orc.Lattice(16, 16, 16, 0.8, walls=False)
+    L.init()
+    X = np.array([[8.3], [7.6], [8.1]])
+    mem = orc.Membrane(X.copy(), np.zeros((0, 2), np.int32), anchors=X + np.array([[0.5], [0], [0]]),
+                       k_tether=1e-3)
+    X1 = X.copy()
+    F, U = orc.coupled_step(L, mem, X1)
+    assert F[0, 0] > 0 and U[0, 0] > 0 and X1[0, 0] > X[0, 0]
+    assert abs(U[1, 0]) < 1e-3 * U[0, 0] and abs(U[2, 0]) < 1e-3 * U[0, 0]
+
+
+# ----------------------------------------------------------------------------- membrane forces
+def _mesh():
+    from paper_1312_2234_amd import inputs
+
+    V, T = inputs.icosphere(2)
+    X = np.ascontiguousarray((V * np.array([3.0, 1.0, 3.0])).T)
+    return X, inputs.mesh_edges(T), inputs.mesh_hinges(T)
+
+
+def test_membrane_forces_are_minus_energy_gradient(orc):
+    X0, E, H = _mesh()
+    rng = np.random.default_rng(7)
+    mem = orc.Membrane(X0, E, k_spring=0.005, hinges=H, k_bend=1e-4, anchors=X0 + 0.01, k_tether=0.01)
+    X = X0 + 0.05 * rng.standard_normal(X0.shape)
+    F = mem.forces(X)
+    h = 1e-6
+    for _ in range(12):
+        i, d = rng.integers(X.shape[1]), rng.integers(3)
+        Xp, Xm = X.copy(), X.copy()
+        Xp[d, i] += h
+        Xm[d, i] -= h
+        fd = -(mem.energy(Xp) - mem.energy(Xm)) / (2 * h)
+        assert abs(fd - F[d, i]) < 1e-7 * max(1e-6, np.abs(F).max())
+
+
+def test_membrane_forces_translation_rotation_invariant(orc):
+    X0, E, H = _mesh()
+    rng = np.random.default_rng(8)
+    mem = orc.Membrane(X0, E, k_spring=0.005, hinges=H, k_bend=1e-4)
+    X = X0 + 0.05 * rng.standard_normal(X0.shape)
+    F = mem.forces(X)
+    assert np.abs(F.sum(axis=1)).max() < 1e-15 * X.shape[1] * 10 + 1e-17
+    torque = np.cross(X.T, F.T).sum(axis=0)
+    assert np.abs(torque).max() < 1e-15 * X.shape[1] * 10
+    assert np.abs(mem.forces(X0)).max() < 1e-15          # rest shape carries no force
+
+
+def test_stretched_spring_pulls_ends_together(orc):
+    X0 = np.array([[0.0, 1.0], [0.0, 0.0], [0.0, 0.0]])
+    mem = orc.Membrane(X0, np.array([[0, 1]], np.int32), k_spring=2.0)
+    X = np.array([[0.0, 1.5], [0.0, 0.0], [0.0, 0.0]])
+    F = mem.forces(X)
+    assert np.allclose(F[:, 0], [1.0, 0, 0]) and np.allclose(F[:, 1], [-1.0, 0, 0])
+
+
+# ----------------------------------------------------------------------------- printed example
+def test_paper_timestep(orc):
+    g = json.load(open(os.path.join(GOLDEN, "lattice_timestep.json")))
+    dt = orc.lattice_timestep(g["tau"], g["h_m"], g["mu_Pa_s"], g["rho_kg_m3"])
+    assert abs(dt - g["dt_s_printed"]) < 0.5e-8 * 10 ** (1 - g["printed_digits"]) * 0.1
