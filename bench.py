@@ -1,0 +1,164 @@
+"""Throughput of the coupled D3Q19 LBM + immersed-boundary step on one MI355X.
+
+One step = the whole hot path of Fig. 1 on the GPU: membrane forces -> IB spreading ->
+lattice-Boltzmann step -> IB interpolation -> node update, for the production shear
+workload (256x128x128 lattice, moving top wall u = 0.05, tau = 1.0, 16 oblate platelets of
+2562 nodes with spring network and bending, cosine delta kernel, weight-shifted float32
+populations).  The step sequence is replayed from a captured HIP graph; inputs are resident
+in HBM before the timed region starts.
+
+Prints ONE JSON line.  Besides the contract fields it carries:
+  roofline      the lattice kernel (which moves >99% of the bytes): algorithmic bytes per
+                launch (152 B per cell in float32, 76 B in 16-bit) over its average launch
+                time, measured here with HIP events around back-to-back launches on the
+                library's stream, against the 8 TB/s HBM peak;
+  cpu_baseline  the FP64 oracle on the host cores, on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LBM+IB MLUPS, % HBM peak; FP16-store/learned vs plain FP32 at fixed error"
+HBM_PEAK = 8.0e12
+BYTES_PER_CELL = {"f32": 152, "f16": 76, "bf16": 76}
+DTYPE = {"f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32"}
+
+
+def make_workload(name):
+    from paper_1312_2234_amd import inputs
+
+    if name == "shear":
+        ch = inputs.shear_platelets(seed=0)
+        desc = ("shear channel 256x128x128, top wall u=0.05, tau=1.0, 16 oblate platelets "
+                "(6,2,6) x 2562 IB nodes, spring k=0.005 + bending 1e-4")
+        return [ch], desc
+    if name == "sphere":
+        ch = inputs.poiseuille_sphere(seed=0)
+        return [ch], "32^3 body-force channel, tau=0.8, tethered 642-node sphere"
+    raise SystemExit("unknown workload " + name)
+
+
+def cpu_baseline(channels, kernel, steps):
+    """The FP64 oracle (as it stands) on `steps` coupled steps of the first channel."""
+    import numpy as np
+
+    from oracle import oracle
+
+    ch = channels[0]
+    b = ch.bodies
+    o = oracle.Lattice(ch.nx, ch.ny, ch.nz, ch.tau, walls=ch.walls, body=ch.body, u_wall_lo=ch.u_wall_lo,
+                       u_wall_hi=ch.u_wall_hi, kernel=kernel)
+    o.init(u=o.shear_profile()) if ch.init == "shear" else o.init()
+    mem = oracle.Membrane(b.X_rest, b.edges, k_spring=b.k_spring, hinges=b.hinges, k_bend=b.k_bend,
+                          anchors=b.anchors, k_tether=b.k_tether)
+    X = b.X.copy()
+    oracle.coupled_step(o, mem, X)  # first touch of the arrays, not timed
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        oracle.coupled_step(o, mem, X)
+    dt = time.perf_counter() - t0
+    return {"value": round(ch.cells * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": "%d coupled steps (forces, spread, LBM, interpolation, move) of the full %dx%dx%d "
+                      "workload, FP64, %.1f s" % (steps, ch.nx, ch.ny, ch.nz, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--workload", default="shear")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--kernel", default="cos", choices=["cos", "peskin4"])
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lbm-only-steps", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1312_2234_amd import lbm
+
+    dev = "cuda:0"
+    channels, desc = make_workload(args.workload)
+    nodes = sum(c.bodies.n for c in channels)
+    cells = sum(c.cells for c in channels)
+    lat = lbm.Lattice(channels, storage=args.storage, kernel=args.kernel, max_nodes=nodes, device=dev)
+    lat.init()
+    b = channels[0].bodies
+    lat.set_nodes(b.n)
+    mem = lbm.Membrane(b, device=dev)
+    X = torch.from_numpy(b.X.copy()).to(dev)
+    F = torch.zeros((3, b.n), dtype=torch.float32, device=dev)
+    U = torch.zeros_like(F)
+    lat.graph_capture(mem, 2, X, F, U)
+    stream = lat.stream  # the library's stream: events are recorded on it
+
+    def run(k):
+        if k // 2:
+            lat.graph_launch(k // 2)
+        if k % 2:
+            lat.coupled_steps(mem, 1, X, F, U)
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    run(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    flags = lat.error_flags()
+
+    # lattice kernel alone: back-to-back launches on the same stream
+    lat.step(10)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    lat.step(args.lbm_only_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_lbm = e0.elapsed_time(e1) / args.lbm_only_steps
+    bytes_launch = BYTES_PER_CELL[args.storage] * cells
+    achieved = bytes_launch / (ms_lbm * 1e-3)
+
+    out = {
+        "metric": METRIC,
+        "value": round(cells / (ms * 1e-3) / 1e6, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.storage],
+        "data": "synthetic",
+        "config": {"workload": desc, "cells": cells, "ib_nodes": nodes, "storage": args.storage,
+                   "delta_kernel": args.kernel, "launch": lat.get_launch(), "graph": "2-step HIP graph replay"},
+        "ib_nodes_per_s": round(nodes / (ms * 1e-3), 1),
+        "lbm_only_mlups": round(cells / (ms_lbm * 1e-3) / 1e6, 2),
+        "error_flags": flags,
+        "roofline": {"bound": "hbm", "kernel": "k_step (lattice step)", "achieved": round(achieved / 1e9, 1),
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
+                     "traffic": None, "bytes_per_launch": bytes_launch,
+                     "avg_launch_us": round(ms_lbm * 1e3, 2)},
+    }
+    if not args.no_cpu_baseline and args.cpu_steps > 0:
+        del lat
+        out["cpu_baseline"] = cpu_baseline(channels, args.kernel, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

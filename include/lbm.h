@@ -1,0 +1,218 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) lattice-Boltzmann + immersed-boundary library.
+ *
+ * The library implements the data-parallel core of the platelet / blood-flow model of
+ * Wu, Xu, Kim & Alber (arXiv:1312.2234): a D3Q19 BGK lattice-Boltzmann step with the
+ * Guo body-force term (section 3.3, Eq. (16)-(21)), coupled to Lagrangian membrane
+ * nodes by the immersed-boundary method (section 3.4.2, Eq. (33)-(36)), in the
+ * per-step order of Fig. 1: membrane forces -> spread -> LBM -> interpolate -> move.
+ *
+ * Conventions shared by every call
+ *   Units        lattice units: h = dt = rho_0 = 1.
+ *   Geometry     x and z periodic; y bounded by two walls (halfway bounce-back) at the
+ *                planes y = -1/2 and y = ny - 1/2 when `walls` = 1, periodic when 0.
+ *   Numbering    D3Q19 directions in the paper's order i = 1..19 (stored 0..18), the
+ *                order fixed by the on-site wall equations Eq. (23)-(30).
+ *   Layout       SoA, x fastest: cell n = x + nx*(y + ny*z).  Per-cell fields of all
+ *                channels are concatenated in channel order (channel c starts at the sum
+ *                of the cell counts of channels < c); vector fields are [3][cells] per
+ *                channel.  Lagrangian arrays are SoA [3][n] (X in float64, F/U float32);
+ *                nodes of all channels concatenated in channel order.
+ *   Memory       every pointer argument except where marked "host" is DEVICE memory owned
+ *                by the caller.  The library never allocates device memory: the caller
+ *                provides one workspace of lbm_workspace_bytes() bytes to lbm_create() and
+ *                keeps it alive until lbm_destroy().  The library owns only the small host
+ *                handle.
+ *   Streams      every call only enqueues work on the context's stream (a hipStream_t
+ *                passed as void*); outputs are valid after that stream synchronises.
+ *                Calls that return data to the host (lbm_error_flags) synchronise it.
+ *   Errors       host-side validation returns LBM_ERR_ARG (null pointer, bad size, tau <=
+ *                1/2, wall-normal wall velocity, workspace too small, node count above the
+ *                capacity given at create time); a failed HIP launch returns LBM_ERR_HIP;
+ *                calls in the wrong order return LBM_ERR_STATE.  Nothing is thrown across
+ *                the ABI.  Conditions only the device can see (an IB node outside the
+ *                wall band, a non-finite force) set bits read by lbm_error_flags(); the
+ *                kernels clamp indices so that they never access memory out of bounds.
+ *   Threads      a context is used by one host thread at a time.
+ */
+#ifndef MI355_LBMIB_H
+#define MI355_LBMIB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx; /* opaque host handle */
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_ERR_ARG = 1,
+    LBM_ERR_STATE = 2,
+    LBM_ERR_HIP = 3,
+    LBM_ERR_UNSUPPORTED = 4
+} lbm_status;
+
+/* Storage of the populations.  All forms store the weight-shifted value g_i = f_i - w_i
+ * and compute in float32; F16 / BF16 halve the bytes per update (round to nearest even
+ * on store). */
+typedef enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2 } lbm_storage;
+
+/* Discrete delta kernel phi of Eq. (35): the cosine kernel of Eq. (36) (zero for
+ * |r| >= 2), or Peskin's 4-point kernel. */
+typedef enum { IB_PHI_COS4 = 0, IB_PHI_PESKIN4 = 1 } ib_kernel;
+
+/* Error bits reported by lbm_error_flags(). */
+#define LBM_FLAG_NODE_OUTSIDE 0x1u  /* an IB node's stencil base fell outside y in [-2, ny] */
+#define LBM_FLAG_LIST_OVERFLOW 0x2u /* IB tile lists exceeded their capacity (contributions lost) */
+#define LBM_FLAG_FORCE_NONFINITE 0x4u /* a Lagrangian force was Inf/NaN (force field set to NaN) */
+#define LBM_FLAG_CLOSURE_FALLBACK 0x8u /* the learned closure fell back to plain BGK at some node */
+
+/* One channel (an independent lattice).  Section 3.3: lattice size, relaxation time tau
+ * (Eq. (16), viscosity (tau - 1/2)/3 by Eq. (22)), constant body force added to the IB
+ * force in Eq. (19), wall velocities of the two y-walls. */
+typedef struct {
+    int32_t nx, ny, nz; /* >= 1 each; the IB calls need nx, nz >= 4 */
+    int32_t walls;      /* 1 = bounce-back walls normal to y, 0 = periodic in y */
+    float tau;          /* > 0.5 */
+    float body_force[3];
+    float u_wall_lo[3]; /* velocity of the wall at y = -1/2; y component must be 0 */
+    float u_wall_hi[3]; /* velocity of the wall at y = ny - 1/2; y component must be 0 */
+} lbm_params;
+
+/* Bytes of device workspace for `nch` channels with the given storage and room for up to
+ * `max_nodes` immersed-boundary nodes in total (0: no IB).  0 on invalid arguments. */
+size_t lbm_workspace_bytes(const lbm_params* ch /*host [nch]*/, int32_t nch, lbm_storage storage,
+                           int64_t max_nodes);
+
+/* Create a context over a caller-owned device workspace (256-byte aligned, at least
+ * lbm_workspace_bytes() bytes).  Enqueues the clearing of the workspace on `stream`.
+ * The populations are undefined until lbm_init() or lbm_set_populations(). */
+lbm_status lbm_create(const lbm_params* ch /*host [nch]*/, int32_t nch, lbm_storage storage,
+                      ib_kernel kernel, int64_t max_nodes, void* workspace, size_t bytes, void* stream,
+                      lbm_ctx** out /*host*/);
+
+/* Synchronise the stream, release the handle (and any captured graph).  NULL is a no-op. */
+lbm_status lbm_destroy(lbm_ctx* ctx);
+
+/* f(x, 0) = f^eq(rho, u) of Eq. (20) at every cell.  rho: [cells] or NULL (rho = 1);
+ * u: [3][cells] per channel or NULL, meaning the steady wall-driven profile
+ * u(y) = u_lo + (u_hi - u_lo) (y + 1/2) / ny with walls (zero without walls). */
+lbm_status lbm_init(lbm_ctx* ctx, const float* rho, const float* u);
+
+/* `nsteps` lattice-Boltzmann steps (section 3.3): collide with BGK (Eq. (16)) and the Guo
+ * force term (Eq. (19), with the sign of the c_s^2 I term read as minus) using the force
+ * F = body_force + g, g the field of the last ib_spread (zero if none), then stream with
+ * halfway bounce-back (moving-wall term 6 w_i c_i.u_w) at the y-walls. */
+lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps);
+
+/* Declare the Lagrangian nodes: n in total (<= max_nodes), node_offsets = host array of
+ * nch+1 ascending offsets assigning nodes to channels (NULL allowed when nch == 1).
+ * Must precede ib_spread / ib_interp. */
+lbm_status ib_set_nodes(lbm_ctx* ctx, int64_t n, const int64_t* node_offsets /*host*/);
+
+/* Eq. (34)-(35), h = 1: g(x) = sum_m F_m phi(x - X_m) phi(y - Y_m) phi(z - Z_m) over the
+ * 4x4x4 stencil floor(X)-1 .. floor(X)+2 (x, z periodic; rows outside the walls dropped).
+ * Replaces the previous force field; the field stays in effect for later lbm_step calls.
+ * X: [3][n] float64, F: [3][n] float32.  Deterministic (fixed-point accumulation). */
+lbm_status ib_spread(lbm_ctx* ctx, int64_t n, const double* X, const float* F);
+
+/* Eq. (33), h = 1: U_m = sum_x v(x) phi phi phi over the same stencil, with the current
+ * fluid velocity v = (sum_i c_i f_i + (body_force + g)/2) / rho (g: last spread field);
+ * stencil rows inside a wall take that wall's velocity.  X: [3][n] float64 (normally the
+ * positions given to the preceding ib_spread), U: [3][n] float32 output. */
+lbm_status ib_interp(lbm_ctx* ctx, int64_t n, const double* X, float* U);
+
+/* Position update after the interpolation (Fig. 1): X <- X + U (float64, dt = 1). */
+lbm_status ib_advance(lbm_ctx* ctx, int64_t n, double* X, const float* U);
+
+/* Eq. (17)-(18) and the velocity shift under Eq. (19) at every cell of the current state:
+ * drho = rho - 1 = sum_i (f_i - w_i)  [cells] and v = (sum_i c_i f_i + (body_force + g)/2)
+ * / rho  [3][cells] per channel.  Either pointer may be NULL. */
+lbm_status lbm_moments(lbm_ctx* ctx, float* drho, float* v);
+
+/* Current pre-collision populations f_i (not shifted), paper order, [19][cells] per
+ * channel, float32.  lbm_set_populations takes the same layout and replaces the state. */
+lbm_status lbm_get_populations(lbm_ctx* ctx, float* f);
+lbm_status lbm_set_populations(lbm_ctx* ctx, const float* f);
+
+/* Raw state (the stored shifted post-collision buffer) for bit-exact checkpoint/resume:
+ * lbm_state_bytes() bytes, device to device. */
+size_t lbm_state_bytes(const lbm_ctx* ctx);
+lbm_status lbm_get_state(lbm_ctx* ctx, void* dst);
+lbm_status lbm_set_state(lbm_ctx* ctx, const void* src);
+
+/* Viscous stress of the Guo-forced BGK scheme at the wall-adjacent rows y = 0 (lo) and
+ * y = ny-1 (hi): sigma_ab = -(1 - 1/2tau) sum_i c_ia c_ib (f_i - f_i^eq)
+ * - (1 - 1/2tau)(F_a v_b + F_b v_a)/2 for (a,b) = (x,y) and (z,y); output [2][nz][nx]
+ * per channel, concatenated.  (The paper gives no stress formula.) */
+lbm_status lbm_wall_stress(lbm_ctx* ctx, float* lo, float* hi);
+
+/* Synchronise the stream and return the OR of the device error bits since the last call
+ * (LBM_FLAG_*), then clear them. */
+lbm_status lbm_error_flags(lbm_ctx* ctx, uint32_t* flags /*host*/);
+
+const char* lbm_status_string(lbm_status s);
+
+/* ---------------------------------------------------------------- membrane forces
+ * Forces on the Lagrangian nodes (Fig. 1, first box), the input of ib_spread:
+ *   springs  Eq. (2)-(3): U = k/2 (|R| - L)^2 per edge, the force on a node is minus the
+ *            gradient (a stretched edge pulls its ends together);
+ *   bending  stand-in for Eq. (6)-(10): E = k_bend sum_hinges (1 - cos(theta - theta0)),
+ *            theta the signed dihedral angle of the two triangles of a hinge;
+ *   tethers  U = k_tether/2 |X - A|^2.
+ * Connectivity is CSR so that every node gathers its own force (no atomics).  All arrays
+ * are device memory; rest_len / rest_theta are filled by ib_membrane_rest(). */
+typedef struct {
+    int64_t n;                 /* nodes */
+    const int32_t* nbr_ptr;    /* [n+1] CSR over spring neighbours (both directions) */
+    const int32_t* nbr_idx;    /* [nnz] neighbour node ids */
+    double* rest_len;          /* [nnz] rest length per CSR entry */
+    double k_spring;
+    const int32_t* hinge_ptr;  /* [n+1] CSR node -> hinge incidences, or NULL */
+    const int32_t* hinge_inc;  /* [nnz_h] (hinge id << 2) | role, role = slot 0..3 in the hinge */
+    const int32_t* hinges;     /* [nh][4] (x0, x1, x2, x3): triangles (x0,x1,x2), (x3,x2,x1) */
+    double* rest_theta;        /* [nh] */
+    int64_t nh;
+    double k_bend;
+    const double* anchors;     /* [3][n] tether anchors, or NULL */
+    double k_tether;
+} ib_membrane;
+
+/* Measure rest lengths and rest dihedral angles on X_rest ([3][n] float64). */
+lbm_status ib_membrane_rest(const ib_membrane* m /*host*/, const double* X_rest, void* stream);
+/* F = -grad(E)(X), float64 arithmetic, float32 output [3][n]. */
+lbm_status ib_membrane_forces(const ib_membrane* m /*host*/, const double* X, float* F, void* stream);
+
+/* ---------------------------------------------------------------- coupled sequence
+ * `nsteps` full steps of Fig. 1 on the context's stream: ib_membrane_forces(X) ->
+ * ib_spread(X, F) -> lbm_step(1) -> ib_interp(X) -> X += U.  m may be NULL (F given,
+ * kept constant).  X is updated in place; F and U hold the last step's values. */
+lbm_status lbm_coupled_steps(lbm_ctx* ctx, const ib_membrane* m /*host*/, int32_t nsteps, double* X,
+                             float* F, float* U);
+
+/* Capture `nsteps` coupled steps (even, >= 2) into a HIP graph held by the context, then
+ * replay it `repeats` times per lbm_graph_launch.  The captured pointers must stay valid.
+ * The context's stream must not be the legacy default (NULL) stream: LBM_ERR_UNSUPPORTED. */
+lbm_status lbm_graph_capture(lbm_ctx* ctx, const ib_membrane* m /*host*/, int32_t nsteps, double* X,
+                             float* F, float* U);
+lbm_status lbm_graph_launch(lbm_ctx* ctx, int32_t repeats);
+
+/* ---------------------------------------------------------------- launch tuning
+ * Launch shape of the lattice kernel, chosen by the autotuner (defaults are valid). */
+typedef struct {
+    int32_t block;       /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+    int32_t xcd_remap;   /* 1 = map consecutive lattice segments to the same XCD */
+    int32_t persistent;  /* 0 = one workgroup per segment; >0 = that many resident workgroups looping */
+    int32_t nontemporal; /* 1 = non-temporal stores of the new populations */
+} lbm_launch;
+
+lbm_status lbm_set_launch(lbm_ctx* ctx, const lbm_launch* cfg /*host*/);
+lbm_status lbm_get_launch(const lbm_ctx* ctx, lbm_launch* cfg /*host*/);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MI355_LBMIB_H */

@@ -49,6 +49,9 @@
  * Build: gcc -O2 -fopenmp -fPIC -shared -o liboracle.so lbm_oracle.c -lm
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -80,6 +83,15 @@ typedef struct {
     double uw_lo[3]; /* velocity of the wall at y = -1/2 */
     double uw_hi[3]; /* velocity of the wall at y = ny - 1/2 */
 } orc_params;
+
+/* threads an OpenMP region of the oracle uses (1 without OpenMP) */
+int32_t orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* accessors so that tests can check the tables against the paper */
 void orc_tables(int32_t* c, double* w, int32_t* opp) {

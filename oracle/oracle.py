@@ -52,6 +52,7 @@ def lib():
         L.orc_phi.argtypes = [C.c_int32, C.c_double]
         L.orc_phi.restype = C.c_double
         L.orc_tables.argtypes = [ip, dp, ip]
+        L.orc_threads.restype = C.c_int32
         L.orc_init.argtypes = [pp, dp, dp, dp]
         L.orc_moments.argtypes = [pp, dp, dp, dp, dp]
         L.orc_step.argtypes = [pp, dp, dp, dp]
@@ -89,6 +90,11 @@ def _f64(a):
 
 
 # ----------------------------------------------------------------- point functions
+def threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().orc_threads())
+
+
 def tables():
     """D3Q19 velocities c[19,3], weights w[19], opposite index opp[19] (paper order)."""
     c = np.zeros((19, 3), np.int32)

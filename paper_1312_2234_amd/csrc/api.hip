@@ -1,0 +1,526 @@
+// api.hip -- host side of the C ABI declared in include/lbm.h.
+//
+// Workspace layout (each region 256-byte aligned), all carved from the caller's buffer:
+//   channel descriptors | segment -> channel map | populations A | populations B |
+//   device error flags | IB: node -> channel, node records, two tile sets (counts,
+//   tile -> slot, flagged list, list channel, fill, list offsets, header), node lists,
+//   force blocks, velocity blocks.
+#include <string.h>
+
+#include <algorithm>
+
+#include "lbm_internal.h"
+
+using namespace lbmib;
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool valid_params(const lbm_params* p, int32_t nch) {
+    if (!p || nch < 1) return false;
+    for (int c = 0; c < nch; ++c) {
+        const lbm_params& q = p[c];
+        if (q.nx < 1 || q.ny < 1 || q.nz < 1) return false;
+        if ((int64_t)q.nx * q.ny * q.nz >= (int64_t(1) << 31)) return false;
+        if (!(q.tau > 0.5f) || !(q.tau < 1e6f)) return false;
+        if (q.walls != 0 && q.walls != 1) return false;
+        if (q.u_wall_lo[1] != 0.0f || q.u_wall_hi[1] != 0.0f) return false;
+    }
+    return true;
+}
+
+size_t elem_size(lbm_storage s) { return s == LBM_STORE_F32 ? 4 : 2; }
+
+struct Sizes {
+    int64_t cells = 0, segs = 0, tiles = 0, slots = 0, list_cap = 0;
+};
+
+Sizes sizes_of(const lbm_params* p, int32_t nch, int64_t max_nodes) {
+    Sizes s;
+    for (int c = 0; c < nch; ++c) {
+        const int64_t n = (int64_t)p[c].nx * p[c].ny * p[c].nz;
+        s.cells += n;
+        s.segs += (n + 63) / 64;
+        s.tiles += (int64_t)((p[c].nx + TILE - 1) / TILE) * ((p[c].ny + TILE - 1) / TILE) * ((p[c].nz + TILE - 1) / TILE);
+    }
+    if (max_nodes > 0) {
+        s.slots = std::min<int64_t>(s.tiles, 27 * max_nodes);
+        s.list_cap = 27 * max_nodes;
+    }
+    return s;
+}
+
+Layout layout_of(const lbm_params* p, int32_t nch, lbm_storage st, int64_t max_nodes, Sizes& sz) {
+    sz = sizes_of(p, nch, max_nodes);
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.chan = take(sizeof(Chan) * nch);
+    L.seg_ch = take(sizeof(int32_t) * sz.segs);
+    L.popA = take(elem_size(st) * Q * sz.cells);
+    L.popB = take(elem_size(st) * Q * sz.cells);
+    L.flags = take(64);
+    if (max_nodes > 0) {
+        L.node_ch = take(sizeof(int32_t) * max_nodes);
+        L.rec = take(sizeof(float) * 20 * max_nodes);
+        for (int k = 0; k < 2; ++k) {
+            L.sets[k][0] = take(sizeof(int32_t) * sz.tiles);           // cnt
+            L.sets[k][1] = take(sizeof(int32_t) * sz.tiles);           // tile_slot
+            L.sets[k][2] = take(sizeof(int32_t) * sz.slots);           // flag_list
+            L.sets[k][3] = take(sizeof(int32_t) * sz.slots);           // flag_ch
+            L.sets[k][4] = take(sizeof(int32_t) * sz.slots);           // fill
+            L.sets[k][5] = take(sizeof(int32_t) * (sz.slots + 1));     // slot_off
+            L.sets[k][6] = take(sizeof(IbHdr));                        // header
+        }
+        L.list = take(sizeof(int32_t) * sz.list_cap);
+        L.force = take(sizeof(float) * 3 * TILE_CELLS * sz.slots);
+        L.vel = take(sizeof(float) * 3 * TILE_CELLS * sz.slots);
+    }
+    L.total = off;
+    return L;
+}
+
+// Round-up reciprocal for q = (umulhi(n, m) + n) >> s, exact for n < 2^31.
+void fast_div(uint32_t d, uint32_t& m, uint32_t& s) {
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    m = (uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+    s = l;
+}
+
+lbm_status hip_ok(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_ERR_HIP; }
+
+LatArgs lat_args(lbm_ctx* c) {
+    LatArgs a{};
+    a.chan = c->d_chan;
+    a.seg_ch = c->d_seg_ch;
+    a.nseg = c->total_segs;
+    a.src = c->pop[c->cur];
+    a.dst = c->pop[c->cur ^ 1];
+    if (c->max_nodes > 0) {
+        a.tile_slot = c->set[c->ibset].tile_slot;
+        a.force = c->d_force;
+    }
+    return a;
+}
+
+IbArgs ib_args(lbm_ctx* c, int set) {
+    IbArgs a{};
+    a.chan = c->d_chan;
+    a.node_ch = c->d_node_ch;
+    a.n = c->n_nodes;
+    a.rec = c->d_rec;
+    a.set = c->set[set];
+    a.other = c->set[set ^ 1];
+    a.list = c->d_list;
+    a.list_cap = c->list_cap;
+    a.force = c->d_force;
+    a.vel = c->d_vel;
+    a.flags = c->d_flags;
+    a.pop = c->pop[c->cur];
+    a.kernel = (int32_t)c->kernel;
+    return a;
+}
+
+lbm_status upload_chans(lbm_ctx* c) {
+    hipError_t e = hipMemcpyAsync(c->d_chan, c->chans.data(), sizeof(Chan) * c->nch, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return LBM_ERR_HIP;
+    return hip_ok(hipStreamSynchronize(c->stream));
+}
+
+lbm_status check_ib(lbm_ctx* c, int64_t n) {
+    if (c->max_nodes <= 0) return LBM_ERR_STATE;
+    if (!c->nodes_set) return LBM_ERR_STATE;
+    if (n != c->n_nodes) return LBM_ERR_ARG;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_status_string(lbm_status s) {
+    switch (s) {
+        case LBM_OK: return "ok";
+        case LBM_ERR_ARG: return "invalid argument";
+        case LBM_ERR_STATE: return "call out of order";
+        case LBM_ERR_HIP: return "HIP error";
+        case LBM_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+size_t lbm_workspace_bytes(const lbm_params* ch, int32_t nch, lbm_storage storage, int64_t max_nodes) {
+    if (!valid_params(ch, nch) || max_nodes < 0) return 0;
+    if (storage != LBM_STORE_F32 && storage != LBM_STORE_F16 && storage != LBM_STORE_BF16) return 0;
+    Sizes sz;
+    return layout_of(ch, nch, storage, max_nodes, sz).total;
+}
+
+lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib_kernel kernel, int64_t max_nodes,
+                      void* workspace, size_t bytes, void* stream, lbm_ctx** out) {
+    if (!out) return LBM_ERR_ARG;
+    *out = nullptr;
+    if (!valid_params(ch, nch) || max_nodes < 0 || !workspace) return LBM_ERR_ARG;
+    if (storage != LBM_STORE_F32 && storage != LBM_STORE_F16 && storage != LBM_STORE_BF16) return LBM_ERR_ARG;
+    if (kernel != IB_PHI_COS4 && kernel != IB_PHI_PESKIN4) return LBM_ERR_ARG;
+    if (((uintptr_t)workspace & 255) != 0) return LBM_ERR_ARG;
+    if (max_nodes > 0)
+        for (int c = 0; c < nch; ++c)
+            if (ch[c].nx < 4 || ch[c].nz < 4 || (!ch[c].walls && ch[c].ny < 4)) return LBM_ERR_UNSUPPORTED;
+    Sizes sz;
+    Layout L = layout_of(ch, nch, storage, max_nodes, sz);
+    if (bytes < L.total) return LBM_ERR_ARG;
+
+    lbm_ctx* c = new lbm_ctx();
+    c->nch = nch;
+    c->storage = storage;
+    c->kernel = kernel;
+    c->max_nodes = max_nodes;
+    c->stream = (hipStream_t)stream;
+    c->params.assign(ch, ch + nch);
+    c->total_cells = sz.cells;
+    c->total_segs = sz.segs;
+    c->total_tiles = sz.tiles;
+    c->max_slots = sz.slots;
+    c->list_cap = sz.list_cap;
+    c->esize = elem_size(storage);
+    c->ws = (char*)workspace;
+    c->lay = L;
+    c->d_chan = (Chan*)(c->ws + L.chan);
+    c->d_seg_ch = (int32_t*)(c->ws + L.seg_ch);
+    c->pop[0] = c->ws + L.popA;
+    c->pop[1] = c->ws + L.popB;
+    c->d_flags = (uint32_t*)(c->ws + L.flags);
+    if (max_nodes > 0) {
+        c->d_node_ch = (int32_t*)(c->ws + L.node_ch);
+        c->d_rec = (float*)(c->ws + L.rec);
+        for (int k = 0; k < 2; ++k) {
+            c->set[k].cnt = (int32_t*)(c->ws + L.sets[k][0]);
+            c->set[k].tile_slot = (int32_t*)(c->ws + L.sets[k][1]);
+            c->set[k].flag_list = (int32_t*)(c->ws + L.sets[k][2]);
+            c->set[k].flag_ch = (int32_t*)(c->ws + L.sets[k][3]);
+            c->set[k].fill = (int32_t*)(c->ws + L.sets[k][4]);
+            c->set[k].slot_off = (int32_t*)(c->ws + L.sets[k][5]);
+            c->set[k].hdr = (IbHdr*)(c->ws + L.sets[k][6]);
+        }
+        c->d_list = (int32_t*)(c->ws + L.list);
+        c->d_force = (float*)(c->ws + L.force);
+        c->d_vel = (float*)(c->ws + L.vel);
+    }
+
+    // channel descriptors and the segment map
+    c->chans.resize(nch);
+    std::vector<int32_t> seg_ch(sz.segs);
+    int64_t cell_off = 0, seg_off = 0, tile_off = 0, pop_off = 0, wss_off = 0;
+    for (int k = 0; k < nch; ++k) {
+        const lbm_params& p = ch[k];
+        Chan& d = c->chans[k];
+        memset(&d, 0, sizeof(d));
+        d.nx = p.nx; d.ny = p.ny; d.nz = p.nz; d.walls = p.walls;
+        d.ncell = (int64_t)p.nx * p.ny * p.nz;
+        d.pop_off = pop_off;
+        d.cell_off = cell_off;
+        d.seg_off = seg_off;
+        d.tile_off = tile_off;
+        d.wss_off = wss_off;
+        d.tnx = (p.nx + TILE - 1) / TILE;
+        d.tny = (p.ny + TILE - 1) / TILE;
+        d.tnz = (p.nz + TILE - 1) / TILE;
+        fast_div((uint32_t)p.nx, d.mx, d.sx);
+        fast_div((uint32_t)p.ny, d.my, d.sy);
+        d.tau = p.tau;
+        d.omega = 1.0f / p.tau;
+        d.guo = 1.0f - 0.5f / p.tau;
+        for (int q = 0; q < 3; ++q) {
+            d.body[q] = p.body_force[q];
+            d.uw_lo[q] = p.u_wall_lo[q];
+            d.uw_hi[q] = p.u_wall_hi[q];
+        }
+        const int64_t ns = (d.ncell + 63) / 64;
+        for (int64_t s = 0; s < ns; ++s) seg_ch[seg_off + s] = k;
+        pop_off += (int64_t)Q * d.ncell;
+        cell_off += d.ncell;
+        seg_off += ns;
+        tile_off += (int64_t)d.tnx * d.tny * d.tnz;
+        wss_off += 2 * (int64_t)p.nx * p.nz;
+    }
+    hipError_t e = hipMemcpyAsync(c->d_seg_ch, seg_ch.data(), sizeof(int32_t) * sz.segs, hipMemcpyHostToDevice, c->stream);
+    lbm_status st = e == hipSuccess ? upload_chans(c) : LBM_ERR_HIP;  // synchronises: seg_ch stays alive
+    if (st == LBM_OK) st = hip_ok(launch_fill_i32(c->stream, (int32_t*)c->d_flags, 16, 0));
+    if (st == LBM_OK && max_nodes > 0) {
+        for (int k = 0; k < 2 && st == LBM_OK; ++k) {
+            st = hip_ok(launch_fill_i32(c->stream, c->set[k].cnt, sz.tiles, 0));
+            if (st == LBM_OK) st = hip_ok(launch_fill_i32(c->stream, c->set[k].tile_slot, sz.tiles, -1));
+            if (st == LBM_OK) st = hip_ok(launch_fill_i32(c->stream, c->set[k].fill, sz.slots, 0));
+            if (st == LBM_OK) st = hip_ok(launch_fill_i32(c->stream, c->set[k].slot_off, sz.slots + 1, 0));
+            if (st == LBM_OK)
+                st = hip_ok(launch_fill_i32(c->stream, (int32_t*)c->set[k].hdr, sizeof(IbHdr) / 4, 0));
+        }
+    }
+    if (st != LBM_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_ctx* c) {
+    if (!c) return LBM_OK;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    delete c;
+    return hip_ok(e);
+}
+
+lbm_status lbm_init(lbm_ctx* c, const float* rho, const float* u) {
+    if (!c) return LBM_ERR_ARG;
+    LatArgs a = lat_args(c);
+    a.dst = c->pop[c->cur];
+    a.in_rho = rho;
+    a.in_u = u;
+    return hip_ok(launch_lattice(c, LK_INIT, a));
+}
+
+lbm_status lbm_step(lbm_ctx* c, int32_t nsteps) {
+    if (!c || nsteps < 0) return LBM_ERR_ARG;
+    for (int s = 0; s < nsteps; ++s) {
+        LatArgs a = lat_args(c);
+        hipError_t e = launch_lattice(c, LK_STEP, a);
+        if (e != hipSuccess) return LBM_ERR_HIP;
+        c->cur ^= 1;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx* c, float* drho, float* v) {
+    if (!c) return LBM_ERR_ARG;
+    if (!drho && !v) return LBM_OK;
+    LatArgs a = lat_args(c);
+    a.out_rho = drho;
+    a.out_v = v;
+    return hip_ok(launch_lattice(c, LK_MOMENTS, a));
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, float* f) {
+    if (!c || !f) return LBM_ERR_ARG;
+    LatArgs a = lat_args(c);
+    a.out_f = f;
+    return hip_ok(launch_lattice(c, LK_GETF, a));
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, const float* f) {
+    if (!c || !f) return LBM_ERR_ARG;
+    LatArgs a = lat_args(c);
+    a.dst = c->pop[c->cur];
+    a.in_f = f;
+    return hip_ok(launch_lattice(c, LK_SETF, a));
+}
+
+size_t lbm_state_bytes(const lbm_ctx* c) { return c ? (size_t)Q * c->total_cells * c->esize : 0; }
+
+lbm_status lbm_get_state(lbm_ctx* c, void* dst) {
+    if (!c || !dst) return LBM_ERR_ARG;
+    return hip_ok(hipMemcpyAsync(dst, c->pop[c->cur], lbm_state_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const void* src) {
+    if (!c || !src) return LBM_ERR_ARG;
+    return hip_ok(hipMemcpyAsync(c->pop[c->cur], src, lbm_state_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+}
+
+lbm_status lbm_wall_stress(lbm_ctx* c, float* lo, float* hi) {
+    if (!c || !lo || !hi) return LBM_ERR_ARG;
+    for (const lbm_params& p : c->params)
+        if (!p.walls) return LBM_ERR_STATE;
+    LatArgs a = lat_args(c);
+    a.out_lo = lo;
+    a.out_hi = hi;
+    int64_t total = 0;
+    for (const lbm_params& p : c->params) total += 2 * (int64_t)p.nx * p.nz;
+    return hip_ok(launch_wss(c, a, total));
+}
+
+lbm_status lbm_error_flags(lbm_ctx* c, uint32_t* flags) {
+    if (!c || !flags) return LBM_ERR_ARG;
+    uint32_t h = 0;
+    hipError_t e = hipMemcpyAsync(&h, c->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return LBM_ERR_HIP;
+    *flags = h;
+    return hip_ok(launch_fill_i32(c->stream, (int32_t*)c->d_flags, 1, 0));
+}
+
+lbm_status ib_set_nodes(lbm_ctx* c, int64_t n, const int64_t* node_offsets) {
+    if (!c) return LBM_ERR_ARG;
+    if (c->max_nodes <= 0) return LBM_ERR_STATE;
+    if (n < 0 || n > c->max_nodes) return LBM_ERR_ARG;
+    if (!node_offsets && c->nch != 1) return LBM_ERR_ARG;
+    std::vector<int64_t> off(c->nch + 1);
+    if (node_offsets) {
+        for (int k = 0; k <= c->nch; ++k) off[k] = node_offsets[k];
+        if (off[0] != 0 || off[c->nch] != n) return LBM_ERR_ARG;
+        for (int k = 0; k < c->nch; ++k)
+            if (off[k + 1] < off[k]) return LBM_ERR_ARG;
+    } else {
+        off[0] = 0;
+        off[1] = n;
+    }
+    std::vector<int32_t> node_ch(n > 0 ? n : 1);
+    for (int k = 0; k < c->nch; ++k) {
+        c->chans[k].node_lo = off[k];
+        c->chans[k].node_hi = off[k + 1];
+        for (int64_t m = off[k]; m < off[k + 1]; ++m) node_ch[m] = k;
+    }
+    if (n > 0) {
+        hipError_t e = hipMemcpyAsync(c->d_node_ch, node_ch.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return LBM_ERR_HIP;
+    }
+    lbm_status st = upload_chans(c);  // synchronises, so node_ch may go out of scope
+    if (st != LBM_OK) return st;
+    c->n_nodes = n;
+    c->nodes_set = true;
+    return LBM_OK;
+}
+
+lbm_status ib_spread(lbm_ctx* c, int64_t n, const double* X, const float* F) {
+    if (!c) return LBM_ERR_ARG;
+    lbm_status st = check_ib(c, n);
+    if (st != LBM_OK) return st;
+    if (n > 0 && (!X || !F)) return LBM_ERR_ARG;
+    c->ibset ^= 1;
+    IbArgs a = ib_args(c, c->ibset);
+    a.X = X;
+    a.F = F;
+    return hip_ok(launch_ib_spread(c, a));
+}
+
+lbm_status ib_interp(lbm_ctx* c, int64_t n, const double* X, float* U) {
+    if (!c) return LBM_ERR_ARG;
+    lbm_status st = check_ib(c, n);
+    if (st != LBM_OK) return st;
+    if (n > 0 && (!X || !U)) return LBM_ERR_ARG;
+    IbArgs a = ib_args(c, c->ibset);
+    a.X = X;
+    a.U = U;
+    return hip_ok(launch_ib_interp(c, a));
+}
+
+lbm_status ib_advance(lbm_ctx* c, int64_t n, double* X, const float* U) {
+    if (!c || n < 0) return LBM_ERR_ARG;
+    if (n > 0 && (!X || !U)) return LBM_ERR_ARG;
+    return hip_ok(launch_ib_advance(c->stream, n, X, U));
+}
+
+lbm_status ib_membrane_rest(const ib_membrane* m, const double* X_rest, void* stream) {
+    if (!m || m->n < 0 || (m->n > 0 && !X_rest)) return LBM_ERR_ARG;
+    if (m->nbr_ptr && (!m->nbr_idx || !m->rest_len)) return LBM_ERR_ARG;
+    if (m->nh > 0 && (!m->hinges || !m->rest_theta)) return LBM_ERR_ARG;
+    return hip_ok(launch_membrane_rest(m, X_rest, (hipStream_t)stream));
+}
+
+lbm_status ib_membrane_forces(const ib_membrane* m, const double* X, float* F, void* stream) {
+    if (!m || m->n < 0 || (m->n > 0 && (!X || !F))) return LBM_ERR_ARG;
+    if (m->nbr_ptr && (!m->nbr_idx || !m->rest_len)) return LBM_ERR_ARG;
+    if (m->hinge_ptr && (!m->hinge_inc || !m->hinges || !m->rest_theta)) return LBM_ERR_ARG;
+    return hip_ok(launch_membrane_forces(m, X, F, (hipStream_t)stream));
+}
+
+static lbm_status coupled(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, double* X, float* F, float* U) {
+    const int64_t n = c->n_nodes;
+    for (int s = 0; s < nsteps; ++s) {
+        if (m) {
+            hipError_t e = launch_membrane_forces(m, X, F, c->stream);
+            if (e != hipSuccess) return LBM_ERR_HIP;
+        }
+        c->ibset ^= 1;
+        IbArgs a = ib_args(c, c->ibset);
+        a.X = X;
+        a.F = F;
+        if (launch_ib_spread(c, a) != hipSuccess) return LBM_ERR_HIP;
+        LatArgs la = lat_args(c);
+        if (launch_lattice(c, LK_STEP, la) != hipSuccess) return LBM_ERR_HIP;
+        c->cur ^= 1;
+        IbArgs b = ib_args(c, c->ibset);
+        b.X = X;
+        b.U = U;
+        b.Xout = X;  // X <- X + U, fused into the gather
+        if (launch_ib_interp(c, b) != hipSuccess) return LBM_ERR_HIP;
+        (void)n;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_coupled_steps(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, double* X, float* F, float* U) {
+    if (!c || nsteps < 0) return LBM_ERR_ARG;
+    lbm_status st = check_ib(c, c->n_nodes);
+    if (st != LBM_OK) return st;
+    if (c->n_nodes > 0 && (!X || !F || !U)) return LBM_ERR_ARG;
+    if (m && m->n != c->n_nodes) return LBM_ERR_ARG;
+    return coupled(c, m, nsteps, X, F, U);
+}
+
+lbm_status lbm_graph_capture(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, double* X, float* F, float* U) {
+    if (!c || nsteps < 2 || (nsteps & 1)) return LBM_ERR_ARG;
+    lbm_status st = check_ib(c, c->n_nodes);
+    if (st != LBM_OK) return st;
+    if (c->n_nodes > 0 && (!X || !F || !U)) return LBM_ERR_ARG;
+    if (m && m->n != c->n_nodes) return LBM_ERR_ARG;
+    if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+    if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
+    const int cur0 = c->cur, set0 = c->ibset;
+    if (c->stream == nullptr) return LBM_ERR_UNSUPPORTED;  // the legacy default stream cannot be captured
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LBM_ERR_HIP;
+    st = coupled(c, m, nsteps, X, F, U);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    // nothing ran during capture; with an even step count the buffer and tile-set
+    // parities are back where they started when a replay ends
+    c->cur = cur0;
+    c->ibset = set0;
+    if (st != LBM_OK || e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return st != LBM_OK ? st : LBM_ERR_HIP;
+    }
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        return LBM_ERR_HIP;
+    }
+    c->graph = g;
+    return LBM_OK;
+}
+
+lbm_status lbm_graph_launch(lbm_ctx* c, int32_t repeats) {
+    if (!c || repeats < 0) return LBM_ERR_ARG;
+    if (!c->gexec) return LBM_ERR_STATE;
+    for (int r = 0; r < repeats; ++r)
+        if (hipGraphLaunch(c->gexec, c->stream) != hipSuccess) return LBM_ERR_HIP;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_launch(lbm_ctx* c, const lbm_launch* cfg) {
+    if (!c || !cfg) return LBM_ERR_ARG;
+    const int b = cfg->block;
+    if (b != 64 && b != 128 && b != 256 && b != 512 && b != 1024) return LBM_ERR_ARG;
+    if (cfg->persistent < 0 || (cfg->xcd_remap != 0 && cfg->xcd_remap != 1) ||
+        (cfg->nontemporal != 0 && cfg->nontemporal != 1))
+        return LBM_ERR_ARG;
+    c->launch = *cfg;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_launch(const lbm_ctx* c, lbm_launch* cfg) {
+    if (!c || !cfg) return LBM_ERR_ARG;
+    *cfg = c->launch;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,336 @@
+// lattice.hip -- lattice-Boltzmann kernels for gfx950 (section 3.3).
+//
+// State: weight-shifted populations g_i = f_i - w_i, SoA [19][nz][ny][nx] per channel, two
+// buffers.  The stored buffer holds the post-collision values f* of the previous step
+// ("pull" scheme), so one pass per step reads every population once from the neighbour
+// it streams from and writes every population once, aligned, at its own cell:
+//   152 B per cell per step in float32, 76 B in float16 / bfloat16.
+// Work is split into 64-cell segments (one wavefront each) over all channels; a
+// workgroup takes blockDim/64 consecutive segments.  With `remap` the workgroup order is
+// permuted so that consecutive segments land on the same XCD (the dispatcher deals
+// workgroups round-robin over the 8 XCDs), keeping the cache lines shared by adjacent
+// segments (x-shifted loads straddle them) inside one L2.
+#include "lbm_internal.h"
+
+namespace lbmib {
+
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
+    const int64_t per = G >> 3, rem = G & 7, x = b & 7;
+    return x * per + (x < rem ? x : rem) + (b >> 3);
+}
+
+// Iterate the segments assigned to this wavefront; body(ch, n) runs for every valid cell.
+template <class Body>
+__device__ __forceinline__ void for_cells(const LatArgs& a, Body body) {
+    const int wpb = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t G = gridDim.x;
+    int64_t L = a.remap ? xcd_remap(blockIdx.x, G) : (int64_t)blockIdx.x;
+    for (;; L += G) {
+        const int64_t seg = L * wpb + wave;
+        if (seg >= a.nseg) break;
+        const int c = a.seg_ch[seg];
+        const Chan& ch = a.chan[c];
+        const int64_t n = (seg - ch.seg_off) * 64 + lane;
+        if (n < ch.ncell) body(ch, (int32_t)n);
+        if (!a.persistent) break;
+    }
+}
+
+__device__ __forceinline__ void ib_force(const LatArgs& a, const Chan& ch, int x, int y, int z, float& Fx,
+                                         float& Fy, float& Fz) {
+    Fx = ch.body[0];
+    Fy = ch.body[1];
+    Fz = ch.body[2];
+    if (a.tile_slot) {
+        const int slot = a.tile_slot[tile_of(ch, x, y, z)];
+        if (slot >= 0) {
+            const float* fb = a.force + (int64_t)slot * (3 * TILE_CELLS) + tile_local(x, y, z);
+            Fx += fb[0];
+            Fy += fb[TILE_CELLS];
+            Fz += fb[2 * TILE_CELLS];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- one LBM step
+// For every cell: pull (with bounce-back), moments (Eq. (17)-(18)), v = (j + F/2)/rho,
+// shifted equilibrium of Eq. (20), Guo source of Eq. (19) (minus sign on the c_s^2 I
+// term), BGK relaxation (Eq. (16)), aligned store into the other buffer.
+template <class St, bool NT>
+__global__ void __launch_bounds__(1024) k_step(LatArgs a) {
+    using T = typename St::T;
+    for_cells(a, [&](const Chan& ch, int32_t n) {
+        int x, y, z;
+        cell_xyz(ch, (uint32_t)n, x, y, z);
+        const int64_t N = ch.ncell;
+        const T* s = (const T*)a.src + ch.pop_off;
+        T* d = (T*)a.dst + ch.pop_off;
+        float g[Q];
+        pull<St>(s, ch, N, n, x, y, z, g);
+        float drho, jx, jy, jz, Fx, Fy, Fz;
+        moments(g, drho, jx, jy, jz);
+        ib_force(a, ch, x, y, z, Fx, Fy, Fz);
+        const float rho = 1.0f + drho;
+        const float ir = 1.0f / rho;
+        const float vx = (jx + 0.5f * Fx) * ir, vy = (jy + 0.5f * Fy) * ir, vz = (jz + 0.5f * Fz) * ir;
+        const float vv15 = 1.5f * (vx * vx + vy * vy + vz * vz);
+        const float vF3 = 3.0f * (vx * Fx + vy * Fy + vz * Fz);
+        const float om = ch.omega, guo = ch.guo;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const float cu = cx(i) * vx + cy(i) * vy + cz(i) * vz;
+            const float cF = cx(i) * Fx + cy(i) * Fy + cz(i) * Fz;
+            const float geq = wgt(i) * (drho + rho * (3.0f * cu + 4.5f * cu * cu - vv15));
+            const float S = wgt(i) * guo * (3.0f * cF + 9.0f * cu * cF - vF3);
+            const float gn = g[i] - om * (g[i] - geq) + S;
+            if (NT)
+                St::st_nt(d + (int64_t)i * N + n, gn);
+            else
+                St::st(d + (int64_t)i * N + n, gn);
+        }
+    });
+}
+
+// ---------------------------------------------------------------- initial state
+// Shifted equilibrium of Eq. (20) at rho = 1 + drho and velocity u.
+__device__ __forceinline__ float geq_i(int i, float drho, float ux, float uy, float uz) {
+    const float rho = 1.0f + drho;
+    const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+    return wgt(i) * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * (ux * ux + uy * uy + uz * uz)));
+}
+
+// Cell reached from (x,y,z) along +c_i (x, z periodic; y periodic only without walls).
+// Returns false if +c_i leaves through a wall.
+__device__ __forceinline__ bool step_out(const Chan& ch, int i, int x, int y, int z, int32_t& m) {
+    int xs = x + cx(i), ys = y + cy(i), zs = z + cz(i);
+    if (ys < 0 || ys >= ch.ny) {
+        if (ch.walls) return false;
+        ys = ys < 0 ? ys + ch.ny : ys - ch.ny;
+    }
+    xs = xs < 0 ? xs + ch.nx : (xs >= ch.nx ? xs - ch.nx : xs);
+    zs = zs < 0 ? zs + ch.nz : (zs >= ch.nz ? zs - ch.nz : zs);
+    m = xs + ch.nx * (ys + ch.ny * zs);
+    return true;
+}
+
+__device__ __forceinline__ float wall_term(const Chan& ch, int i) {
+    // population i leaving through the wall on its own side: c_iy = +1 -> upper, -1 -> lower
+    const float* u = cy(i) > 0 ? ch.uw_hi : ch.uw_lo;
+    return 6.0f * wgt(i) * (cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2]);
+}
+
+// Un-stream: store s_i(x) such that the next pull yields the wanted pre-collision state
+// h_i at every cell: s_i(x) = h_i(x + c_i), or h_opp(i)(x) + 6 w_i c_i.u_w when x + c_i
+// is beyond a wall (the inverse of the bounce-back in `pull`).
+template <class St, class Src>
+__device__ __forceinline__ void unstream(const Chan& ch, typename St::T* d, int32_t n, int x, int y, int z,
+                                         Src h) {
+    const int64_t N = ch.ncell;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int32_t m;
+        float v;
+        if (step_out(ch, i, x, y, z, m))
+            v = h(i, m);
+        else
+            v = h(opp(i), n) + wall_term(ch, i);
+        St::st(d + (int64_t)i * N + n, v);
+    }
+}
+
+template <class St>
+__global__ void __launch_bounds__(1024) k_init(LatArgs a) {
+    using T = typename St::T;
+    for_cells(a, [&](const Chan& ch, int32_t n) {
+        int x, y, z;
+        cell_xyz(ch, (uint32_t)n, x, y, z);
+        T* d = (T*)a.dst + ch.pop_off;
+        const int64_t N = ch.ncell;
+        const float* rho = a.in_rho ? a.in_rho + ch.cell_off : nullptr;
+        const float* u = a.in_u ? a.in_u + 3 * ch.cell_off : nullptr;
+        auto h = [&](int i, int32_t m) {
+            float dr = rho ? rho[m] - 1.0f : 0.0f;
+            float ux, uy, uz;
+            if (u) {
+                ux = u[m];
+                uy = u[N + m];
+                uz = u[2 * N + m];
+            } else if (ch.walls) {
+                const int ym = (int)((m / ch.nx) % ch.ny);
+                const float s = ((float)ym + 0.5f) / (float)ch.ny;
+                ux = ch.uw_lo[0] + (ch.uw_hi[0] - ch.uw_lo[0]) * s;
+                uy = 0.0f;
+                uz = ch.uw_lo[2] + (ch.uw_hi[2] - ch.uw_lo[2]) * s;
+            } else {
+                ux = uy = uz = 0.0f;
+            }
+            return geq_i(i, dr, ux, uy, uz);
+        };
+        unstream<St>(ch, d, n, x, y, z, h);
+    });
+}
+
+template <class St>
+__global__ void __launch_bounds__(1024) k_setf(LatArgs a) {
+    using T = typename St::T;
+    for_cells(a, [&](const Chan& ch, int32_t n) {
+        int x, y, z;
+        cell_xyz(ch, (uint32_t)n, x, y, z);
+        T* d = (T*)a.dst + ch.pop_off;
+        const int64_t N = ch.ncell;
+        const float* f = a.in_f + (int64_t)Q * ch.cell_off;
+        auto h = [&](int i, int32_t m) { return f[(int64_t)i * N + m] - wgt(i); };
+        unstream<St>(ch, d, n, x, y, z, h);
+    });
+}
+
+// ---------------------------------------------------------------- read-outs
+template <class St>
+__global__ void __launch_bounds__(1024) k_moments(LatArgs a) {
+    using T = typename St::T;
+    for_cells(a, [&](const Chan& ch, int32_t n) {
+        int x, y, z;
+        cell_xyz(ch, (uint32_t)n, x, y, z);
+        const int64_t N = ch.ncell;
+        float g[Q];
+        pull<St>((const T*)a.src + ch.pop_off, ch, N, n, x, y, z, g);
+        float drho, jx, jy, jz, Fx, Fy, Fz;
+        moments(g, drho, jx, jy, jz);
+        ib_force(a, ch, x, y, z, Fx, Fy, Fz);
+        const float ir = 1.0f / (1.0f + drho);
+        if (a.out_rho) a.out_rho[ch.cell_off + n] = drho;
+        if (a.out_v) {
+            float* v = a.out_v + 3 * ch.cell_off;
+            v[n] = (jx + 0.5f * Fx) * ir;
+            v[N + n] = (jy + 0.5f * Fy) * ir;
+            v[2 * N + n] = (jz + 0.5f * Fz) * ir;
+        }
+    });
+}
+
+template <class St>
+__global__ void __launch_bounds__(1024) k_getf(LatArgs a) {
+    using T = typename St::T;
+    for_cells(a, [&](const Chan& ch, int32_t n) {
+        int x, y, z;
+        cell_xyz(ch, (uint32_t)n, x, y, z);
+        const int64_t N = ch.ncell;
+        float g[Q];
+        pull<St>((const T*)a.src + ch.pop_off, ch, N, n, x, y, z, g);
+        float* f = a.out_f + (int64_t)Q * ch.cell_off;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[(int64_t)i * N + n] = g[i] + wgt(i);
+    });
+}
+
+// Wall stress at rows y = 0 and y = ny-1, one thread per (x, z, side).  Output index
+// space: per channel [2 sides][nx*nz], channels concatenated (Chan::wss_off).
+template <class St>
+__global__ void __launch_bounds__(256) k_wss(LatArgs a, int nch, int64_t total) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    using T = typename St::T;
+    if (gid >= total) return;
+    int c = 0;  // channel owning this output element (few channels: linear search)
+    while (c + 1 < nch && gid >= a.chan[c + 1].wss_off) ++c;
+    const Chan& ch = a.chan[c];
+    const int64_t k = gid - ch.wss_off;
+    const int64_t plane = (int64_t)ch.nx * ch.nz;
+    const int side = k >= plane ? 1 : 0;
+    const int64_t q = k - side * plane;
+    const int x = (int)(q % ch.nx), z = (int)(q / ch.nx);
+    const int y = side ? ch.ny - 1 : 0;
+    const int32_t n = x + ch.nx * (y + ch.ny * z);
+    const int64_t N = ch.ncell;
+    float g[Q];
+    pull<St>((const T*)a.src + ch.pop_off, ch, N, n, x, y, z, g);
+    float drho, jx, jy, jz, Fx, Fy, Fz;
+    moments(g, drho, jx, jy, jz);
+    ib_force(a, ch, x, y, z, Fx, Fy, Fz);
+    const float rho = 1.0f + drho, ir = 1.0f / rho;
+    const float vx = (jx + 0.5f * Fx) * ir, vy = (jy + 0.5f * Fy) * ir, vz = (jz + 0.5f * Fz) * ir;
+    float sxy = 0.f, szy = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (cy(i) == 0) continue;
+        const float neq = g[i] - geq_i(i, drho, vx, vy, vz);
+        if (cx(i)) sxy += (float)(cx(i) * cy(i)) * neq;
+        if (cz(i)) szy += (float)(cz(i) * cy(i)) * neq;
+    }
+    const float k2 = 1.0f - 0.5f * ch.omega;
+    float* out = (side ? a.out_hi : a.out_lo) + ch.wss_off;
+    out[q] = -k2 * sxy - k2 * 0.5f * (Fx * vy + Fy * vx);
+    out[plane + q] = -k2 * szy - k2 * 0.5f * (Fz * vy + Fy * vz);
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    k_fill_i32<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+template <class St>
+static hipError_t launch_typed(lbm_ctx* c, int which, const LatArgs& a0) {
+    LatArgs a = a0;
+    const int block = c->launch.block;
+    const int wpb = block / 64;
+    const int64_t nblk = (c->total_segs + wpb - 1) / wpb;
+    int64_t grid = nblk;
+    a.remap = c->launch.xcd_remap;
+    a.persistent = 0;
+    if (which == LK_STEP && c->launch.persistent > 0 && c->launch.persistent < nblk) {
+        grid = c->launch.persistent;
+        a.persistent = 1;
+    }
+    if (which != LK_STEP) a.remap = 0;
+    dim3 g((unsigned)grid), b((unsigned)block);
+    switch (which) {
+        case LK_STEP:
+            if (c->launch.nontemporal)
+                k_step<St, true><<<g, b, 0, c->stream>>>(a);
+            else
+                k_step<St, false><<<g, b, 0, c->stream>>>(a);
+            break;
+        case LK_INIT: k_init<St><<<g, b, 0, c->stream>>>(a); break;
+        case LK_MOMENTS: k_moments<St><<<g, b, 0, c->stream>>>(a); break;
+        case LK_GETF: k_getf<St><<<g, b, 0, c->stream>>>(a); break;
+        case LK_SETF: k_setf<St><<<g, b, 0, c->stream>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <class St>
+static hipError_t launch_wss_typed(lbm_ctx* c, const LatArgs& a, int64_t total) {
+    const int64_t blocks = (total + 255) / 256;
+    k_wss<St><<<dim3((unsigned)blocks), dim3(256), 0, c->stream>>>(a, c->nch, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice(lbm_ctx* c, int which, const LatArgs& a) {
+    switch (c->storage) {
+        case LBM_STORE_F32: return launch_typed<StF32>(c, which, a);
+        case LBM_STORE_F16: return launch_typed<StF16>(c, which, a);
+        case LBM_STORE_BF16: return launch_typed<StBF16>(c, which, a);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_wss(lbm_ctx* c, const LatArgs& a, int64_t total) {
+    switch (c->storage) {
+        case LBM_STORE_F32: return launch_wss_typed<StF32>(c, a, total);
+        case LBM_STORE_F16: return launch_wss_typed<StF16>(c, a, total);
+        case LBM_STORE_BF16: return launch_wss_typed<StBF16>(c, a, total);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lbmib

@@ -1,0 +1,156 @@
+// lbm_device.h -- device-side building blocks shared by the library's kernels.
+//
+// D3Q19 in the paper's numbering (section 3.3, Eq. (21); the order of the directions
+// is the one fixed by the on-site wall equations Eq. (23)-(30)), population storage
+// codecs for the weight-shifted state g_i = f_i - w_i, the per-channel descriptor and
+// the pull-streaming gather with halfway bounce-back at the y-walls.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmib {
+
+constexpr int Q = 19;
+constexpr int TILE = 8;               // immersed-boundary tile edge (cells)
+constexpr int TILE_CELLS = TILE * TILE * TILE;
+
+__host__ __device__ constexpr int cx(int i) {
+    constexpr int t[Q] = {1, -1, 0, 0, 0, 0, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0, 0, 0};
+    return t[i];
+}
+__host__ __device__ constexpr int cy(int i) {
+    constexpr int t[Q] = {0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0};
+    return t[i];
+}
+__host__ __device__ constexpr int cz(int i) {
+    constexpr int t[Q] = {0, 0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 1, -1, 0};
+    return t[i];
+}
+__host__ __device__ constexpr int opp(int i) {
+    constexpr int t[Q] = {1, 0, 3, 2, 5, 4, 11, 10, 13, 12, 7, 6, 9, 8, 17, 16, 15, 14, 18};
+    return t[i];
+}
+__host__ __device__ constexpr float wgt(int i) {
+    return i < 6 ? 1.0f / 18.0f : (i < 18 ? 1.0f / 36.0f : 1.0f / 3.0f);
+}
+
+// Per-channel descriptor (device copy in the workspace; read with scalar loads).
+struct Chan {
+    int32_t nx, ny, nz, walls;
+    int64_t ncell;     // nx*ny*nz (< 2^31)
+    int64_t pop_off;   // element offset of this channel's [19][ncell] population block
+    int64_t cell_off;  // offset of this channel in concatenated per-cell outputs
+    int64_t seg_off;   // first 64-cell segment of this channel
+    int64_t tile_off;  // first IB tile of this channel
+    int64_t node_lo, node_hi;  // immersed-boundary nodes of this channel
+    int64_t wss_off;   // offset in the concatenated [2][nz][nx] wall-stress outputs
+    int32_t tnx, tny, tnz, pad0;  // IB tiles per axis
+    uint32_t mx, sx, my, sy;      // fast division by nx and ny
+    float tau, omega, guo, pad1;  // tau, 1/tau, 1 - 1/(2 tau)
+    float body[3];
+    float uw_lo[3];
+    float uw_hi[3];
+    float pad2[3];
+};
+
+// q = n / d for n < 2^31 (round-up reciprocal, see host set-up).
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t m, uint32_t s) {
+    return (__umulhi(n, m) + n) >> s;
+}
+
+__device__ __forceinline__ void cell_xyz(const Chan& ch, uint32_t n, int& x, int& y, int& z) {
+    uint32_t q = fdiv(n, ch.mx, ch.sx);
+    x = (int)(n - q * (uint32_t)ch.nx);
+    uint32_t r = fdiv(q, ch.my, ch.sy);
+    y = (int)(q - r * (uint32_t)ch.ny);
+    z = (int)r;
+}
+
+// ---------------------------------------------------------------- storage codecs
+struct StF32 {
+    using T = float;
+    static __device__ __forceinline__ float ld(const T* p) { return *p; }
+    static __device__ __forceinline__ void st(T* p, float v) { *p = v; }
+    static __device__ __forceinline__ void st_nt(T* p, float v) { __builtin_nontemporal_store(v, p); }
+};
+struct StF16 {
+    using T = uint16_t;
+    static __device__ __forceinline__ float ld(const T* p) { return __half2float(__ushort_as_half(*p)); }
+    static __device__ __forceinline__ uint16_t enc(float v) { return __half_as_ushort(__float2half_rn(v)); }
+    static __device__ __forceinline__ void st(T* p, float v) { *p = enc(v); }
+    static __device__ __forceinline__ void st_nt(T* p, float v) { __builtin_nontemporal_store(enc(v), p); }
+};
+struct StBF16 {
+    using T = uint16_t;
+    static __device__ __forceinline__ float ld(const T* p) { return __uint_as_float((uint32_t)(*p) << 16); }
+    // round to nearest, ties to even; NaN stays a quiet NaN
+    static __device__ __forceinline__ uint16_t enc(float v) {
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+    }
+    static __device__ __forceinline__ void st(T* p, float v) { *p = enc(v); }
+    static __device__ __forceinline__ void st_nt(T* p, float v) { __builtin_nontemporal_store(enc(v), p); }
+};
+
+// ---------------------------------------------------------------- pull streaming
+// Populations arriving at cell n = (x, y, z) of the current step: f_i(x) = f*_i(x - c_i)
+// with x, z periodic; when x - c_i lies beyond a y-wall the halfway bounce-back gives
+// f_i(x) = f*_opp(i)(x) + 6 w_i c_i.u_w.  In the shifted variables the same relation
+// holds for g = f - w because w_i = w_opp(i).  `s` points at the channel's block.
+template <class St>
+__device__ __forceinline__ void pull(const typename St::T* __restrict__ s, const Chan& ch, int64_t N,
+                                     int32_t n, int x, int y, int z, float g[Q]) {
+    const int nx = ch.nx, ny = ch.ny, nz = ch.nz;
+    const int32_t sxy = nx * ny;
+    const int32_t ox_p = (x == 0) ? (nx - 1) : -1;          // c_x = +1 comes from x-1
+    const int32_t ox_m = (x == nx - 1) ? -(nx - 1) : 1;     // c_x = -1 comes from x+1
+    const int32_t oy_p = (y == 0) ? (ny - 1) * nx : -nx;
+    const int32_t oy_m = (y == ny - 1) ? -(ny - 1) * nx : nx;
+    const int32_t oz_p = (z == 0) ? (nz - 1) * sxy : -sxy;
+    const int32_t oz_m = (z == nz - 1) ? -(nz - 1) * sxy : sxy;
+    const bool wlo = ch.walls && y == 0;
+    const bool whi = ch.walls && y == ny - 1;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int32_t off = (cx(i) == 1 ? ox_p : (cx(i) == -1 ? ox_m : 0)) +
+                      (cy(i) == 1 ? oy_p : (cy(i) == -1 ? oy_m : 0)) +
+                      (cz(i) == 1 ? oz_p : (cz(i) == -1 ? oz_m : 0));
+        const bool bb = (cy(i) == 1 && wlo) || (cy(i) == -1 && whi);
+        const typename St::T* p = bb ? (s + (int64_t)opp(i) * N + n) : (s + (int64_t)i * N + (n + off));
+        float v = St::ld(p);
+        if (cy(i) != 0) {
+            const float* u = cy(i) == 1 ? ch.uw_lo : ch.uw_hi;
+            float corr = 6.0f * wgt(i) * (cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2]);
+            v += bb ? corr : 0.0f;
+        }
+        g[i] = v;
+    }
+}
+
+// Zeroth and first moments of the shifted populations: drho = sum g, j = sum c g
+// (Eq. (17)-(18) with sum w = 1 and sum w c = 0).
+__device__ __forceinline__ void moments(const float g[Q], float& drho, float& jx, float& jy, float& jz) {
+    float r = 0.f, a = 0.f, b = 0.f, c = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        r += g[i];
+        if (cx(i)) a += cx(i) * g[i];
+        if (cy(i)) b += cy(i) * g[i];
+        if (cz(i)) c += cz(i) * g[i];
+    }
+    drho = r; jx = a; jy = b; jz = c;
+}
+
+// IB force-field lookup: tile of the cell -> slot (or -1) -> [3][512] block.
+__device__ __forceinline__ int64_t tile_of(const Chan& ch, int x, int y, int z) {
+    return ch.tile_off + (x >> 3) + (int64_t)ch.tnx * ((y >> 3) + (int64_t)ch.tny * (z >> 3));
+}
+__device__ __forceinline__ int tile_local(int x, int y, int z) {
+    return ((z & 7) << 6) | ((y & 7) << 3) | (x & 7);
+}
+
+}  // namespace lbmib

@@ -1,0 +1,128 @@
+// lbm_internal.h -- host-side context and the launchers shared by the library's sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_device.h"
+
+namespace lbmib {
+
+// Header of one immersed-boundary tile set (device).
+struct IbHdr {
+    int32_t nflag;       // flagged tiles of the last spread using this set
+    uint32_t fmax_bits;  // max |F| over the nodes (float bits)
+    int32_t scale_exp;   // fixed-point scale 2^scale_exp of the spread accumulation
+    int32_t nonfinite;   // 1 if a force was Inf/NaN
+};
+
+// Device arrays of one tile set.  Two sets alternate between successive spreads so
+// that each spread can clear the set used two spreads earlier without an extra launch.
+struct IbSet {
+    int32_t* cnt;        // [ntiles] nodes whose stencil touches the tile
+    int32_t* tile_slot;  // [ntiles] slot of a flagged tile, -1 otherwise
+    int32_t* flag_list;  // [max_slots] tile id of each slot
+    int32_t* flag_ch;    // [max_slots] channel of each slot
+    int32_t* fill;       // [max_slots] fill counters of the node lists
+    int32_t* slot_off;   // [max_slots+1] list offsets
+    IbHdr* hdr;
+};
+
+// Arguments of the lattice kernels (walk over 64-cell segments of all channels).
+struct LatArgs {
+    const Chan* chan;
+    const int32_t* seg_ch;
+    int64_t nseg;
+    const void* src;        // current stored (post-collision, shifted) populations
+    void* dst;              // next buffer (lbm_step) or unused
+    const int32_t* tile_slot;  // IB tile -> slot of the current force field, or null
+    const float* force;        // [slots][3][512]
+    int32_t remap;          // XCD-aware block order
+    int32_t persistent;     // loop over blocks
+    // auxiliary inputs / outputs of the non-step kernels
+    const float* in_rho;
+    const float* in_u;
+    const float* in_f;
+    float* out_rho;
+    float* out_v;
+    float* out_f;
+    float* out_lo;
+    float* out_hi;
+};
+
+struct IbArgs {
+    const Chan* chan;
+    const int32_t* node_ch;
+    int64_t n;
+    const double* X;
+    const float* F;
+    float* U;
+    double* Xout;
+    float* rec;             // [n][20] node records
+    IbSet set;              // tile set of this spread
+    IbSet other;            // set cleared by this spread
+    int32_t* list;
+    int64_t list_cap;
+    float* force;           // [max_slots][3][512]
+    float* vel;             // [max_slots][3][512]
+    uint32_t* flags;
+    const void* pop;        // current stored populations (interpolation)
+    int32_t kernel;         // ib_kernel
+};
+
+struct Layout {
+    size_t chan, seg_ch, popA, popB, flags, node_ch, rec, sets[2][7], list, force, vel, total;
+};
+
+}  // namespace lbmib
+
+struct lbm_ctx {
+    int nch = 0;
+    lbm_storage storage = LBM_STORE_F32;
+    ib_kernel kernel = IB_PHI_COS4;
+    int64_t max_nodes = 0;
+    hipStream_t stream = nullptr;
+    std::vector<lbm_params> params;
+    std::vector<lbmib::Chan> chans;
+    int64_t total_cells = 0, total_segs = 0, total_tiles = 0, max_slots = 0, list_cap = 0;
+    size_t esize = 4;
+    char* ws = nullptr;
+    lbmib::Layout lay{};
+    lbmib::Chan* d_chan = nullptr;
+    int32_t* d_seg_ch = nullptr;
+    void* pop[2] = {nullptr, nullptr};
+    int cur = 0;  // buffer holding the current state
+    uint32_t* d_flags = nullptr;
+    // immersed boundary
+    int64_t n_nodes = 0;
+    bool nodes_set = false;
+    int32_t* d_node_ch = nullptr;
+    float* d_rec = nullptr;
+    lbmib::IbSet set[2]{};
+    int ibset = 0;  // set of the latest spread (both clean at creation)
+    int32_t* d_list = nullptr;
+    float* d_force = nullptr;
+    float* d_vel = nullptr;
+    lbm_launch launch{256, 1, 0, 0};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+namespace lbmib {
+
+// lattice.hip
+hipError_t launch_lattice(lbm_ctx* c, int which, const LatArgs& a);
+enum { LK_STEP = 0, LK_INIT, LK_MOMENTS, LK_GETF, LK_SETF, LK_WSS };
+hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
+hipError_t launch_wss(lbm_ctx* c, const LatArgs& a, int64_t total);
+
+// ib.hip
+hipError_t launch_ib_spread(lbm_ctx* c, const IbArgs& a);
+hipError_t launch_ib_interp(lbm_ctx* c, const IbArgs& a);
+hipError_t launch_ib_advance(hipStream_t s, int64_t n, double* X, const float* U);
+hipError_t launch_membrane_rest(const ib_membrane* m, const double* X_rest, hipStream_t s);
+hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* F, hipStream_t s);
+
+}  // namespace lbmib

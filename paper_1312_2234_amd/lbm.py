@@ -1,0 +1,354 @@
+"""ctypes binding of the gfx950 C-ABI library (include/lbm.h).
+
+Argument marshalling only: every computation runs in the library's HIP kernels.  PyTorch
+provides the device memory (the workspace and the caller-owned arrays) and the stream.
+The library must be built (``python -m paper_1312_2234_amd.build``); loading fails
+loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmib.so")
+
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+KERNEL = {"cos": 0, "peskin4": 1}
+FLAG_NODE_OUTSIDE, FLAG_LIST_OVERFLOW, FLAG_FORCE_NONFINITE, FLAG_CLOSURE_FALLBACK = 1, 2, 4, 8
+
+EXPORTS = [
+    "lbm_workspace_bytes", "lbm_create", "lbm_destroy", "lbm_init", "lbm_step", "ib_set_nodes",
+    "ib_spread", "ib_interp", "ib_advance", "lbm_moments", "lbm_get_populations",
+    "lbm_set_populations", "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_wall_stress",
+    "lbm_error_flags", "lbm_status_string", "ib_membrane_rest", "ib_membrane_forces",
+    "lbm_coupled_steps", "lbm_graph_capture", "lbm_graph_launch", "lbm_set_launch", "lbm_get_launch",
+]
+
+
+class LbmParams(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("walls", C.c_int32),
+                ("tau", C.c_float), ("body_force", C.c_float * 3), ("u_wall_lo", C.c_float * 3),
+                ("u_wall_hi", C.c_float * 3)]
+
+
+class LbmLaunch(C.Structure):
+    _fields_ = [("block", C.c_int32), ("xcd_remap", C.c_int32), ("persistent", C.c_int32),
+                ("nontemporal", C.c_int32)]
+
+
+class IbMembrane(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nbr_ptr", C.c_void_p), ("nbr_idx", C.c_void_p), ("rest_len", C.c_void_p),
+                ("k_spring", C.c_double), ("hinge_ptr", C.c_void_p), ("hinge_inc", C.c_void_p),
+                ("hinges", C.c_void_p), ("rest_theta", C.c_void_p), ("nh", C.c_int64), ("k_bend", C.c_double),
+                ("anchors", C.c_void_p), ("k_tether", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load liblbmib.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("liblbmib.so is not built: run `python -m paper_1312_2234_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, f32p = C.c_void_p, C.c_int32, C.c_int64, C.c_void_p
+        P = C.POINTER(LbmParams)
+        L.lbm_workspace_bytes.argtypes = [P, i32, i32, i64]
+        L.lbm_workspace_bytes.restype = C.c_size_t
+        L.lbm_create.argtypes = [P, i32, i32, i32, i64, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_init.argtypes = [vp, vp, vp]
+        L.lbm_step.argtypes = [vp, i32]
+        L.ib_set_nodes.argtypes = [vp, i64, C.POINTER(C.c_int64)]
+        L.ib_spread.argtypes = [vp, i64, vp, vp]
+        L.ib_interp.argtypes = [vp, i64, vp, vp]
+        L.ib_advance.argtypes = [vp, i64, vp, vp]
+        L.lbm_moments.argtypes = [vp, vp, vp]
+        L.lbm_get_populations.argtypes = [vp, vp]
+        L.lbm_set_populations.argtypes = [vp, vp]
+        L.lbm_state_bytes.argtypes = [vp]
+        L.lbm_state_bytes.restype = C.c_size_t
+        L.lbm_get_state.argtypes = [vp, vp]
+        L.lbm_set_state.argtypes = [vp, vp]
+        L.lbm_wall_stress.argtypes = [vp, vp, vp]
+        L.lbm_error_flags.argtypes = [vp, C.POINTER(C.c_uint32)]
+        L.lbm_status_string.argtypes = [i32]
+        L.lbm_status_string.restype = C.c_char_p
+        M = C.POINTER(IbMembrane)
+        L.ib_membrane_rest.argtypes = [M, vp, vp]
+        L.ib_membrane_forces.argtypes = [M, vp, vp, vp]
+        L.lbm_coupled_steps.argtypes = [vp, M, i32, vp, vp, vp]
+        L.lbm_graph_capture.argtypes = [vp, M, i32, vp, vp, vp]
+        L.lbm_graph_launch.argtypes = [vp, i32]
+        L.lbm_set_launch.argtypes = [vp, C.POINTER(LbmLaunch)]
+        L.lbm_get_launch.argtypes = [vp, C.POINTER(LbmLaunch)]
+        for name in EXPORTS:
+            if name not in ("lbm_workspace_bytes", "lbm_state_bytes", "lbm_status_string"):
+                getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+class LbmError(RuntimeError):
+    pass
+
+
+def _check(status, what):
+    if status != 0:
+        msg = lib().lbm_status_string(status).decode()
+        raise LbmError("%s failed: %s (%d)" % (what, msg, status))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_contiguous(), "arrays passed to the library must be contiguous"
+    return C.c_void_p(t.data_ptr())
+
+
+def params_of(ch) -> LbmParams:
+    """lbm_params from an inputs.Channel (or any object with the same fields)."""
+    return LbmParams(ch.nx, ch.ny, ch.nz, 1 if ch.walls else 0, float(ch.tau), (C.c_float * 3)(*ch.body),
+                     (C.c_float * 3)(*ch.u_wall_lo), (C.c_float * 3)(*ch.u_wall_hi))
+
+
+def _stream_ptr(torch, device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class _Ordered:
+    """Order the context's stream after torch's current stream on entry and torch's current
+    stream after the context's stream on exit (event waits, no host synchronisation)."""
+
+    def __init__(self, lat):
+        self.lat = lat
+
+    def __enter__(self):
+        self.lat.stream.wait_stream(self.lat.torch.cuda.current_stream(self.lat.device))
+
+    def __exit__(self, *exc):
+        self.lat.torch.cuda.current_stream(self.lat.device).wait_stream(self.lat.stream)
+        return False
+
+
+class Lattice:
+    """One context over `channels` (list of inputs.Channel-like objects).
+
+    The context owns a torch stream of default priority (a non-default stream, so that its
+    work can be captured into a HIP graph); every call is ordered after torch's current
+    stream and torch's current stream after it."""
+
+    def __init__(self, channels, storage="f32", kernel="cos", max_nodes=0, device="cuda:0"):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(self.device)
+        self.ordered = _Ordered(self)
+        self.channels = list(channels)
+        self.nch = len(self.channels)
+        arr = (LbmParams * self.nch)(*[params_of(c) for c in self.channels])
+        self._params = arr
+        self.storage = storage
+        nbytes = lib().lbm_workspace_bytes(arr, self.nch, STORAGE[storage], int(max_nodes))
+        if nbytes == 0:
+            raise LbmError("invalid lattice parameters")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        h = C.c_void_p()
+        with self.ordered:
+            _check(lib().lbm_create(arr, self.nch, STORAGE[storage], KERNEL[kernel], int(max_nodes),
+                                    C.c_void_p(base + off), nbytes, C.c_void_p(self.stream.cuda_stream),
+                                    C.byref(h)), "lbm_create")
+        self.h = h
+        self.cells = [c.nx * c.ny * c.nz for c in self.channels]
+        self.total_cells = sum(self.cells)
+        self.n_nodes = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- lattice
+    def init(self, rho=None, u=None):
+        with self.ordered:
+            _check(lib().lbm_init(self.h, _ptr(rho), _ptr(u)), "lbm_init")
+
+    def step(self, nsteps=1):
+        with self.ordered:
+            _check(lib().lbm_step(self.h, int(nsteps)), "lbm_step")
+
+    def moments(self):
+        t = self.torch
+        drho = t.empty(self.total_cells, dtype=t.float32, device=self.device)
+        v = t.empty(3 * self.total_cells, dtype=t.float32, device=self.device)
+        with self.ordered:
+            _check(lib().lbm_moments(self.h, _ptr(drho), _ptr(v)), "lbm_moments")
+        return drho, v
+
+    def moments_channel(self, c=0):
+        """(drho[nz,ny,nx], v[3,nz,ny,nx]) of channel c as torch tensors."""
+        drho, v = self.moments()
+        ch = self.channels[c]
+        off = sum(self.cells[:c])
+        n = self.cells[c]
+        shp = (ch.nz, ch.ny, ch.nx)
+        return drho[off:off + n].view(shp), v[3 * off:3 * off + 3 * n].view((3,) + shp)
+
+    def populations(self):
+        t = self.torch
+        f = t.empty(19 * self.total_cells, dtype=t.float32, device=self.device)
+        with self.ordered:
+            _check(lib().lbm_get_populations(self.h, _ptr(f)), "lbm_get_populations")
+        return f
+
+    def set_populations(self, f):
+        with self.ordered:
+            _check(lib().lbm_set_populations(self.h, _ptr(f)), "lbm_set_populations")
+
+    def state_bytes(self):
+        return lib().lbm_state_bytes(self.h)
+
+    def get_state(self):
+        t = self.torch
+        buf = t.empty(self.state_bytes(), dtype=t.uint8, device=self.device)
+        with self.ordered:
+            _check(lib().lbm_get_state(self.h, _ptr(buf)), "lbm_get_state")
+        return buf
+
+    def set_state(self, buf):
+        with self.ordered:
+            _check(lib().lbm_set_state(self.h, _ptr(buf)), "lbm_set_state")
+
+    def wall_stress(self):
+        t = self.torch
+        tot = sum(2 * c.nx * c.nz for c in self.channels)
+        lo = t.empty(tot, dtype=t.float32, device=self.device)
+        hi = t.empty(tot, dtype=t.float32, device=self.device)
+        with self.ordered:
+            _check(lib().lbm_wall_stress(self.h, _ptr(lo), _ptr(hi)), "lbm_wall_stress")
+        return lo, hi
+
+    def error_flags(self):
+        f = C.c_uint32()
+        _check(lib().lbm_error_flags(self.h, C.byref(f)), "lbm_error_flags")
+        return f.value
+
+    # -- immersed boundary
+    def set_nodes(self, n, offsets=None):
+        if offsets is not None:
+            arr = (C.c_int64 * len(offsets))(*[int(o) for o in offsets])
+            _check(lib().ib_set_nodes(self.h, int(n), arr), "ib_set_nodes")
+        else:
+            _check(lib().ib_set_nodes(self.h, int(n), None), "ib_set_nodes")
+        self.n_nodes = int(n)
+
+    def spread(self, X, F):
+        with self.ordered:
+            _check(lib().ib_spread(self.h, self.n_nodes, _ptr(X), _ptr(F)), "ib_spread")
+
+    def interp(self, X, U=None):
+        t = self.torch
+        if U is None:
+            U = t.empty((3, self.n_nodes), dtype=t.float32, device=self.device)
+        with self.ordered:
+            _check(lib().ib_interp(self.h, self.n_nodes, _ptr(X), _ptr(U)), "ib_interp")
+        return U
+
+    def advance(self, X, U):
+        with self.ordered:
+            _check(lib().ib_advance(self.h, self.n_nodes, _ptr(X), _ptr(U)), "ib_advance")
+
+    def coupled_steps(self, membrane, nsteps, X, F, U):
+        m = C.byref(membrane.struct) if membrane is not None else None
+        with self.ordered:
+            _check(lib().lbm_coupled_steps(self.h, m, int(nsteps), _ptr(X), _ptr(F), _ptr(U)), "lbm_coupled_steps")
+
+    def graph_capture(self, membrane, nsteps, X, F, U):
+        m = C.byref(membrane.struct) if membrane is not None else None
+        with self.ordered:
+            _check(lib().lbm_graph_capture(self.h, m, int(nsteps), _ptr(X), _ptr(F), _ptr(U)), "lbm_graph_capture")
+
+    def graph_launch(self, repeats=1):
+        with self.ordered:
+            _check(lib().lbm_graph_launch(self.h, int(repeats)), "lbm_graph_launch")
+
+    def set_launch(self, block=256, xcd_remap=1, persistent=0, nontemporal=0):
+        cfg = LbmLaunch(block, xcd_remap, persistent, nontemporal)
+        _check(lib().lbm_set_launch(self.h, C.byref(cfg)), "lbm_set_launch")
+
+    def get_launch(self):
+        cfg = LbmLaunch()
+        _check(lib().lbm_get_launch(self.h, C.byref(cfg)), "lbm_get_launch")
+        return dict(block=cfg.block, xcd_remap=cfg.xcd_remap, persistent=cfg.persistent,
+                    nontemporal=cfg.nontemporal)
+
+
+class Membrane:
+    """Device copy of a spring / hinge / tether network (inputs.Bodies) for
+    ib_membrane_rest / ib_membrane_forces (run on torch's current stream)."""
+
+    def __init__(self, bodies, device="cuda:0", stream=None):
+        import torch
+
+        from . import inputs
+
+        dev = torch.device(device)
+        n = bodies.n
+        self._keep = []
+
+        def dev_i32(a):
+            t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(dev)
+            self._keep.append(t)
+            return t
+
+        s = IbMembrane()
+        s.n = n
+        if len(bodies.edges):
+            ptr, idx = inputs.csr_neighbours(n, bodies.edges)
+            p, i = dev_i32(ptr), dev_i32(idx)
+            rl = torch.zeros(len(idx), dtype=torch.float64, device=dev)
+            self._keep.append(rl)
+            s.nbr_ptr, s.nbr_idx, s.rest_len = p.data_ptr(), i.data_ptr(), rl.data_ptr()
+        s.k_spring = float(bodies.k_spring)
+        if len(bodies.hinges) and bodies.k_bend != 0.0:
+            hp, hi = inputs.csr_hinges(n, bodies.hinges)
+            hpt, hit, ht = dev_i32(hp), dev_i32(hi), dev_i32(bodies.hinges.reshape(-1))
+            rt = torch.zeros(len(bodies.hinges), dtype=torch.float64, device=dev)
+            self._keep.append(rt)
+            s.hinge_ptr, s.hinge_inc, s.hinges, s.rest_theta = hpt.data_ptr(), hit.data_ptr(), ht.data_ptr(), rt.data_ptr()
+            s.nh = len(bodies.hinges)
+        s.k_bend = float(bodies.k_bend)
+        if bodies.anchors is not None:
+            a = torch.from_numpy(np.ascontiguousarray(bodies.anchors, dtype=np.float64)).to(dev)
+            self._keep.append(a)
+            s.anchors = a.data_ptr()
+        s.k_tether = float(bodies.k_tether)
+        self.struct = s
+        self.n = n
+        st = stream if stream is not None else _stream_ptr(torch, dev)
+        Xr = torch.from_numpy(np.ascontiguousarray(bodies.X_rest, dtype=np.float64)).to(dev)
+        _check(lib().ib_membrane_rest(C.byref(s), _ptr(Xr), st), "ib_membrane_rest")
+        self._keep.append(Xr)
+        self.stream = st
+
+    def forces(self, X, F=None):
+        import torch
+
+        if F is None:
+            F = torch.empty((3, self.n), dtype=torch.float32, device=X.device)
+        _check(lib().ib_membrane_forces(C.byref(self.struct), _ptr(X), _ptr(F), self.stream), "ib_membrane_forces")
+        return F

@@ -1,0 +1,82 @@
+"""The C-ABI library loads and exports every function include/lbm.h declares; host-side
+validation works without a GPU (no compute is launched here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*((?:lbm|ib)_[a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_functions()
+    for must in ["lbm_create", "lbm_step", "ib_spread", "ib_interp", "lbm_moments"]:
+        assert must in names
+    assert len(names) >= 20
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1312_2234_amd import lbm
+
+    L = lbm.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(declared_functions()) <= set(lbm.EXPORTS)
+
+
+def _params(**kw):
+    from paper_1312_2234_amd import lbm
+
+    d = dict(nx=32, ny=32, nz=32, walls=1, tau=0.8)
+    d.update(kw)
+    p = lbm.LbmParams(d["nx"], d["ny"], d["nz"], d["walls"], d["tau"], (C.c_float * 3)(0, 0, 0),
+                      (C.c_float * 3)(0, 0, 0), (C.c_float * 3)(*(d.get("uhi", (0, 0, 0)))))
+    return (lbm.LbmParams * 1)(p)
+
+
+def test_workspace_size_and_validation():
+    from paper_1312_2234_amd import lbm
+
+    L = lbm.lib()
+    ok = L.lbm_workspace_bytes(_params(), 1, 0, 0)
+    assert ok >= 2 * 19 * 32 ** 3 * 4
+    half = L.lbm_workspace_bytes(_params(), 1, 1, 0)
+    assert half < ok and half >= 2 * 19 * 32 ** 3 * 2
+    assert L.lbm_workspace_bytes(_params(tau=0.5), 1, 0, 0) == 0          # tau must exceed 1/2
+    assert L.lbm_workspace_bytes(_params(nx=0), 1, 0, 0) == 0
+    assert L.lbm_workspace_bytes(_params(uhi=(0, 0.1, 0)), 1, 0, 0) == 0  # wall-normal wall speed
+    assert L.lbm_workspace_bytes(_params(), 1, 7, 0) == 0                 # unknown storage
+    assert L.lbm_workspace_bytes(_params(), 1, 0, 1000) > ok              # IB buffers
+
+
+def test_create_rejects_bad_arguments_on_host():
+    from paper_1312_2234_amd import lbm
+
+    L = lbm.lib()
+    h = C.c_void_p()
+    assert L.lbm_create(_params(), 1, 0, 0, 0, None, 0, None, C.byref(h)) == 1       # no workspace
+    assert L.lbm_create(_params(tau=0.4), 1, 0, 0, 0, C.c_void_p(256), 1 << 30, None, C.byref(h)) == 1
+    assert L.lbm_create(_params(), 1, 0, 0, 0, C.c_void_p(256), 16, None, C.byref(h)) == 1  # too small
+    assert L.lbm_create(_params(), 1, 0, 0, 0, C.c_void_p(257), 1 << 30, None, C.byref(h)) == 1  # misaligned
+    assert L.lbm_create(_params(nx=3), 1, 0, 0, 10, C.c_void_p(256), 1 << 30, None, C.byref(h)) == 4  # IB needs nx>=4
+    assert h.value is None
+    assert L.lbm_step(None, 1) == 1 and L.ib_spread(None, 0, None, None) == 1
+    assert L.lbm_status_string(3) == b"HIP error"
+
+
+def test_oracle_builds_and_is_separate():
+    """The oracle is its own gcc-built library; the GPU sources never include it."""
+    from oracle import oracle
+
+    assert os.path.exists(oracle.build(force=False))
+    csrc = os.path.join(ROOT, "paper_1312_2234_amd", "csrc")
+    for f in os.listdir(csrc):
+        assert "oracle" not in open(os.path.join(csrc, f)).read()

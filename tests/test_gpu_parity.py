@@ -1,0 +1,336 @@
+"""GPU (gfx950 HIP, through the C ABI) against the FP64 oracle on the same seeded inputs.
+
+Tolerance for float32 (weight-shifted storage, float32 arithmetic): the maximum relative
+velocity error e_max = max|v_gpu - v_ref| / max|v_ref| <= 1e-5; positions and
+interpolated velocities likewise relative to their own scale.  Lattice sizes include
+ragged ones (not multiples of the 64-cell segment or the 8-cell IB tile).
+"""
+import numpy as np
+import pytest
+
+from paper_1312_2234_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL32 = 1e-5
+
+
+def emax(a, ref):
+    a, ref = np.asarray(a, float), np.asarray(ref, float)
+    return np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300)
+
+
+def T(x, dtype=None):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dtype)).to(DEV)
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+def pair(orc, gpu, ch, kernel="cos", storage="f32", max_nodes=0):
+    o = orc.Lattice(ch.nx, ch.ny, ch.nz, ch.tau, walls=ch.walls, body=ch.body, u_wall_lo=ch.u_wall_lo,
+                    u_wall_hi=ch.u_wall_hi, kernel=kernel)
+    g = gpu.Lattice([ch], storage=storage, kernel=kernel, max_nodes=max_nodes, device=DEV)
+    if ch.init == "shear":
+        o.init(u=o.shear_profile())
+    else:
+        o.init()
+    g.init()
+    return o, g
+
+
+def gpu_fields(g, c=0):
+    drho, v = g.moments_channel(c)
+    return N(drho), N(v)
+
+
+# ----------------------------------------------------------------------------- lattice only
+@pytest.mark.parametrize("dims", [(32, 32, 32), (45, 37, 29)])
+def test_lbm_poiseuille_box(orc, gpu, dims):
+    ch = inputs.Channel(*dims, 0.8, body=(1e-6, 0.0, 0.0))
+    o, g = pair(orc, gpu, ch)
+    o.step(100)
+    g.step(100)
+    rho_o, v_o = o.moments()
+    drho_g, v_g = gpu_fields(g)
+    assert emax(v_g, v_o) <= TOL32
+    assert np.abs(drho_g - (rho_o - 1)).max() < 1e-9
+
+
+def test_lbm_couette_shear_init(orc, gpu):
+    ch = inputs.Channel(40, 24, 16, 1.0, u_wall_hi=(0.05, 0.0, 0.02), u_wall_lo=(-0.01, 0.0, 0.0), init="shear")
+    o, g = pair(orc, gpu, ch)
+    _, v0 = gpu_fields(g)
+    _, vo0 = o.moments()
+    assert emax(v0, vo0) <= TOL32      # the un-streamed initial state pulls back to f_eq(u0)
+    o.step(200)
+    g.step(200)
+    assert emax(gpu_fields(g)[1], o.moments()[1]) <= TOL32
+    lo_g, hi_g = g.wall_stress()
+    lo_o, hi_o = o.wall_stress()
+    assert emax(N(lo_g).reshape(lo_o.shape), lo_o) <= 1e-4
+    assert emax(N(hi_g).reshape(hi_o.shape), hi_o) <= 1e-4
+
+
+def test_lbm_periodic_random_velocity(orc, gpu):
+    rng = np.random.default_rng(11)
+    ch = inputs.Channel(24, 20, 18, 0.7, walls=False, body=(1e-5, -2e-6, 0.0))
+    o, g = pair(orc, gpu, ch)
+    u = 0.02 * rng.standard_normal((3, 18, 20, 24))
+    rho = 1 + 0.01 * rng.standard_normal((18, 20, 24))
+    o.init(rho=rho, u=u)
+    g.init(rho=T(rho.reshape(-1), np.float32), u=T(u.reshape(-1), np.float32))
+    o.step(50)
+    g.step(50)
+    rho_o, v_o = o.moments()
+    drho_g, v_g = gpu_fields(g)
+    assert emax(v_g, v_o) <= TOL32
+    assert np.abs(drho_g - (rho_o - 1)).max() < 1e-6   # input rho rounded to float32
+
+
+def test_mass_conservation_float32(gpu):
+    """Mass changes only by float32 rounding of the stored populations: at most 19 half-ulps
+    of max|g| (~1e-2 here) per cell and step.  A mass source such as the '+ c_s^2 I' reading of
+    Eq. (19) would add 6 (1 - 1/2tau) v.F per cell and step, ~10x more than this bound."""
+    ch = inputs.Channel(64, 48, 40, 0.9, u_wall_hi=(0.05, 0, 0), init="shear", body=(1e-6, 0, 0))
+    g = gpu.Lattice([ch], device=DEV)
+    g.init()
+    m0 = float(N(g.moments()[0]).astype(np.float64).sum())
+    steps = 300
+    g.step(steps)
+    m1 = float(N(g.moments()[0]).astype(np.float64).sum())
+    bound = 19 * 2.0 ** -24 * 1e-2 * ch.cells * steps
+    print("mass drift %.3e (bound %.3e)" % (m1 - m0, bound))
+    assert abs(m1 - m0) < bound
+
+
+# ----------------------------------------------------------------------------- IB in isolation
+@pytest.mark.parametrize("kernel", ["cos", "peskin4"])
+@pytest.mark.parametrize("dims", [(32, 32, 32), (45, 37, 29)])
+def test_spread_matches_oracle(orc, gpu, kernel, dims):
+    """At rest with no body force v = g/2, so the moments expose the spread force field."""
+    rng = np.random.default_rng(12)
+    nx, ny, nz = dims
+    ch = inputs.Channel(nx, ny, nz, 0.8)
+    o, g = pair(orc, gpu, ch, kernel=kernel, max_nodes=500)
+    n = 500
+    X = np.stack([rng.uniform(-3, nx + 3, n), rng.uniform(-0.5, ny - 0.5, n), rng.uniform(-3, nz + 3, n)])
+    X[:, :40] = np.round(X[:, :40])      # nodes exactly on lattice points
+    F = 1e-3 * rng.standard_normal((3, n))
+    F32 = F.astype(np.float32)
+    o.spread(X, F32.astype(np.float64))
+    g.set_nodes(n)
+    g.spread(T(X), T(F32))
+    _, v_g = gpu_fields(g)
+    assert emax(2 * v_g, o.g) <= 2e-6
+    assert g.error_flags() == 0
+
+
+@pytest.mark.parametrize("kernel", ["cos", "peskin4"])
+def test_interp_matches_oracle(orc, gpu, kernel):
+    rng = np.random.default_rng(13)
+    nx, ny, nz = 45, 37, 29
+    ch = inputs.Channel(nx, ny, nz, 0.8, u_wall_lo=(0.01, 0, 0), u_wall_hi=(-0.02, 0, 0.03))
+    o, g = pair(orc, gpu, ch, kernel=kernel, max_nodes=400)
+    u = 0.01 * rng.standard_normal((3, nz, ny, nx))
+    o.init(u=u)
+    g.init(u=T(u.reshape(-1), np.float32))
+    n = 400
+    X = np.stack([rng.uniform(0, nx, n), rng.uniform(-0.5, ny - 0.5, n), rng.uniform(0, nz, n)])
+    F = np.zeros((3, n), np.float32)
+    o.spread(X, F.astype(np.float64))
+    g.set_nodes(n)
+    g.spread(T(X), T(F))
+    U_o = o.interp(X)
+    U_g = N(g.interp(T(X)))
+    assert emax(U_g, U_o) <= TOL32
+    # nodes that moved off the spread footprint are evaluated on the fly
+    X2 = X.copy()
+    X2[0] += 7.3
+    U2_o = o.interp(X2)
+    U2_g = N(g.interp(T(X2)))
+    assert emax(U2_g, U2_o) <= TOL32
+
+
+def test_spread_is_deterministic_and_empty_ok(gpu):
+    rng = np.random.default_rng(14)
+    ch = inputs.Channel(64, 40, 48, 0.8)
+    g = gpu.Lattice([ch], max_nodes=20000, device=DEV)
+    g.init()
+    n = 20000
+    X = T(np.stack([rng.uniform(0, 64, n), rng.uniform(0, 39, n), rng.uniform(0, 48, n)]))
+    F = T(rng.standard_normal((3, n)), np.float32)
+    g.set_nodes(n)
+    g.spread(X, F)
+    a = N(g.moments()[1])
+    g.spread(X, F)
+    b = N(g.moments()[1])
+    assert np.array_equal(a, b)
+    g.set_nodes(0)
+    g.spread(None, None)
+    _, v = g.moments()
+    assert float(N(v).__abs__().max()) == 0.0
+
+
+def test_error_flags(gpu):
+    ch = inputs.Channel(16, 16, 16, 0.8)
+    g = gpu.Lattice([ch], max_nodes=2, device=DEV)
+    g.init()
+    g.set_nodes(2)
+    X = T(np.array([[4.0, 5.0], [40.0, 3.0], [4.0, 5.0]]))
+    F = T(np.array([[1.0, np.inf], [0, 0], [0, 0]]), np.float32)
+    g.spread(X, F)
+    fl = g.error_flags()
+    assert fl & gpu.FLAG_NODE_OUTSIDE and fl & gpu.FLAG_FORCE_NONFINITE
+    assert g.error_flags() == 0
+
+
+# ----------------------------------------------------------------------------- membrane forces
+def test_membrane_forces_match_oracle(orc, gpu):
+    rng = np.random.default_rng(15)
+    b = inputs.platelets(rng, 64, 48, 64, 2, (6.0, 2.0, 6.0), 2562, (8.0, 20.0), 0.005, 1e-4)
+    X = b.X + 0.05 * rng.standard_normal(b.X.shape)
+    om = orc.Membrane(b.X_rest, b.edges, k_spring=b.k_spring, hinges=b.hinges, k_bend=b.k_bend)
+    gm = gpu.Membrane(b, device=DEV)
+    F_o = om.forces(X)
+    F_g = N(gm.forces(T(X)))
+    assert emax(F_g, F_o) <= 1e-6
+    t = inputs.tethered_sphere(rng, (16, 10, 16), 4.0, 642, 0.01, 0.1)
+    om = orc.Membrane(t.X_rest, t.edges, anchors=t.anchors, k_tether=t.k_tether)
+    gm = gpu.Membrane(t, device=DEV)
+    assert emax(N(gm.forces(T(t.X))), om.forces(t.X)) <= 1e-6
+
+
+# ----------------------------------------------------------------------------- coupled steps
+def run_oracle_coupled(orc, ch, kernel, steps):
+    b = ch.bodies
+    o = orc.Lattice(ch.nx, ch.ny, ch.nz, ch.tau, walls=ch.walls, body=ch.body, u_wall_lo=ch.u_wall_lo,
+                    u_wall_hi=ch.u_wall_hi, kernel=kernel)
+    o.init(u=o.shear_profile()) if ch.init == "shear" else o.init()
+    mem = orc.Membrane(b.X_rest, b.edges, k_spring=b.k_spring, hinges=b.hinges, k_bend=b.k_bend,
+                       anchors=b.anchors, k_tether=b.k_tether)
+    X = b.X.copy()
+    for _ in range(steps):
+        F, U = orc.coupled_step(o, mem, X)
+    return o, X, U
+
+
+def run_gpu_coupled(gpu, ch, kernel, steps, graph=False, storage="f32"):
+    import torch
+
+    b = ch.bodies
+    g = gpu.Lattice([ch], storage=storage, kernel=kernel, max_nodes=b.n, device=DEV)
+    g.init()
+    g.set_nodes(b.n)
+    mem = gpu.Membrane(b, device=DEV)
+    X = T(b.X)
+    F = torch.zeros((3, b.n), dtype=torch.float32, device=DEV)
+    U = torch.zeros_like(F)
+    if graph:
+        g.graph_capture(mem, 2, X, F, U)
+        g.graph_launch(steps // 2)
+    else:
+        g.coupled_steps(mem, steps, X, F, U)
+    torch.cuda.synchronize()
+    return g, X, U
+
+
+@pytest.mark.parametrize("kernel", ["peskin4", "cos"])
+def test_coupled_poiseuille_sphere_100_steps(orc, gpu, kernel):
+    """32^3 box, body force 1e-6, tethered 642-node sphere (k = 0.01, N(0, 0.1^2) start), 100 steps."""
+    for seed in (0, 1):
+        ch = inputs.poiseuille_sphere(seed=seed)
+        o, Xo, Uo = run_oracle_coupled(orc, ch, kernel, 100)
+        g, Xg, Ug = run_gpu_coupled(gpu, ch, kernel, 100)
+        assert emax(gpu_fields(g)[1], o.moments()[1]) <= TOL32
+        assert emax(N(Ug), Uo) <= TOL32
+        assert np.abs(N(Xg) - Xo).max() <= TOL32 * np.abs(Xo - ch.bodies.X).max()
+        assert g.error_flags() == 0
+
+
+def test_graph_replay_matches_eager(gpu):
+    ch = inputs.poiseuille_sphere(seed=2)
+    g1, X1, U1 = run_gpu_coupled(gpu, ch, "peskin4", 20)
+    g2, X2, U2 = run_gpu_coupled(gpu, ch, "peskin4", 20, graph=True)
+    assert np.array_equal(N(X1), N(X2)) and np.array_equal(N(U1), N(U2))
+    assert np.array_equal(N(g1.moments()[1]), N(g2.moments()[1]))
+
+
+def test_coupled_shear_platelets_crop(orc, gpu):
+    """Production-shear setup at reduced size: 96x48x64, 3 platelets of 642 nodes, 30 steps."""
+    ch = inputs.shear_platelets(seed=5, nx=96, ny=48, nz=64, count=3, nodes=642)
+    o, Xo, Uo = run_oracle_coupled(orc, ch, "cos", 30)
+    g, Xg, Ug = run_gpu_coupled(gpu, ch, "cos", 30)
+    assert emax(gpu_fields(g)[1], o.moments()[1]) <= TOL32
+    assert emax(N(Ug), Uo) <= TOL32
+    lo_g, _ = g.wall_stress()
+    lo_o, _ = o.wall_stress()
+    assert emax(N(lo_g).reshape(lo_o.shape), lo_o) <= 1e-4
+
+
+# ----------------------------------------------------------------------------- state, channels
+def test_populations_roundtrip_and_resume(orc, gpu):
+    import torch
+
+    ch = inputs.Channel(33, 20, 17, 0.85, u_wall_hi=(0.03, 0, 0), init="shear")
+    o, g = pair(orc, gpu, ch)
+    o.step(7)
+    g.step(7)
+    f_g = N(g.populations()).reshape(19, 17, 20, 33)
+    ulp = 2.0 ** -25  # float32 ulp of f near 1/3 is 2^-25 * 2 = 3e-8
+    assert np.abs(f_g - o.f).max() < 2 * ulp * 2
+    g.set_populations(T(o.f.reshape(-1), np.float32))
+    assert np.abs(N(g.populations()).reshape(o.f.shape) - o.f).max() < 2 * ulp * 2
+    st = g.get_state().clone()
+    g.step(5)
+    a = N(g.moments()[1])
+    g.set_state(st)
+    g.step(5)
+    torch.cuda.synchronize()
+    assert np.array_equal(a, N(g.moments()[1]))
+
+
+def test_multichannel_batch(orc, gpu):
+    chans = [inputs.Channel(48, 32, 32, 0.75, u_wall_hi=(0.02, 0, 0), init="shear"),
+             inputs.Channel(37, 21, 19, 1.1, body=(2e-6, 0, 0)),
+             inputs.Channel(64, 48, 48, 0.95, u_wall_hi=(0.04, 0, 0.01), init="shear")]
+    g = gpu.Lattice(chans, device=DEV)
+    g.init()
+    g.step(40)
+    for c, ch in enumerate(chans):
+        o = orc.Lattice(ch.nx, ch.ny, ch.nz, ch.tau, walls=ch.walls, body=ch.body, u_wall_lo=ch.u_wall_lo,
+                        u_wall_hi=ch.u_wall_hi)
+        o.init(u=o.shear_profile()) if ch.init == "shear" else o.init()
+        o.step(40)
+        assert emax(gpu_fields(g, c)[1], o.moments()[1]) <= TOL32
+
+
+@pytest.mark.parametrize("launch", [dict(block=64, xcd_remap=0), dict(block=1024, xcd_remap=1),
+                                    dict(block=256, persistent=97), dict(block=512, nontemporal=1)])
+def test_launch_shapes_agree(gpu, launch):
+    ch = inputs.Channel(45, 37, 29, 0.8, u_wall_hi=(0.05, 0, 0), init="shear")
+    ref = gpu.Lattice([ch], device=DEV)
+    ref.init()
+    ref.step(10)
+    g = gpu.Lattice([ch], device=DEV)
+    g.set_launch(**{**dict(block=256, xcd_remap=1, persistent=0, nontemporal=0), **launch})
+    g.init()
+    g.step(10)
+    assert np.array_equal(N(ref.moments()[1]), N(g.moments()[1]))
+
+
+# ----------------------------------------------------------------------------- 16-bit storage
+@pytest.mark.parametrize("storage,bound", [("f16", 2e-3), ("bf16", 2e-2)])
+def test_half_storage_error_bounded(orc, gpu, storage, bound):
+    """Weight-shifted 16-bit storage, float32 arithmetic: error against the FP64 oracle on a
+    sheared channel (reported, loosely bounded)."""
+    ch = inputs.Channel(64, 32, 32, 1.0, u_wall_hi=(0.05, 0, 0), init="shear")
+    o, g = pair(orc, gpu, ch, storage=storage)
+    o.step(200)
+    g.step(200)
+    e = emax(gpu_fields(g)[1], o.moments()[1])
+    print("%s e_max after 200 steps: %.3e" % (storage, e))
+    assert e <= bound
