@@ -79,6 +79,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lbm-only-steps", type=int, default=200)
+    ap.add_argument("--tune", action="store_true", help="re-time the lattice kernel's launch shapes")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run plain device copies of the lattice kernel's byte count (calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
@@ -94,6 +98,10 @@ def main():
     nodes = sum(c.bodies.n for c in channels)
     cells = sum(c.cells for c in channels)
     lat = lbm.Lattice(channels, storage=args.storage, kernel=args.kernel, max_nodes=nodes, device=dev)
+    lat.init()
+    from paper_1312_2234_amd import tune
+
+    launch, _ = tune.apply_cached_or_tune(lat, retune=args.tune)
     lat.init()
     b = channels[0].bodies
     lat.set_nodes(b.n)
@@ -130,6 +138,7 @@ def main():
     ms_lbm = e0.elapsed_time(e1) / args.lbm_only_steps
     bytes_launch = BYTES_PER_CELL[args.storage] * cells
     achieved = bytes_launch / (ms_lbm * 1e-3)
+    ceiling, ceiling_cfg = tune.copy_ceiling(torch, lat.device, bytes_launch // 2)
 
     out = {
         "metric": METRIC,
@@ -152,8 +161,19 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_step (lattice step)", "achieved": round(achieved / 1e9, 1),
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
                      "traffic": None, "bytes_per_launch": bytes_launch,
-                     "avg_launch_us": round(ms_lbm * 1e3, 2)},
+                     "avg_launch_us": round(ms_lbm * 1e3, 2),
+                     "copy_ceiling_GBps": round(ceiling / 1e9, 1),
+                     "frac_of_copy_ceiling": round(achieved / ceiling, 4)},
     }
+    if args.copy_probe:
+        half = bytes_launch // 2  # read half, write half: the same bytes as one lattice launch
+        src = torch.empty(half, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes_read"] = half
+        del src, dst
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         del lat
         out["cpu_baseline"] = cpu_baseline(channels, args.kernel, args.cpu_steps)

@@ -65,7 +65,7 @@ typedef enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2 } lbm_st
 typedef enum { IB_PHI_COS4 = 0, IB_PHI_PESKIN4 = 1 } ib_kernel;
 
 /* Error bits reported by lbm_error_flags(). */
-#define LBM_FLAG_NODE_OUTSIDE 0x1u  /* an IB node's stencil base fell outside y in [-2, ny] */
+#define LBM_FLAG_NODE_OUTSIDE 0x1u  /* an IB node's y fell outside [-1, ny) (or was not finite) */
 #define LBM_FLAG_LIST_OVERFLOW 0x2u /* IB tile lists exceeded their capacity (contributions lost) */
 #define LBM_FLAG_FORCE_NONFINITE 0x4u /* a Lagrangian force was Inf/NaN (force field set to NaN) */
 #define LBM_FLAG_CLOSURE_FALLBACK 0x8u /* the learned closure fell back to plain BGK at some node */
@@ -163,8 +163,9 @@ const char* lbm_status_string(lbm_status s);
  *   bending  stand-in for Eq. (6)-(10): E = k_bend sum_hinges (1 - cos(theta - theta0)),
  *            theta the signed dihedral angle of the two triangles of a hinge;
  *   tethers  U = k_tether/2 |X - A|^2.
- * Connectivity is CSR so that every node gathers its own force (no atomics).  All arrays
- * are device memory; rest_len / rest_theta are filled by ib_membrane_rest(). */
+ * Connectivity is CSR so that every node gathers its own force (no atomics): a first pass
+ * evaluates every hinge once into hinge_force, a second gathers per node.  All arrays are
+ * device memory; rest_len / rest_theta are filled by ib_membrane_rest(). */
 typedef struct {
     int64_t n;                 /* nodes */
     const int32_t* nbr_ptr;    /* [n+1] CSR over spring neighbours (both directions) */
@@ -175,13 +176,17 @@ typedef struct {
     const int32_t* hinge_inc;  /* [nnz_h] (hinge id << 2) | role, role = slot 0..3 in the hinge */
     const int32_t* hinges;     /* [nh][4] (x0, x1, x2, x3): triangles (x0,x1,x2), (x3,x2,x1) */
     double* rest_theta;        /* [nh] */
+    int32_t* hinge_slot;       /* [nh][4] scratch: position of (hinge, role) in hinge_inc (set by
+                                  ib_membrane_rest) */
+    double* hinge_force;       /* [nh*4][3] scratch: bending force of each incidence, CSR order */
     int64_t nh;
     double k_bend;
     const double* anchors;     /* [3][n] tether anchors, or NULL */
     double k_tether;
 } ib_membrane;
 
-/* Measure rest lengths and rest dihedral angles on X_rest ([3][n] float64). */
+/* Measure rest lengths and rest dihedral angles on X_rest ([3][n] float64); build
+ * hinge_slot.  Requires every hinge vertex's incidences in hinge_ptr / hinge_inc. */
 lbm_status ib_membrane_rest(const ib_membrane* m /*host*/, const double* X_rest, void* stream);
 /* F = -grad(E)(X), float64 arithmetic, float32 output [3][n]. */
 lbm_status ib_membrane_forces(const ib_membrane* m /*host*/, const double* X, float* F, void* stream);
@@ -207,10 +212,19 @@ typedef struct {
     int32_t xcd_remap;   /* 1 = map consecutive lattice segments to the same XCD */
     int32_t persistent;  /* 0 = one workgroup per segment; >0 = that many resident workgroups looping */
     int32_t nontemporal; /* 1 = non-temporal stores of the new populations */
+    int32_t vec;         /* cells per lane: 0/1 scalar step; 2 or 4 = vector step (aligned V-wide
+                            accesses, 256-thread workgroups), used when every channel has
+                            nx % V == 0 and nx*ny*nz % (64 V) == 0, else the scalar step runs */
 } lbm_launch;
 
 lbm_status lbm_set_launch(lbm_ctx* ctx, const lbm_launch* cfg /*host*/);
 lbm_status lbm_get_launch(const lbm_ctx* ctx, lbm_launch* cfg /*host*/);
+
+/* Measurement helper, not part of the method: copy `bytes` (multiple of 16) from src to dst
+ * with 16-byte accesses (variant 0: plain stores, 1: non-temporal stores), `grid`
+ * workgroups of 256 threads (0: one 16-byte element per thread).  Gives the practical HBM
+ * ceiling a lattice step is compared with. */
+lbm_status lbm_stream_copy(const void* src, void* dst, size_t bytes, int32_t variant, int64_t grid, void* stream);
 
 #ifdef __cplusplus
 }

@@ -62,12 +62,14 @@ Layout layout_of(const lbm_params* p, int32_t nch, lbm_storage st, int64_t max_n
     };
     L.chan = take(sizeof(Chan) * nch);
     L.seg_ch = take(sizeof(int32_t) * sz.segs);
-    L.popA = take(elem_size(st) * Q * sz.cells);
-    L.popB = take(elem_size(st) * Q * sz.cells);
+    L.popA = take(elem_size(st) * Q * 64 * sz.segs);
+    L.popB = take(elem_size(st) * Q * 64 * sz.segs);
     L.flags = take(64);
     if (max_nodes > 0) {
         L.node_ch = take(sizeof(int32_t) * max_nodes);
         L.rec = take(sizeof(float) * 20 * max_nodes);
+        L.rank = take(sizeof(int32_t) * 27 * max_nodes);
+        L.blkbase = take(sizeof(int32_t) * 2048 * ((max_nodes + 255) / 256));
         for (int k = 0; k < 2; ++k) {
             L.sets[k][0] = take(sizeof(int32_t) * sz.tiles);           // cnt
             L.sets[k][1] = take(sizeof(int32_t) * sz.tiles);           // tile_slot
@@ -124,6 +126,9 @@ IbArgs ib_args(lbm_ctx* c, int set) {
     a.flags = c->d_flags;
     a.pop = c->pop[c->cur];
     a.kernel = (int32_t)c->kernel;
+    a.nch = c->nch;
+    a.rank = c->d_rank;
+    a.blkbase = c->d_blkbase;
     return a;
 }
 
@@ -210,6 +215,8 @@ lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib
             c->set[k].hdr = (IbHdr*)(c->ws + L.sets[k][6]);
         }
         c->d_list = (int32_t*)(c->ws + L.list);
+        c->d_rank = (int32_t*)(c->ws + L.rank);
+        c->d_blkbase = (int32_t*)(c->ws + L.blkbase);
         c->d_force = (float*)(c->ws + L.force);
         c->d_vel = (float*)(c->ws + L.vel);
     }
@@ -244,7 +251,7 @@ lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib
         }
         const int64_t ns = (d.ncell + 63) / 64;
         for (int64_t s = 0; s < ns; ++s) seg_ch[seg_off + s] = k;
-        pop_off += (int64_t)Q * d.ncell;
+        pop_off += (int64_t)Q * 64 * ns;
         cell_off += d.ncell;
         seg_off += ns;
         tile_off += (int64_t)d.tnx * d.tny * d.tnz;
@@ -324,7 +331,7 @@ lbm_status lbm_set_populations(lbm_ctx* c, const float* f) {
     return hip_ok(launch_lattice(c, LK_SETF, a));
 }
 
-size_t lbm_state_bytes(const lbm_ctx* c) { return c ? (size_t)Q * c->total_cells * c->esize : 0; }
+size_t lbm_state_bytes(const lbm_ctx* c) { return c ? (size_t)Q * 64 * c->total_segs * c->esize : 0; }
 
 lbm_status lbm_get_state(lbm_ctx* c, void* dst) {
     if (!c || !dst) return LBM_ERR_ARG;
@@ -423,13 +430,16 @@ lbm_status ib_membrane_rest(const ib_membrane* m, const double* X_rest, void* st
     if (!m || m->n < 0 || (m->n > 0 && !X_rest)) return LBM_ERR_ARG;
     if (m->nbr_ptr && (!m->nbr_idx || !m->rest_len)) return LBM_ERR_ARG;
     if (m->nh > 0 && (!m->hinges || !m->rest_theta)) return LBM_ERR_ARG;
+    if (m->hinge_ptr && m->nh > 0 && (!m->hinge_inc || !m->hinge_slot)) return LBM_ERR_ARG;
     return hip_ok(launch_membrane_rest(m, X_rest, (hipStream_t)stream));
 }
 
 lbm_status ib_membrane_forces(const ib_membrane* m, const double* X, float* F, void* stream) {
     if (!m || m->n < 0 || (m->n > 0 && (!X || !F))) return LBM_ERR_ARG;
     if (m->nbr_ptr && (!m->nbr_idx || !m->rest_len)) return LBM_ERR_ARG;
-    if (m->hinge_ptr && (!m->hinge_inc || !m->hinges || !m->rest_theta)) return LBM_ERR_ARG;
+    if (m->hinge_ptr && (!m->hinge_inc || !m->hinges || !m->rest_theta ||
+                         (m->nh > 0 && (!m->hinge_force || !m->hinge_slot))))
+        return LBM_ERR_ARG;
     return hip_ok(launch_membrane_forces(m, X, F, (hipStream_t)stream));
 }
 
@@ -511,7 +521,7 @@ lbm_status lbm_set_launch(lbm_ctx* c, const lbm_launch* cfg) {
     const int b = cfg->block;
     if (b != 64 && b != 128 && b != 256 && b != 512 && b != 1024) return LBM_ERR_ARG;
     if (cfg->persistent < 0 || (cfg->xcd_remap != 0 && cfg->xcd_remap != 1) ||
-        (cfg->nontemporal != 0 && cfg->nontemporal != 1))
+        (cfg->nontemporal != 0 && cfg->nontemporal != 1) || cfg->vec < 0 || cfg->vec > 4 || cfg->vec == 3)
         return LBM_ERR_ARG;
     c->launch = *cfg;
     return LBM_OK;
@@ -521,6 +531,12 @@ lbm_status lbm_get_launch(const lbm_ctx* c, lbm_launch* cfg) {
     if (!c || !cfg) return LBM_ERR_ARG;
     *cfg = c->launch;
     return LBM_OK;
+}
+
+lbm_status lbm_stream_copy(const void* src, void* dst, size_t bytes, int32_t variant, int64_t grid, void* stream) {
+    if (!src || !dst || (bytes & 15) || variant < 0 || variant > 1 || grid < 0) return LBM_ERR_ARG;
+    if (((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return LBM_ERR_ARG;
+    return hip_ok(launch_copy16((hipStream_t)stream, src, dst, (int64_t)bytes, variant, grid));
 }
 
 }  // extern "C"

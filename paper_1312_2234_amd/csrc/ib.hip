@@ -97,69 +97,145 @@ __device__ __forceinline__ void stencil_cells(const Chan& ch, int bx, int by, in
 }
 
 // ---------------------------------------------------------------- bin
-__global__ void __launch_bounds__(256) k_ib_bin(IbArgs a) {
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= a.n) return;
-    const int c = a.node_ch[m];
-    const Chan& ch = a.chan[c];
-    float* r = a.rec + m * REC;
-    float w[3][4];
-    int b[3];
-    bool bad = false;
-    for (int d = 0; d < 3; ++d) {
-        const double X = a.X[d * a.n + m];
-        const int dim = d == 0 ? ch.nx : (d == 1 ? ch.ny : ch.nz);
-        bool finite = isfinite(X) && fabs(X) < 1e9;
-        int64_t base = finite ? ib_weights(a.kernel, X, w[d]) : 0;
-        if (!finite) {
-            bad = true;
-            w[d][0] = w[d][1] = w[d][2] = w[d][3] = 0.0f;
-        }
-        if (d == 1 && ch.walls) {
-            if (base < -2 || base > ch.ny - 2) bad = true;  // node outside y in [-1, ny)
-            if (base < -4) base = -4;
-            if (base > ch.ny) base = ch.ny;
-            b[d] = (int)base;
-        } else {
-            b[d] = wrapi(base, dim);
-        }
+// One thread per node, 256 nodes per block.  Tile counts are first aggregated per block in
+// an LDS hash (tile id -> count), then added to the global counter with one atomic per
+// (block, tile); a node's rank inside a tile's list is the block's base (kept per hash entry
+// in `blkbase`) plus its rank inside the block (kept packed in `rank`).  With nodes numbered
+// along the surface a block touches a few tiles, so global atomics drop from one per
+// (node, tile) to a few per block.
+constexpr int HS = 2048;   // hash entries per block
+constexpr int MAXT = 27;   // most tiles a 4x4x4 stencil can touch
+
+__device__ __forceinline__ int chan_of_tile(const Chan* chan, int nch, int64_t T) {
+    int lo = 0, hi = nch - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (chan[mid].tile_off <= T) lo = mid; else hi = mid - 1;
     }
-    if (bad) atomicOr(a.flags, LBM_FLAG_NODE_OUTSIDE);
-    r[0] = __int_as_float(b[0]);
-    r[1] = __int_as_float(b[1]);
-    r[2] = __int_as_float(b[2]);
-    r[3] = __int_as_float(c);
-    float fm = 0.0f;
-    for (int k = 0; k < 4; ++k) {
-        r[4 + k] = w[0][k];
-        r[8 + k] = w[1][k];
-        r[12 + k] = w[2][k];
-    }
-    for (int d = 0; d < 3; ++d) {
-        const float F = a.F[d * a.n + m];
-        r[16 + d] = F;
-        fm = fmaxf(fm, fabsf(F));
-        if (!isfinite(F)) fm = __uint_as_float(0x7f800000u);
-    }
-    atomicMax(&a.set.hdr->fmax_bits, __float_as_uint(fm));
+    return lo;
+}
+
+__device__ __forceinline__ void append_flagged(const IbArgs& a, int64_t T) {
+    const int slot = atomicAdd(&a.set.hdr->nflag, 1);
+    a.set.flag_list[slot] = (int32_t)T;
+    a.set.flag_ch[slot] = chan_of_tile(a.chan, a.nch, T);
+}
+
+// Tiles touched by the stencil of a node, in a fixed order (z outer, x inner).
+template <class F>
+__device__ __forceinline__ void for_tiles(const Chan& ch, int bx, int by, int bz, F f) {
     Stencil s;
-    stencil_cells(ch, b[0], b[1], b[2], s);
+    stencil_cells(ch, bx, by, bz, s);
     bool all[4] = {true, true, true, true};
     int tx[4], ty[4], tz[4];
     const int nxt = distinct_tiles(s.x, all, tx);
     const int nyt = distinct_tiles(s.y, s.yok, ty);
     const int nzt = distinct_tiles(s.z, all, tz);
+    int q = 0;
     for (int k = 0; k < nzt; ++k)
         for (int j = 0; j < nyt; ++j)
-            for (int i = 0; i < nxt; ++i) {
-                const int64_t T = ch.tile_off + tx[i] + (int64_t)ch.tnx * (ty[j] + (int64_t)ch.tny * tz[k]);
-                const int old = atomicAdd(&a.set.cnt[T], 1);
-                if (old == 0) {
-                    const int slot = atomicAdd(&a.set.hdr->nflag, 1);
-                    a.set.flag_list[slot] = (int32_t)T;
-                    a.set.flag_ch[slot] = c;
-                }
+            for (int i = 0; i < nxt; ++i)
+                f(q++, ch.tile_off + tx[i] + (int64_t)ch.tnx * (ty[j] + (int64_t)ch.tny * tz[k]));
+}
+
+__global__ void __launch_bounds__(256) k_ib_bin(IbArgs a) {
+    __shared__ int hkey[HS];
+    __shared__ int hcnt[HS];
+    __shared__ float wmax[4];
+    for (int e = threadIdx.x; e < HS; e += blockDim.x) {
+        hkey[e] = -1;
+        hcnt[e] = 0;
+    }
+    __syncthreads();
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float fm = 0.0f;
+    if (m < a.n) {
+        const int c = a.node_ch[m];
+        const Chan& ch = a.chan[c];
+        float* r = a.rec + m * REC;
+        float w[3][4];
+        int b[3];
+        bool bad = false;
+        for (int d = 0; d < 3; ++d) {
+            const double X = a.X[d * a.n + m];
+            const int dim = d == 0 ? ch.nx : (d == 1 ? ch.ny : ch.nz);
+            const bool finite = isfinite(X) && fabs(X) < 1e9;
+            int64_t base = finite ? ib_weights(a.kernel, X, w[d]) : 0;
+            if (!finite) {
+                bad = true;
+                w[d][0] = w[d][1] = w[d][2] = w[d][3] = 0.0f;
             }
+            if (d == 1 && ch.walls) {
+                if (base < -2 || base > ch.ny - 2) bad = true;  // node outside y in [-1, ny)
+                if (base < -4) base = -4;
+                if (base > ch.ny) base = ch.ny;
+                b[d] = (int)base;
+            } else {
+                b[d] = wrapi(base, dim);
+            }
+        }
+        if (bad) atomicOr(a.flags, LBM_FLAG_NODE_OUTSIDE);
+        r[0] = __int_as_float(b[0]);
+        r[1] = __int_as_float(b[1]);
+        r[2] = __int_as_float(b[2]);
+        r[3] = __int_as_float(c);
+        for (int k = 0; k < 4; ++k) {
+            r[4 + k] = w[0][k];
+            r[8 + k] = w[1][k];
+            r[12 + k] = w[2][k];
+        }
+        for (int d = 0; d < 3; ++d) {
+            const float F = a.F[d * a.n + m];
+            r[16 + d] = F;
+            fm = fmaxf(fm, fabsf(F));
+            if (!isfinite(F)) fm = __uint_as_float(0x7f800000u);
+        }
+        int32_t* rk = a.rank + m * MAXT;
+        for_tiles(ch, b[0], b[1], b[2], [&](int q, int64_t T) {
+            int h = (int)(((uint32_t)T * 2654435761u) >> 21) & (HS - 1);
+            int packed = INT32_MIN;
+            for (int probe = 0; probe < 64; ++probe) {
+                const int old = atomicCAS(&hkey[h], -1, (int)T);
+                if (old == -1 || old == (int)T) {
+                    packed = (h << 16) | atomicAdd(&hcnt[h], 1);
+                    break;
+                }
+                h = (h + 1) & (HS - 1);
+            }
+            if (packed == INT32_MIN) {  // block table full: count this one directly
+                const int rr = atomicAdd(&a.set.cnt[T], 1);
+                if (rr == 0) append_flagged(a, T);
+                packed = -(rr + 1);
+            }
+            rk[q] = packed;
+        });
+    }
+    // block maximum of |F| (NaN/Inf bits compare above all finite values)
+    uint32_t ub = __float_as_uint(fm);
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = __shfl_xor(ub, d, 64);
+        ub = o > ub ? o : ub;
+    }
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = __uint_as_float(ub);
+    __syncthreads();
+    int32_t* bb = a.blkbase + (int64_t)blockIdx.x * HS;
+    for (int e = threadIdx.x; e < HS; e += blockDim.x) {
+        const int T = hkey[e];
+        int base = 0;
+        if (T >= 0) {
+            base = atomicAdd(&a.set.cnt[T], hcnt[e]);
+            if (base == 0) append_flagged(a, T);
+        }
+        bb[e] = base;
+    }
+    if (threadIdx.x == 0) {
+        uint32_t mx = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+            const uint32_t v = __float_as_uint(wmax[k]);
+            mx = v > mx ? v : mx;
+        }
+        atomicMax(&a.set.hdr->fmax_bits, mx);
+    }
 }
 
 // ---------------------------------------------------------------- scan (one workgroup)
@@ -183,7 +259,6 @@ __global__ void __launch_bounds__(1024) k_ib_scan(IbArgs a) {
         const int T = a.other.flag_list[k];
         a.other.cnt[T] = 0;
         a.other.tile_slot[T] = -1;
-        a.other.fill[k] = 0;
     }
     const int nf = a.set.hdr->nflag;
     if (tid == 0) carry = 0;
@@ -235,45 +310,46 @@ __global__ void __launch_bounds__(1024) k_ib_scan(IbArgs a) {
     }
 }
 
-// ---------------------------------------------------------------- scatter
+// ---------------------------------------------------------------- scatter (no atomics)
 __global__ void __launch_bounds__(256) k_ib_scatter(IbArgs a) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= a.n) return;
     const float* r = a.rec + m * REC;
-    const int c = __float_as_int(r[3]);
-    const Chan& ch = a.chan[c];
-    Stencil s;
-    stencil_cells(ch, __float_as_int(r[0]), __float_as_int(r[1]), __float_as_int(r[2]), s);
-    bool all[4] = {true, true, true, true};
-    int tx[4], ty[4], tz[4];
-    const int nxt = distinct_tiles(s.x, all, tx);
-    const int nyt = distinct_tiles(s.y, s.yok, ty);
-    const int nzt = distinct_tiles(s.z, all, tz);
-    for (int k = 0; k < nzt; ++k)
-        for (int j = 0; j < nyt; ++j)
-            for (int i = 0; i < nxt; ++i) {
-                const int64_t T = ch.tile_off + tx[i] + (int64_t)ch.tnx * (ty[j] + (int64_t)ch.tny * tz[k]);
-                const int slot = a.set.tile_slot[T];
-                const int64_t pos = (int64_t)a.set.slot_off[slot] + atomicAdd(&a.set.fill[slot], 1);
-                if (pos < a.list_cap) a.list[pos] = (int32_t)m;
-            }
+    const Chan& ch = a.chan[__float_as_int(r[3])];
+    const int32_t* rk = a.rank + m * MAXT;
+    const int32_t* bb = a.blkbase + (m >> 8) * HS;
+    for_tiles(ch, __float_as_int(r[0]), __float_as_int(r[1]), __float_as_int(r[2]), [&](int q, int64_t T) {
+        const int packed = rk[q];
+        const int rr = packed >= 0 ? bb[packed >> 16] + (packed & 0xffff) : -packed - 1;
+        const int slot = a.set.tile_slot[T];
+        const int64_t pos = (int64_t)a.set.slot_off[slot] + rr;
+        if (pos < a.list_cap) a.list[pos] = (int32_t)m;
+    });
 }
 
 // ---------------------------------------------------------------- spread (LDS, fixed point)
+// Work item = (flagged tile, one of its eight 4x4x4 sub-tiles): the tile's node list is
+// scanned by all threads, each node adding its stencil points that fall in the sub-tile.
 __global__ void __launch_bounds__(256) k_ib_spread(IbArgs a) {
-    __shared__ unsigned long long acc[3 * TILE_CELLS];
+    __shared__ unsigned long long acc[3 * 64];
     const int nf = a.set.hdr->nflag;
     const int sexp = a.set.hdr->scale_exp;
     const bool nonfinite = a.set.hdr->nonfinite != 0;
     const double scale = ldexp(1.0, sexp), inv = ldexp(1.0, -sexp);
-    for (int slot = blockIdx.x; slot < nf; slot += gridDim.x) {
-        for (int k = threadIdx.x; k < 3 * TILE_CELLS; k += blockDim.x) acc[k] = 0ull;
+    // the eight sub-tiles of a tile go to workgroups dealt to the same XCD (the dispatcher
+    // deals workgroups round-robin over 8 XCDs), so the tile's node records stay in one L2
+    const int b = blockIdx.x;
+    const int first = (b & ~63) | ((b & 7) << 3) | ((b >> 3) & 7);
+    for (int wi = first; wi < nf * 8; wi += gridDim.x) {
+        const int slot = wi >> 3, sub = wi & 7;
+        for (int k = threadIdx.x; k < 3 * 64; k += blockDim.x) acc[k] = 0ull;
         __syncthreads();
         const int T = a.set.flag_list[slot];
         const Chan& ch = a.chan[a.set.flag_ch[slot]];
         const int t = (int)(T - ch.tile_off);
-        const int tx = t % ch.tnx, ty = (t / ch.tnx) % ch.tny, tz = t / (ch.tnx * ch.tny);
-        const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
+        const int sx = (t % ch.tnx) * TILE + 4 * (sub & 1);
+        const int sy = ((t / ch.tnx) % ch.tny) * TILE + 4 * ((sub >> 1) & 1);
+        const int sz = (t / (ch.tnx * ch.tny)) * TILE + 4 * (sub >> 2);
         int64_t beg = a.set.slot_off[slot], end = a.set.slot_off[slot + 1];
         if (end > a.list_cap) end = a.list_cap;
         for (int64_t k = beg + threadIdx.x; k < end; k += blockDim.x) {
@@ -281,33 +357,39 @@ __global__ void __launch_bounds__(256) k_ib_spread(IbArgs a) {
             const float* r = a.rec + m * REC;
             Stencil s;
             stencil_cells(ch, __float_as_int(r[0]), __float_as_int(r[1]), __float_as_int(r[2]), s);
-            float w[12], F[3];
-            for (int q = 0; q < 12; ++q) w[q] = r[4 + q];
-            F[0] = r[16];
-            F[1] = r[17];
-            F[2] = r[18];
-            for (int cz4 = 0; cz4 < 4; ++cz4) {
-                if ((s.z[cz4] >> 3) != tz) continue;
-                for (int cy4 = 0; cy4 < 4; ++cy4) {
-                    if (!s.yok[cy4] || (s.y[cy4] >> 3) != ty) continue;
-                    const float wyz = w[4 + cy4] * w[8 + cz4];
-                    for (int cx4 = 0; cx4 < 4; ++cx4) {
-                        if ((s.x[cx4] >> 3) != tx) continue;
-                        const float ww = w[cx4] * wyz;
-                        const int loc = ((s.z[cz4] - oz) << 6) | ((s.y[cy4] - oy) << 3) | (s.x[cx4] - ox);
+            uint32_t mx = 0, my = 0, mz = 0;
 #pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            const long long q = (long long)rint((double)(ww * F[d]) * scale);
-                            atomicAdd(&acc[d * TILE_CELLS + loc], (unsigned long long)q);
-                        }
+            for (int q = 0; q < 4; ++q) {
+                mx |= ((unsigned)(s.x[q] - sx) < 4u) << q;
+                my |= (s.yok[q] && (unsigned)(s.y[q] - sy) < 4u) << q;
+                mz |= ((unsigned)(s.z[q] - sz) < 4u) << q;
+            }
+            if (!mx || !my || !mz) continue;
+            const float F0 = r[16], F1 = r[17], F2 = r[18];
+            for (int cz4 = 0; cz4 < 4; ++cz4) {
+                if (!((mz >> cz4) & 1)) continue;
+                for (int cy4 = 0; cy4 < 4; ++cy4) {
+                    if (!((my >> cy4) & 1)) continue;
+                    const float wyz = r[8 + cy4] * r[12 + cz4];
+                    for (int cx4 = 0; cx4 < 4; ++cx4) {
+                        if (!((mx >> cx4) & 1)) continue;
+                        const float ww = r[4 + cx4] * wyz;
+                        const int loc = ((s.z[cz4] - sz) << 4) | ((s.y[cy4] - sy) << 2) | (s.x[cx4] - sx);
+                        atomicAdd(&acc[loc], (unsigned long long)(long long)rint((double)(ww * F0) * scale));
+                        atomicAdd(&acc[64 + loc], (unsigned long long)(long long)rint((double)(ww * F1) * scale));
+                        atomicAdd(&acc[128 + loc], (unsigned long long)(long long)rint((double)(ww * F2) * scale));
                     }
                 }
             }
         }
         __syncthreads();
         float* out = a.force + (int64_t)slot * (3 * TILE_CELLS);
-        for (int k = threadIdx.x; k < 3 * TILE_CELLS; k += blockDim.x)
-            out[k] = nonfinite ? __builtin_nanf("") : (float)((double)(long long)acc[k] * inv);
+        for (int k = threadIdx.x; k < 3 * 64; k += blockDim.x) {
+            const int d = k >> 6, l = k & 63;
+            const int lx = (sx & 7) + (l & 3), ly = (sy & 7) + ((l >> 2) & 3), lz = (sz & 7) + (l >> 4);
+            out[d * TILE_CELLS + ((lz << 6) | (ly << 3) | lx)] =
+                nonfinite ? __builtin_nanf("") : (float)((double)(long long)acc[k] * inv);
+        }
         __syncthreads();
     }
 }
@@ -317,8 +399,8 @@ hipError_t launch_ib_spread(lbm_ctx* c, const IbArgs& a) {
     if (a.n > 0) k_ib_bin<<<dim3(nb), dim3(256), 0, c->stream>>>(a);
     k_ib_scan<<<dim3(1), dim3(1024), 0, c->stream>>>(a);
     if (a.n > 0) k_ib_scatter<<<dim3(nb), dim3(256), 0, c->stream>>>(a);
-    int64_t g = c->max_slots < 4096 ? c->max_slots : 4096;
-    if (g < 1) g = 1;
+    int64_t g = 8 * c->max_slots < 8192 ? 8 * c->max_slots : 8192;
+    g = (g + 63) & ~int64_t(63);  // whole groups of 64 for the XCD-aware mapping
     k_ib_spread<<<dim3((unsigned)g), dim3(256), 0, c->stream>>>(a);
     return hipGetLastError();
 }
@@ -327,7 +409,7 @@ hipError_t launch_ib_spread(lbm_ctx* c, const IbArgs& a) {
 // Fluid velocity of the current state, v = (j + (F_body + g)/2)/rho (Eq. (18) and the
 // shift under Eq. (19)), on every cell of every flagged tile.
 template <class St>
-__global__ void __launch_bounds__(256) k_ib_vel(IbArgs a) {
+__global__ void __launch_bounds__(512) k_ib_vel(IbArgs a) {
     using T = typename St::T;
     const int nf = a.set.hdr->nflag;
     for (int slot = blockIdx.x; slot < nf; slot += gridDim.x) {
@@ -354,69 +436,84 @@ __global__ void __launch_bounds__(256) k_ib_vel(IbArgs a) {
 }
 
 // U_m = sum over the stencil of v(x) phi phi phi, rows inside a wall taking the wall
-// velocity; optionally X_out = X + U.
+// velocity; optionally X_out = X + U.  Sixteen lanes per node: lane (b, c) takes stencil
+// row y = base_y + b, z = base_z + c and its four x cells; the 16 partial sums are
+// combined by a fixed butterfly, so the result does not depend on scheduling.
 template <class St>
 __global__ void __launch_bounds__(256) k_ib_gather(IbArgs a) {
     using T = typename St::T;
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= a.n) return;
-    const int c = a.node_ch[m];
-    const Chan& ch = a.chan[c];
-    float w[3][4];
-    int b[3];
-    double X[3];
-    for (int d = 0; d < 3; ++d) {
-        X[d] = a.X[d * a.n + m];
-        const int dim = d == 0 ? ch.nx : (d == 1 ? ch.ny : ch.nz);
-        const bool finite = isfinite(X[d]) && fabs(X[d]) < 1e9;
-        int64_t base = finite ? ib_weights(a.kernel, X[d], w[d]) : 0;
-        if (!finite) w[d][0] = w[d][1] = w[d][2] = w[d][3] = 0.0f;
-        if (d == 1 && ch.walls) {
-            if (base < -4) base = -4;
-            if (base > ch.ny) base = ch.ny;
-            b[d] = (int)base;
-        } else {
-            b[d] = wrapi(base, dim);
-        }
-    }
-    Stencil s;
-    stencil_cells(ch, b[0], b[1], b[2], s);
+    // consecutive node blocks on the same XCD: neighbouring nodes share tiles in one L2
+    const int64_t G = gridDim.x, bx = blockIdx.x, per = G >> 3, rem = G & 7, xcd = bx & 7;
+    const int64_t L = xcd * per + (xcd < rem ? xcd : rem) + (bx >> 3);
+    const int64_t m = (L * blockDim.x + threadIdx.x) >> 4;
+    const int sl = threadIdx.x & 15, bq = sl & 3, cq = sl >> 2;
     float U[3] = {0.f, 0.f, 0.f};
-    for (int cz4 = 0; cz4 < 4; ++cz4)
-        for (int cy4 = 0; cy4 < 4; ++cy4) {
-            const float wyz = w[1][cy4] * w[2][cz4];
-            for (int cx4 = 0; cx4 < 4; ++cx4) {
-                const float ww = w[0][cx4] * wyz;
-                float v[3];
-                if (!s.yok[cy4]) {
-                    const float* uw = s.y[cy4] < 0 ? ch.uw_lo : ch.uw_hi;
-                    v[0] = uw[0]; v[1] = uw[1]; v[2] = uw[2];
-                } else {
-                    const int x = s.x[cx4], y = s.y[cy4], z = s.z[cz4];
-                    const int slot = a.set.tile_slot[tile_of(ch, x, y, z)];
-                    if (slot >= 0) {
-                        const float* vb = a.vel + (int64_t)slot * (3 * TILE_CELLS) + tile_local(x, y, z);
-                        v[0] = vb[0]; v[1] = vb[TILE_CELLS]; v[2] = vb[2 * TILE_CELLS];
-                    } else {  // not under any spread stencil: no IB force here
-                        const int32_t n = x + ch.nx * (y + ch.ny * z);
-                        float g[Q];
-                        pull<St>((const T*)a.pop + ch.pop_off, ch, ch.ncell, n, x, y, z, g);
-                        float drho, jx, jy, jz;
-                        moments(g, drho, jx, jy, jz);
-                        const float ir = 1.0f / (1.0f + drho);
-                        v[0] = (jx + 0.5f * ch.body[0]) * ir;
-                        v[1] = (jy + 0.5f * ch.body[1]) * ir;
-                        v[2] = (jz + 0.5f * ch.body[2]) * ir;
-                    }
-                }
-                U[0] += ww * v[0];
-                U[1] += ww * v[1];
-                U[2] += ww * v[2];
+    double X[3] = {0.0, 0.0, 0.0};
+    const bool valid = m < a.n;
+    if (valid) {
+        const int c = a.node_ch[m];
+        const Chan& ch = a.chan[c];
+        float w[3][4];
+        int b[3];
+        for (int d = 0; d < 3; ++d) {
+            X[d] = a.X[d * a.n + m];
+            const int dim = d == 0 ? ch.nx : (d == 1 ? ch.ny : ch.nz);
+            const bool finite = isfinite(X[d]) && fabs(X[d]) < 1e9;
+            int64_t base = finite ? ib_weights(a.kernel, X[d], w[d]) : 0;
+            if (!finite) w[d][0] = w[d][1] = w[d][2] = w[d][3] = 0.0f;
+            if (d == 1 && ch.walls) {
+                if (base < -4) base = -4;
+                if (base > ch.ny) base = ch.ny;
+                b[d] = (int)base;
+            } else {
+                b[d] = wrapi(base, dim);
             }
         }
-    for (int d = 0; d < 3; ++d) {
-        if (a.U) a.U[d * a.n + m] = U[d];
-        if (a.Xout) a.Xout[d * a.n + m] = X[d] + (double)U[d];
+        Stencil s;
+        stencil_cells(ch, b[0], b[1], b[2], s);
+        const float wyz = w[1][bq] * w[2][cq];
+        const int y = s.y[bq], z = s.z[cq];
+#pragma unroll
+        for (int ax = 0; ax < 4; ++ax) {
+            const float ww = w[0][ax] * wyz;
+            float v0, v1, v2;
+            if (!s.yok[bq]) {
+                const float* uw = y < 0 ? ch.uw_lo : ch.uw_hi;
+                v0 = uw[0]; v1 = uw[1]; v2 = uw[2];
+            } else {
+                const int x = s.x[ax];
+                const int slot = a.set.tile_slot[tile_of(ch, x, y, z)];
+                if (slot >= 0) {
+                    const float* vb = a.vel + (int64_t)slot * (3 * TILE_CELLS) + tile_local(x, y, z);
+                    v0 = vb[0]; v1 = vb[TILE_CELLS]; v2 = vb[2 * TILE_CELLS];
+                } else {  // not under any spread stencil: no IB force here
+                    const int32_t n = x + ch.nx * (y + ch.ny * z);
+                    float g[Q];
+                    pull<St>((const T*)a.pop + ch.pop_off, ch, ch.ncell, n, x, y, z, g);
+                    float drho, jx, jy, jz;
+                    moments(g, drho, jx, jy, jz);
+                    const float ir = 1.0f / (1.0f + drho);
+                    v0 = (jx + 0.5f * ch.body[0]) * ir;
+                    v1 = (jy + 0.5f * ch.body[1]) * ir;
+                    v2 = (jz + 0.5f * ch.body[2]) * ir;
+                }
+            }
+            U[0] += ww * v0;
+            U[1] += ww * v1;
+            U[2] += ww * v2;
+        }
+    }
+#pragma unroll
+    for (int d = 1; d < 16; d <<= 1) {
+        U[0] += __shfl_xor(U[0], d, 64);
+        U[1] += __shfl_xor(U[1], d, 64);
+        U[2] += __shfl_xor(U[2], d, 64);
+    }
+    if (valid && sl == 0) {
+        for (int d = 0; d < 3; ++d) {
+            if (a.U) a.U[d * a.n + m] = U[d];
+            if (a.Xout) a.Xout[d * a.n + m] = X[d] + (double)U[d];
+        }
     }
 }
 
@@ -424,8 +521,8 @@ template <class St>
 static void launch_interp_typed(lbm_ctx* c, const IbArgs& a) {
     int64_t g = c->max_slots < 4096 ? c->max_slots : 4096;
     if (g < 1) g = 1;
-    k_ib_vel<St><<<dim3((unsigned)g), dim3(256), 0, c->stream>>>(a);
-    if (a.n > 0) k_ib_gather<St><<<dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, c->stream>>>(a);
+    k_ib_vel<St><<<dim3((unsigned)g), dim3(512), 0, c->stream>>>(a);
+    if (a.n > 0) k_ib_gather<St><<<dim3((unsigned)((16 * a.n + 255) / 256)), dim3(256), 0, c->stream>>>(a);
 }
 
 hipError_t launch_ib_interp(lbm_ctx* c, const IbArgs& a) {
@@ -467,12 +564,12 @@ __device__ __forceinline__ double dt3(const double a[3], const double b[3]) {
 }
 
 // Signed dihedral angle of hinge (x0, x1, x2, x3) about the shared edge e = x2 - x1,
-// between the normals nA = (x1-x0) x (x2-x0) and nB = (x2-x3) x (x1-x3); optionally the
-// gradient with respect to vertex `role`:
+// between the normals nA = (x1-x0) x (x2-x0) and nB = (x2-x3) x (x1-x3), and its gradient
+// with respect to the four vertices:
 //   d/dx0 = -|e| nA/|nA|^2,  d/dx3 = -|e| nB/|nB|^2,
 //   d/dx1 = -((x0-x2).e/|e|) nA/|nA|^2 - ((x3-x2).e/|e|) nB/|nB|^2,
 //   d/dx2 =  ((x0-x1).e/|e|) nA/|nA|^2 + ((x3-x1).e/|e|) nB/|nB|^2.
-__device__ double hinge(const double x[4][3], int role, double grad[3]) {
+__device__ double hinge(const double x[4][3], double grad[4][3], bool want_grad) {
     double a[3], b[3], nA[3], nB[3], e[3], cr[3];
     sub(x[1], x[0], a); sub(x[2], x[0], b); crs(a, b, nA);
     sub(x[2], x[3], a); sub(x[1], x[3], b); crs(a, b, nB);
@@ -481,20 +578,19 @@ __device__ double hinge(const double x[4][3], int role, double grad[3]) {
     const double la = sqrt(AA), lb = sqrt(BB);
     crs(nA, nB, cr);
     const double theta = atan2(dt3(cr, e) / (la * lb * L), dt3(nA, nB) / (la * lb));
-    if (role >= 0) {
-        double cA = 0.0, cB = 0.0;
-        if (role == 0) { cA = -L; cB = 0.0; }
-        else if (role == 3) { cA = 0.0; cB = -L; }
-        else if (role == 1) {
-            double t0[3], t3[3];
-            sub(x[0], x[2], t0); sub(x[3], x[2], t3);
-            cA = -dt3(t0, e) / L; cB = -dt3(t3, e) / L;
-        } else {
-            double t0[3], t3[3];
-            sub(x[0], x[1], t0); sub(x[3], x[1], t3);
-            cA = dt3(t0, e) / L; cB = dt3(t3, e) / L;
+    if (want_grad) {
+        double t0[3], t3[3];
+        sub(x[0], x[2], t0); sub(x[3], x[2], t3);
+        const double c1A = -dt3(t0, e) / L, c1B = -dt3(t3, e) / L;
+        sub(x[0], x[1], t0); sub(x[3], x[1], t3);
+        const double c2A = dt3(t0, e) / L, c2B = dt3(t3, e) / L;
+        for (int d = 0; d < 3; ++d) {
+            const double qA = nA[d] / AA, qB = nB[d] / BB;
+            grad[0][d] = -L * qA;
+            grad[3][d] = -L * qB;
+            grad[1][d] = c1A * qA + c1B * qB;
+            grad[2][d] = c2A * qA + c2B * qB;
         }
-        for (int d = 0; d < 3; ++d) grad[d] = cA * nA[d] / AA + cB * nB[d] / BB;
     }
     return theta;
 }
@@ -511,12 +607,33 @@ __global__ void k_mem_rest(ib_membrane m, const double* X) {
         }
     }
     if (i < m.nh) {
-        double x[4][3], gdummy[3];
+        double x[4][3], gdummy[4][3];
         for (int k = 0; k < 4; ++k) ld3(X, m.n, m.hinges[4 * i + k], x[k]);
-        m.rest_theta[i] = hinge(x, -1, gdummy);
+        m.rest_theta[i] = hinge(x, gdummy, false);
     }
 }
 
+// Bending forces of every hinge on its four vertices: -k_b sin(theta - theta0) grad(theta).
+__global__ void __launch_bounds__(256) k_mem_hinges(ib_membrane m, const double* X) {
+    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= m.nh) return;
+    double x[4][3], gr[4][3];
+    for (int k = 0; k < 4; ++k) ld3(X, m.n, m.hinges[4 * h + k], x[k]);
+    const double th = hinge(x, gr, true);
+    const double dE = m.k_bend * sin(th - m.rest_theta[h]);
+    for (int k = 0; k < 4; ++k) {
+        double* out = m.hinge_force + 3 * (int64_t)m.hinge_slot[4 * h + k];
+        for (int d = 0; d < 3; ++d) out[d] = -dE * gr[k][d];
+    }
+}
+
+// Inverse of the node -> hinge incidence CSR: position of (hinge, role) in hinge_inc.
+__global__ void k_mem_hinge_slots(ib_membrane m, int64_t nnz) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nnz) m.hinge_slot[m.hinge_inc[e]] = (int32_t)e;
+}
+
+// Per node: springs (CSR), the hinge forces of its incidences, tether.
 __global__ void __launch_bounds__(256) k_mem_forces(ib_membrane m, const double* X, float* Fout) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
@@ -533,13 +650,8 @@ __global__ void __launch_bounds__(256) k_mem_forces(ib_membrane m, const double*
     }
     if (m.hinge_ptr && m.k_bend != 0.0) {
         for (int e = m.hinge_ptr[i]; e < m.hinge_ptr[i + 1]; ++e) {
-            const int code = m.hinge_inc[e];
-            const int h = code >> 2, role = code & 3;
-            double x[4][3], gr[3];
-            for (int k = 0; k < 4; ++k) ld3(X, m.n, m.hinges[4 * h + k], x[k]);
-            const double th = hinge(x, role, gr);
-            const double dE = m.k_bend * sin(th - m.rest_theta[h]);
-            F[0] -= dE * gr[0]; F[1] -= dE * gr[1]; F[2] -= dE * gr[2];
+            const double* hf = m.hinge_force + 3 * (int64_t)e;
+            F[0] += hf[0]; F[1] += hf[1]; F[2] += hf[2];
         }
     }
     if (m.anchors) {
@@ -552,11 +664,17 @@ hipError_t launch_membrane_rest(const ib_membrane* m, const double* X_rest, hipS
     const int64_t n = m->n > m->nh ? m->n : m->nh;
     if (n <= 0) return hipSuccess;
     k_mem_rest<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(*m, X_rest);
+    if (m->hinge_ptr && m->nh > 0) {
+        const int64_t nnz = 4 * m->nh;
+        k_mem_hinge_slots<<<dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s>>>(*m, nnz);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* F, hipStream_t s) {
     if (m->n <= 0) return hipSuccess;
+    if (m->hinge_ptr && m->k_bend != 0.0 && m->nh > 0)
+        k_mem_hinges<<<dim3((unsigned)((m->nh + 255) / 256)), dim3(256), 0, s>>>(*m, X);
     k_mem_forces<<<dim3((unsigned)((m->n + 255) / 256)), dim3(256), 0, s>>>(*m, X, F);
     return hipGetLastError();
 }

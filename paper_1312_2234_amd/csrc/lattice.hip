@@ -1,7 +1,7 @@
 // lattice.hip -- lattice-Boltzmann kernels for gfx950 (section 3.3).
 //
-// State: weight-shifted populations g_i = f_i - w_i, SoA [19][nz][ny][nx] per channel, two
-// buffers.  The stored buffer holds the post-collision values f* of the previous step
+// State: weight-shifted populations g_i = f_i - w_i, in blocks of 64 consecutive cells
+// ([ncell/64][19][64] per channel, see pidx), two buffers.  The stored buffer holds the post-collision values f* of the previous step
 // ("pull" scheme), so one pass per step reads every population once from the neighbour
 // it streams from and writes every population once, aligned, at its own cell:
 //   152 B per cell per step in float32, 76 B in float16 / bfloat16.
@@ -86,11 +86,128 @@ __global__ void __launch_bounds__(1024) k_step(LatArgs a) {
             const float S = wgt(i) * guo * (3.0f * cF + 9.0f * cu * cF - vF3);
             const float gn = g[i] - om * (g[i] - geq) + S;
             if (NT)
-                St::st_nt(d + (int64_t)i * N + n, gn);
+                St::st_nt(d + pidx(i, n), gn);
             else
-                St::st(d + (int64_t)i * N + n, gn);
+                St::st(d + pidx(i, n), gn);
         }
     });
+}
+
+// Vector form of the same step: V consecutive cells of one x-row per lane (nx % V == 0,
+// every channel a whole number of 64V-cell units), so every population is read and written
+// with one aligned V-wide access per lane and a wavefront covers 64V consecutive cells of
+// each of the 19 arrays.  Populations with c_x != 0 need the element just outside the
+// lane's aligned group: it comes from the neighbouring lane by a lane shuffle, or by a
+// direct load at a row end or at the edge of the wavefront.
+template <class St, bool NT, int V>
+__global__ void __launch_bounds__(256) k_step_v(LatArgs a) {
+    using T = typename St::T;
+    const int wpb = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t G = gridDim.x;
+    int64_t L = a.remap ? xcd_remap(blockIdx.x, G) : (int64_t)blockIdx.x;
+    for (;; L += G) {
+        const int64_t seg = (L * wpb + wave) * V;
+        if (seg >= a.nseg) break;
+        const Chan& ch = a.chan[a.seg_ch[seg]];
+        const int32_t n0 = (int32_t)((seg - ch.seg_off) * 64) + lane * V;
+        int x0, y, z;
+        cell_xyz(ch, (uint32_t)n0, x0, y, z);
+        const int nx = ch.nx, ny = ch.ny, nz = ch.nz;
+        const int32_t sxy = nx * ny;
+        const int32_t oy_p = (y == 0) ? (ny - 1) * nx : -nx;
+        const int32_t oy_m = (y == ny - 1) ? -(ny - 1) * nx : nx;
+        const int32_t oz_p = (z == 0) ? (nz - 1) * sxy : -sxy;
+        const int32_t oz_m = (z == nz - 1) ? -(nz - 1) * sxy : sxy;
+        const bool wlo = ch.walls && y == 0;
+        const bool whi = ch.walls && y == ny - 1;
+        const int64_t N = ch.ncell;
+        const T* s = (const T*)a.src + ch.pop_off;
+        T* d = (T*)a.dst + ch.pop_off;
+        const int32_t row0 = n0 - x0;
+        float g[Q][V];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const bool bb = (cy(i) == 1 && wlo) || (cy(i) == -1 && whi);
+            const int32_t row = row0 + (cy(i) == 1 ? oy_p : (cy(i) == -1 ? oy_m : 0)) +
+                                (cz(i) == 1 ? oz_p : (cz(i) == -1 ? oz_m : 0));
+            float A[V];
+            ldv<St, V>(bb ? (s + pidx(opp(i), n0)) : (s + pidx(i, row + x0)), A);
+            float corr = 0.0f;
+            if (cy(i) != 0) {
+                const float* u = cy(i) == 1 ? ch.uw_lo : ch.uw_hi;
+                corr = bb ? 6.0f * wgt(i) * (cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2]) : 0.0f;
+            }
+            if (cx(i) == 1) {
+                float prev = __shfl_up(A[V - 1], 1, 64);
+                if (!bb && (x0 == 0 || lane == 0)) prev = St::ld(s + pidx(i, row + (x0 == 0 ? nx - 1 : x0 - 1)));
+                g[i][0] = bb ? A[0] + corr : prev;
+#pragma unroll
+                for (int k = 1; k < V; ++k) g[i][k] = bb ? A[k] + corr : A[k - 1];
+            } else if (cx(i) == -1) {
+                float next = __shfl_down(A[0], 1, 64);
+                if (!bb && (x0 + V == nx || lane == 63)) next = St::ld(s + pidx(i, row + (x0 + V == nx ? 0 : x0 + V)));
+#pragma unroll
+                for (int k = 0; k < V - 1; ++k) g[i][k] = bb ? A[k] + corr : A[k + 1];
+                g[i][V - 1] = bb ? A[V - 1] + corr : next;
+            } else {
+#pragma unroll
+                for (int k = 0; k < V; ++k) g[i][k] = A[k] + corr;
+            }
+        }
+        // force: the V cells lie in one IB tile (V divides the tile edge)
+        float Fx[V], Fy[V], Fz[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            Fx[k] = ch.body[0];
+            Fy[k] = ch.body[1];
+            Fz[k] = ch.body[2];
+        }
+        if (a.tile_slot) {
+            const int slot = a.tile_slot[tile_of(ch, x0, y, z)];
+            if (slot >= 0) {
+                const float* fb = a.force + (int64_t)slot * (3 * TILE_CELLS) + tile_local(x0, y, z);
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    Fx[k] += fb[k];
+                    Fy[k] += fb[TILE_CELLS + k];
+                    Fz[k] += fb[2 * TILE_CELLS + k];
+                }
+            }
+        }
+        float drho[V], rho[V], vx[V], vy[V], vz[V], vv15[V], vF3[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            float gk[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) gk[i] = g[i][k];
+            float jx, jy, jz;
+            moments(gk, drho[k], jx, jy, jz);
+            rho[k] = 1.0f + drho[k];
+            const float ir = 1.0f / rho[k];
+            vx[k] = (jx + 0.5f * Fx[k]) * ir;
+            vy[k] = (jy + 0.5f * Fy[k]) * ir;
+            vz[k] = (jz + 0.5f * Fz[k]) * ir;
+            vv15[k] = 1.5f * (vx[k] * vx[k] + vy[k] * vy[k] + vz[k] * vz[k]);
+            vF3[k] = 3.0f * (vx[k] * Fx[k] + vy[k] * Fy[k] + vz[k] * Fz[k]);
+        }
+        const float om = ch.omega, guo = ch.guo;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            float out[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const float cu = cx(i) * vx[k] + cy(i) * vy[k] + cz(i) * vz[k];
+                const float cF = cx(i) * Fx[k] + cy(i) * Fy[k] + cz(i) * Fz[k];
+                const float geq = wgt(i) * (drho[k] + rho[k] * (3.0f * cu + 4.5f * cu * cu - vv15[k]));
+                const float S = wgt(i) * guo * (3.0f * cF + 9.0f * cu * cF - vF3[k]);
+                out[k] = g[i][k] - om * (g[i][k] - geq) + S;
+            }
+            stv<St, V, NT>(d + pidx(i, n0), out);
+        }
+        if (!a.persistent) break;
+    }
 }
 
 // ---------------------------------------------------------------- initial state
@@ -136,7 +253,7 @@ __device__ __forceinline__ void unstream(const Chan& ch, typename St::T* d, int3
             v = h(i, m);
         else
             v = h(opp(i), n) + wall_term(ch, i);
-        St::st(d + (int64_t)i * N + n, v);
+        St::st(d + pidx(i, n), v);
     }
 }
 
@@ -264,6 +381,31 @@ __global__ void __launch_bounds__(256) k_wss(LatArgs a, int nch, int64_t total) 
     out[plane + q] = -k2 * szy - k2 * 0.5f * (Fz * vy + Fy * vz);
 }
 
+// STREAM-style copy used to measure the practical HBM ceiling (16 bytes per lane per
+// iteration, grid-stride; variant 1 stores non-temporally).
+typedef float f4v __attribute__((ext_vector_type(4)));
+template <bool NT>
+__global__ void __launch_bounds__(256) k_copy16(const f4v* __restrict__ src, f4v* __restrict__ dst, int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) {
+        const f4v v = src[i];
+        if (NT)
+            __builtin_nontemporal_store(v, dst + i);
+        else
+            dst[i] = v;
+    }
+}
+
+hipError_t launch_copy16(hipStream_t s, const void* src, void* dst, int64_t bytes, int variant, int64_t grid) {
+    const int64_t n16 = bytes / 16;
+    if (grid <= 0) grid = (n16 + 255) / 256;
+    if (variant == 1)
+        k_copy16<true><<<dim3((unsigned)grid), dim3(256), 0, s>>>((const f4v*)src, (f4v*)dst, n16);
+    else
+        k_copy16<false><<<dim3((unsigned)grid), dim3(256), 0, s>>>((const f4v*)src, (f4v*)dst, n16);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -277,8 +419,38 @@ hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v) {
     return hipGetLastError();
 }
 
+template <class St, int V>
+static hipError_t launch_step_v(lbm_ctx* c, const LatArgs& a0) {
+    LatArgs a = a0;
+    const int block = 256, wpb = 4;
+    const int64_t units = c->total_segs / V;
+    const int64_t nblk = (units + wpb - 1) / wpb;
+    int64_t grid = nblk;
+    a.remap = c->launch.xcd_remap;
+    a.persistent = 0;
+    if (c->launch.persistent > 0 && c->launch.persistent < nblk) {
+        grid = c->launch.persistent;
+        a.persistent = 1;
+    }
+    if (c->launch.nontemporal)
+        k_step_v<St, true, V><<<dim3((unsigned)grid), dim3(block), 0, c->stream>>>(a);
+    else
+        k_step_v<St, false, V><<<dim3((unsigned)grid), dim3(block), 0, c->stream>>>(a);
+    return hipGetLastError();
+}
+
+// The vector step applies when every channel has nx % V == 0 and a whole number of
+// 64V-cell units; otherwise the scalar step runs.
+static bool vec_ok(const lbm_ctx* c, int V) {
+    for (const Chan& ch : c->chans)
+        if (ch.nx % V != 0 || ch.ncell % (64 * V) != 0) return false;
+    return true;
+}
+
 template <class St>
 static hipError_t launch_typed(lbm_ctx* c, int which, const LatArgs& a0) {
+    if (which == LK_STEP && c->launch.vec == 4 && vec_ok(c, 4)) return launch_step_v<St, 4>(c, a0);
+    if (which == LK_STEP && c->launch.vec == 2 && vec_ok(c, 2)) return launch_step_v<St, 2>(c, a0);
     LatArgs a = a0;
     const int block = c->launch.block;
     const int wpb = block / 64;

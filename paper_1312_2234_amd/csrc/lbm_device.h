@@ -40,7 +40,7 @@ __host__ __device__ constexpr float wgt(int i) {
 struct Chan {
     int32_t nx, ny, nz, walls;
     int64_t ncell;     // nx*ny*nz (< 2^31)
-    int64_t pop_off;   // element offset of this channel's [19][ncell] population block
+    int64_t pop_off;   // element offset of this channel's [ncell/64][19][64] population blocks
     int64_t cell_off;  // offset of this channel in concatenated per-cell outputs
     int64_t seg_off;   // first 64-cell segment of this channel
     int64_t tile_off;  // first IB tile of this channel
@@ -54,6 +54,15 @@ struct Chan {
     float uw_hi[3];
     float pad2[3];
 };
+
+// Population layout: blocks of 64 consecutive cells (one wavefront's segment), each block
+// holding its 19 populations one after another ([cells/64][19][64], "AoSoA").  A wavefront
+// then writes one contiguous 19 x 64-element run per step and reads 64-element runs,
+// instead of touching 19 + 19 arrays a whole lattice apart.
+constexpr int BLK = 64;
+__device__ __forceinline__ int64_t pidx(int i, int32_t n) {
+    return (int64_t)(n >> 6) * (Q * BLK) + i * BLK + (n & (BLK - 1));
+}
 
 // q = n / d for n < 2^31 (round-up reciprocal, see host set-up).
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t m, uint32_t s) {
@@ -71,20 +80,24 @@ __device__ __forceinline__ void cell_xyz(const Chan& ch, uint32_t n, int& x, int
 // ---------------------------------------------------------------- storage codecs
 struct StF32 {
     using T = float;
+    static __device__ __forceinline__ float dec(T v) { return v; }
+    static __device__ __forceinline__ T enc(float v) { return v; }
     static __device__ __forceinline__ float ld(const T* p) { return *p; }
     static __device__ __forceinline__ void st(T* p, float v) { *p = v; }
     static __device__ __forceinline__ void st_nt(T* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 struct StF16 {
     using T = uint16_t;
-    static __device__ __forceinline__ float ld(const T* p) { return __half2float(__ushort_as_half(*p)); }
+    static __device__ __forceinline__ float dec(T v) { return __half2float(__ushort_as_half(v)); }
+    static __device__ __forceinline__ float ld(const T* p) { return dec(*p); }
     static __device__ __forceinline__ uint16_t enc(float v) { return __half_as_ushort(__float2half_rn(v)); }
     static __device__ __forceinline__ void st(T* p, float v) { *p = enc(v); }
     static __device__ __forceinline__ void st_nt(T* p, float v) { __builtin_nontemporal_store(enc(v), p); }
 };
 struct StBF16 {
     using T = uint16_t;
-    static __device__ __forceinline__ float ld(const T* p) { return __uint_as_float((uint32_t)(*p) << 16); }
+    static __device__ __forceinline__ float dec(T v) { return __uint_as_float((uint32_t)v << 16); }
+    static __device__ __forceinline__ float ld(const T* p) { return dec(*p); }
     // round to nearest, ties to even; NaN stays a quiet NaN
     static __device__ __forceinline__ uint16_t enc(float v) {
         uint32_t u = __float_as_uint(v);
@@ -95,6 +108,28 @@ struct StBF16 {
     static __device__ __forceinline__ void st(T* p, float v) { *p = enc(v); }
     static __device__ __forceinline__ void st_nt(T* p, float v) { __builtin_nontemporal_store(enc(v), p); }
 };
+
+// V consecutive stored elements (address aligned to V elements) <-> floats.
+template <class St, int V>
+__device__ __forceinline__ void ldv(const typename St::T* p, float out[V]) {
+    using T = typename St::T;
+    typedef T vec __attribute__((ext_vector_type(V)));
+    const vec t = *(const vec*)p;
+#pragma unroll
+    for (int k = 0; k < V; ++k) out[k] = St::dec(t[k]);
+}
+template <class St, int V, bool NT>
+__device__ __forceinline__ void stv(typename St::T* p, const float in[V]) {
+    using T = typename St::T;
+    typedef T vec __attribute__((ext_vector_type(V)));
+    vec t;
+#pragma unroll
+    for (int k = 0; k < V; ++k) t[k] = St::enc(in[k]);
+    if (NT)
+        __builtin_nontemporal_store(t, (vec*)p);
+    else
+        *(vec*)p = t;
+}
 
 // ---------------------------------------------------------------- pull streaming
 // Populations arriving at cell n = (x, y, z) of the current step: f_i(x) = f*_i(x - c_i)
@@ -120,7 +155,7 @@ __device__ __forceinline__ void pull(const typename St::T* __restrict__ s, const
                       (cy(i) == 1 ? oy_p : (cy(i) == -1 ? oy_m : 0)) +
                       (cz(i) == 1 ? oz_p : (cz(i) == -1 ? oz_m : 0));
         const bool bb = (cy(i) == 1 && wlo) || (cy(i) == -1 && whi);
-        const typename St::T* p = bb ? (s + (int64_t)opp(i) * N + n) : (s + (int64_t)i * N + (n + off));
+        const typename St::T* p = bb ? (s + pidx(opp(i), n)) : (s + pidx(i, n + off));
         float v = St::ld(p);
         if (cy(i) != 0) {
             const float* u = cy(i) == 1 ? ch.uw_lo : ch.uw_hi;

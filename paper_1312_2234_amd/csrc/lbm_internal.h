@@ -70,10 +70,13 @@ struct IbArgs {
     uint32_t* flags;
     const void* pop;        // current stored populations (interpolation)
     int32_t kernel;         // ib_kernel
+    int32_t nch;
+    int32_t* rank;          // [n][27] packed rank of a node in each tile list it joins
+    int32_t* blkbase;       // [ceil(n/256)][2048] per-block base of each hashed tile
 };
 
 struct Layout {
-    size_t chan, seg_ch, popA, popB, flags, node_ch, rec, sets[2][7], list, force, vel, total;
+    size_t chan, seg_ch, popA, popB, flags, node_ch, rec, rank, blkbase, sets[2][7], list, force, vel, total;
 };
 
 }  // namespace lbmib
@@ -103,9 +106,11 @@ struct lbm_ctx {
     lbmib::IbSet set[2]{};
     int ibset = 0;  // set of the latest spread (both clean at creation)
     int32_t* d_list = nullptr;
+    int32_t* d_rank = nullptr;
+    int32_t* d_blkbase = nullptr;
     float* d_force = nullptr;
     float* d_vel = nullptr;
-    lbm_launch launch{256, 1, 0, 0};
+    lbm_launch launch{256, 1, 0, 1, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
 };
@@ -117,6 +122,7 @@ hipError_t launch_lattice(lbm_ctx* c, int which, const LatArgs& a);
 enum { LK_STEP = 0, LK_INIT, LK_MOMENTS, LK_GETF, LK_SETF, LK_WSS };
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
 hipError_t launch_wss(lbm_ctx* c, const LatArgs& a, int64_t total);
+hipError_t launch_copy16(hipStream_t s, const void* src, void* dst, int64_t bytes, int variant, int64_t grid);
 
 // ib.hip
 hipError_t launch_ib_spread(lbm_ctx* c, const IbArgs& a);

@@ -151,9 +151,29 @@ class Bodies:
         return self.X.shape[1]
 
 
+def morton_order(V, bits=10):
+    """Permutation that numbers points along a Morton (Z-order) curve of their position, so
+    that nodes with nearby numbers are nearby in space."""
+    lo, hi = V.min(axis=0), V.max(axis=0)
+    q = ((V - lo) / np.maximum(hi - lo, 1e-30) * ((1 << bits) - 1)).astype(np.int64)
+    code = np.zeros(len(V), np.int64)
+    for b in range(bits):
+        for d in range(3):
+            code |= ((q[:, d] >> b) & 1) << (3 * b + d)
+    return np.argsort(code, kind="stable")
+
+
+def renumber(V, T, order):
+    """Renumber vertices so that new vertex k is old vertex order[k]."""
+    inv = np.empty(len(order), np.int64)
+    inv[order] = np.arange(len(order))
+    return V[order], inv[T].astype(np.int32)
+
+
 @functools.lru_cache(maxsize=None)
 def _topology(nodes):
     V0, T = unit_sphere(nodes)
+    V0, T = renumber(V0, T, morton_order(V0))
     return V0, T, mesh_edges(T), mesh_hinges(T)
 
 

@@ -25,6 +25,7 @@ EXPORTS = [
     "lbm_set_populations", "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_wall_stress",
     "lbm_error_flags", "lbm_status_string", "ib_membrane_rest", "ib_membrane_forces",
     "lbm_coupled_steps", "lbm_graph_capture", "lbm_graph_launch", "lbm_set_launch", "lbm_get_launch",
+    "lbm_stream_copy",
 ]
 
 
@@ -36,13 +37,15 @@ class LbmParams(C.Structure):
 
 class LbmLaunch(C.Structure):
     _fields_ = [("block", C.c_int32), ("xcd_remap", C.c_int32), ("persistent", C.c_int32),
-                ("nontemporal", C.c_int32)]
+                ("nontemporal", C.c_int32), ("vec", C.c_int32)]
 
 
 class IbMembrane(C.Structure):
     _fields_ = [("n", C.c_int64), ("nbr_ptr", C.c_void_p), ("nbr_idx", C.c_void_p), ("rest_len", C.c_void_p),
                 ("k_spring", C.c_double), ("hinge_ptr", C.c_void_p), ("hinge_inc", C.c_void_p),
-                ("hinges", C.c_void_p), ("rest_theta", C.c_void_p), ("nh", C.c_int64), ("k_bend", C.c_double),
+                ("hinges", C.c_void_p), ("rest_theta", C.c_void_p), ("hinge_slot", C.c_void_p),
+                ("hinge_force", C.c_void_p),
+                ("nh", C.c_int64), ("k_bend", C.c_double),
                 ("anchors", C.c_void_p), ("k_tether", C.c_double)]
 
 
@@ -87,6 +90,7 @@ def lib():
         L.lbm_graph_launch.argtypes = [vp, i32]
         L.lbm_set_launch.argtypes = [vp, C.POINTER(LbmLaunch)]
         L.lbm_get_launch.argtypes = [vp, C.POINTER(LbmLaunch)]
+        L.lbm_stream_copy.argtypes = [vp, vp, C.c_size_t, i32, i64, vp]
         for name in EXPORTS:
             if name not in ("lbm_workspace_bytes", "lbm_state_bytes", "lbm_status_string"):
                 getattr(L, name).restype = C.c_int32
@@ -286,15 +290,25 @@ class Lattice:
         with self.ordered:
             _check(lib().lbm_graph_launch(self.h, int(repeats)), "lbm_graph_launch")
 
-    def set_launch(self, block=256, xcd_remap=1, persistent=0, nontemporal=0):
-        cfg = LbmLaunch(block, xcd_remap, persistent, nontemporal)
+    def set_launch(self, block=256, xcd_remap=1, persistent=0, nontemporal=0, vec=0):
+        cfg = LbmLaunch(block, xcd_remap, persistent, nontemporal, vec)
         _check(lib().lbm_set_launch(self.h, C.byref(cfg)), "lbm_set_launch")
 
     def get_launch(self):
         cfg = LbmLaunch()
         _check(lib().lbm_get_launch(self.h, C.byref(cfg)), "lbm_get_launch")
         return dict(block=cfg.block, xcd_remap=cfg.xcd_remap, persistent=cfg.persistent,
-                    nontemporal=cfg.nontemporal)
+                    nontemporal=cfg.nontemporal, vec=cfg.vec)
+
+
+def stream_copy(src, dst, variant=0, grid=0):
+    """Device copy with the library's STREAM-style kernel (measurement helper); ordered on
+    torch's current stream."""
+    import torch
+
+    assert src.numel() * src.element_size() == dst.numel() * dst.element_size()
+    _check(lib().lbm_stream_copy(_ptr(src), _ptr(dst), src.numel() * src.element_size(), int(variant), int(grid),
+                                 _stream_ptr(torch, src.device)), "lbm_stream_copy")
 
 
 class Membrane:
@@ -328,8 +342,11 @@ class Membrane:
             hp, hi = inputs.csr_hinges(n, bodies.hinges)
             hpt, hit, ht = dev_i32(hp), dev_i32(hi), dev_i32(bodies.hinges.reshape(-1))
             rt = torch.zeros(len(bodies.hinges), dtype=torch.float64, device=dev)
-            self._keep.append(rt)
+            hf = torch.zeros(12 * len(bodies.hinges), dtype=torch.float64, device=dev)
+            hs = torch.zeros(4 * len(bodies.hinges), dtype=torch.int32, device=dev)
+            self._keep += [rt, hf, hs]
             s.hinge_ptr, s.hinge_inc, s.hinges, s.rest_theta = hpt.data_ptr(), hit.data_ptr(), ht.data_ptr(), rt.data_ptr()
+            s.hinge_force, s.hinge_slot = hf.data_ptr(), hs.data_ptr()
             s.nh = len(bodies.hinges)
         s.k_bend = float(bodies.k_bend)
         if bodies.anchors is not None:

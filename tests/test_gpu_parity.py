@@ -293,6 +293,36 @@ def test_populations_roundtrip_and_resume(orc, gpu):
     assert np.array_equal(a, N(g.moments()[1]))
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_vector_step_matches_scalar_all_storages(gpu, storage):
+    rng = np.random.default_rng(21)
+    ch = inputs.Channel(64, 24, 16, 0.9, u_wall_hi=(0.04, 0, 0), init="shear")
+    out = []
+    for vec in (0, 2, 4):
+        g = gpu.Lattice([ch], storage=storage, max_nodes=300, device=DEV)
+        g.set_launch(vec=vec)
+        g.init()
+        X = T(np.stack([rng.uniform(0, 64, 300), rng.uniform(2, 20, 300), rng.uniform(0, 16, 300)]))
+        F = T(1e-3 * rng.standard_normal((3, 300)), np.float32)
+        rng = np.random.default_rng(21)
+        g.set_nodes(300)
+        g.spread(X, F)
+        g.step(12)
+        out.append(N(g.populations()))
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+def test_stream_copy(gpu):
+    import torch
+
+    src = torch.arange(1 << 20, dtype=torch.float32, device=DEV)
+    for variant in (0, 1):
+        dst = torch.zeros_like(src)
+        gpu.stream_copy(src, dst, variant, 0 if variant == 0 else 512)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst)
+
+
 def test_multichannel_batch(orc, gpu):
     chans = [inputs.Channel(48, 32, 32, 0.75, u_wall_hi=(0.02, 0, 0), init="shear"),
              inputs.Channel(37, 21, 19, 1.1, body=(2e-6, 0, 0)),
@@ -308,18 +338,24 @@ def test_multichannel_batch(orc, gpu):
         assert emax(gpu_fields(g, c)[1], o.moments()[1]) <= TOL32
 
 
+@pytest.mark.parametrize("dims", [(45, 37, 29), (48, 20, 16)])
 @pytest.mark.parametrize("launch", [dict(block=64, xcd_remap=0), dict(block=1024, xcd_remap=1),
-                                    dict(block=256, persistent=97), dict(block=512, nontemporal=1)])
-def test_launch_shapes_agree(gpu, launch):
-    ch = inputs.Channel(45, 37, 29, 0.8, u_wall_hi=(0.05, 0, 0), init="shear")
+                                    dict(block=256, persistent=97), dict(block=512, nontemporal=1),
+                                    dict(vec=2), dict(vec=4, nontemporal=1), dict(vec=2, persistent=33),
+                                    dict(vec=4, xcd_remap=0)])
+def test_launch_shapes_agree(gpu, launch, dims):
+    """Every launch shape (scalar and vector steps) gives bitwise the same state; (48,20,16)
+    is eligible for the vector step, (45,37,29) falls back to the scalar one."""
+    ch = inputs.Channel(*dims, 0.8, u_wall_hi=(0.05, 0, 0.01), u_wall_lo=(0, 0, -0.02), init="shear",
+                        body=(1e-5, 0, 0))
     ref = gpu.Lattice([ch], device=DEV)
     ref.init()
     ref.step(10)
     g = gpu.Lattice([ch], device=DEV)
-    g.set_launch(**{**dict(block=256, xcd_remap=1, persistent=0, nontemporal=0), **launch})
+    g.set_launch(**{**dict(block=256, xcd_remap=1, persistent=0, nontemporal=0, vec=0), **launch})
     g.init()
     g.step(10)
-    assert np.array_equal(N(ref.moments()[1]), N(g.moments()[1]))
+    assert np.array_equal(N(ref.populations()), N(g.populations()))
 
 
 # ----------------------------------------------------------------------------- 16-bit storage
