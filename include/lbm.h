@@ -165,7 +165,7 @@ const char* lbm_status_string(lbm_status s);
  *   tethers  U = k_tether/2 |X - A|^2.
  * Connectivity is CSR so that every node gathers its own force (no atomics): a first pass
  * evaluates every hinge once into hinge_force, a second gathers per node.  All arrays are
- * device memory; rest_len / rest_theta are filled by ib_membrane_rest(). */
+ * device memory; rest_len / rest_cs are filled by ib_membrane_rest(). */
 typedef struct {
     int64_t n;                 /* nodes */
     const int32_t* nbr_ptr;    /* [n+1] CSR over spring neighbours (both directions) */
@@ -175,7 +175,7 @@ typedef struct {
     const int32_t* hinge_ptr;  /* [n+1] CSR node -> hinge incidences, or NULL */
     const int32_t* hinge_inc;  /* [nnz_h] (hinge id << 2) | role, role = slot 0..3 in the hinge */
     const int32_t* hinges;     /* [nh][4] (x0, x1, x2, x3): triangles (x0,x1,x2), (x3,x2,x1) */
-    double* rest_theta;        /* [nh] */
+    double* rest_cs;           /* [nh][2] cos and sin of the rest dihedral angle */
     int32_t* hinge_slot;       /* [nh][4] scratch: position of (hinge, role) in hinge_inc (set by
                                   ib_membrane_rest) */
     double* hinge_force;       /* [nh*4][3] scratch: bending force of each incidence, CSR order */

@@ -70,6 +70,7 @@ Layout layout_of(const lbm_params* p, int32_t nch, lbm_storage st, int64_t max_n
         L.rec = take(sizeof(float) * 20 * max_nodes);
         L.rank = take(sizeof(int32_t) * 27 * max_nodes);
         L.blkbase = take(sizeof(int32_t) * 2048 * ((max_nodes + 255) / 256));
+        L.nbase = take(sizeof(int4) * max_nodes);
         for (int k = 0; k < 2; ++k) {
             L.sets[k][0] = take(sizeof(int32_t) * sz.tiles);           // cnt
             L.sets[k][1] = take(sizeof(int32_t) * sz.tiles);           // tile_slot
@@ -81,7 +82,8 @@ Layout layout_of(const lbm_params* p, int32_t nch, lbm_storage st, int64_t max_n
         }
         L.list = take(sizeof(int32_t) * sz.list_cap);
         L.force = take(sizeof(float) * 3 * TILE_CELLS * sz.slots);
-        L.vel = take(sizeof(float) * 3 * TILE_CELLS * sz.slots);
+        L.vel = take(sizeof(float) * 4 * TILE_CELLS * sz.slots);
+
     }
     L.total = off;
     return L;
@@ -129,6 +131,7 @@ IbArgs ib_args(lbm_ctx* c, int set) {
     a.nch = c->nch;
     a.rank = c->d_rank;
     a.blkbase = c->d_blkbase;
+    a.nbase = c->d_nbase;
     return a;
 }
 
@@ -217,6 +220,7 @@ lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib
         c->d_list = (int32_t*)(c->ws + L.list);
         c->d_rank = (int32_t*)(c->ws + L.rank);
         c->d_blkbase = (int32_t*)(c->ws + L.blkbase);
+        c->d_nbase = (int4*)(c->ws + L.nbase);
         c->d_force = (float*)(c->ws + L.force);
         c->d_vel = (float*)(c->ws + L.vel);
     }
@@ -269,6 +273,13 @@ lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib
             if (st == LBM_OK)
                 st = hip_ok(launch_fill_i32(c->stream, (int32_t*)c->set[k].hdr, sizeof(IbHdr) / 4, 0));
         }
+
+    }
+    if (st == LBM_OK) {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            c->ib_grid = 4 * (int64_t)cus;
     }
     if (st != LBM_OK) {
         delete c;
@@ -429,7 +440,7 @@ lbm_status ib_advance(lbm_ctx* c, int64_t n, double* X, const float* U) {
 lbm_status ib_membrane_rest(const ib_membrane* m, const double* X_rest, void* stream) {
     if (!m || m->n < 0 || (m->n > 0 && !X_rest)) return LBM_ERR_ARG;
     if (m->nbr_ptr && (!m->nbr_idx || !m->rest_len)) return LBM_ERR_ARG;
-    if (m->nh > 0 && (!m->hinges || !m->rest_theta)) return LBM_ERR_ARG;
+    if (m->nh > 0 && (!m->hinges || !m->rest_cs)) return LBM_ERR_ARG;
     if (m->hinge_ptr && m->nh > 0 && (!m->hinge_inc || !m->hinge_slot)) return LBM_ERR_ARG;
     return hip_ok(launch_membrane_rest(m, X_rest, (hipStream_t)stream));
 }
@@ -437,7 +448,7 @@ lbm_status ib_membrane_rest(const ib_membrane* m, const double* X_rest, void* st
 lbm_status ib_membrane_forces(const ib_membrane* m, const double* X, float* F, void* stream) {
     if (!m || m->n < 0 || (m->n > 0 && (!X || !F))) return LBM_ERR_ARG;
     if (m->nbr_ptr && (!m->nbr_idx || !m->rest_len)) return LBM_ERR_ARG;
-    if (m->hinge_ptr && (!m->hinge_inc || !m->hinges || !m->rest_theta ||
+    if (m->hinge_ptr && (!m->hinge_inc || !m->hinges || !m->rest_cs ||
                          (m->nh > 0 && (!m->hinge_force || !m->hinge_slot))))
         return LBM_ERR_ARG;
     return hip_ok(launch_membrane_forces(m, X, F, (hipStream_t)stream));

@@ -175,6 +175,7 @@ __global__ void __launch_bounds__(256) k_ib_bin(IbArgs a) {
             }
         }
         if (bad) atomicOr(a.flags, LBM_FLAG_NODE_OUTSIDE);
+        a.nbase[m] = make_int4(b[0], b[1], b[2], c);
         r[0] = __int_as_float(b[0]);
         r[1] = __int_as_float(b[1]);
         r[2] = __int_as_float(b[2]);
@@ -303,7 +304,8 @@ __global__ void __launch_bounds__(1024) k_ib_scan(IbArgs a) {
             frexpf(fm, &e);  // fm < 2^e
             int L = 1;
             while ((1ll << L) < a.n) ++L;
-            s = 62 - e - L;
+            s = 62 - e - L;           // sum of <= n contributions below 2^59
+            if (s > 51 - e) s = 51 - e;  // one contribution below 2^48 (exact rounding trick)
         }
         a.set.hdr->scale_exp = s;
         if (carry > a.list_cap) atomicOr(a.flags, LBM_FLAG_LIST_OVERFLOW);
@@ -328,22 +330,71 @@ __global__ void __launch_bounds__(256) k_ib_scatter(IbArgs a) {
 }
 
 // ---------------------------------------------------------------- spread (LDS, fixed point)
-// Work item = (flagged tile, one of its eight 4x4x4 sub-tiles): the tile's node list is
-// scanned by all threads, each node adding its stencil points that fall in the sub-tile.
-__global__ void __launch_bounds__(256) k_ib_spread(IbArgs a) {
+// Work item = (flagged 8x8x8 tile, one of its eight 4x4x4 sub-tiles); the item owns the 64
+// cells of its sub-tile, so no item needs another's result.  The item scans the tile's node
+// list (stencil bases from the compact `nbase` array), keeps the nodes whose stencil box
+// overlaps the sub-tile together with the overlap box, turns the overlapping (node, point)
+// pairs into one flat index space by a block prefix sum, and lets every thread take an
+// equal contiguous range of pairs.  Each pair adds w_x w_y w_z F to a 64-bit fixed-point
+// LDS accumulator; integer sums are exact, so the result does not depend on the order in
+// which nodes were listed.
+constexpr int SP_THREADS = 1024;  // 16 wavefronts per item hide the LDS latency of the pair loop
+constexpr int SP_U = 1;           // list entries a thread loads at once while collecting
+constexpr int SP_BATCH = 1024;    // overlapping nodes held in LDS at a time (>= SP_U * SP_THREADS)
+constexpr int SP_WIN = 4096;     // pairs per owner-map window
+
+__device__ __forceinline__ long long fixed_round(float c, double scale) {
+    // round-to-nearest of c * scale for |c * scale| < 2^51: add 1.5 * 2^52 in double
+    const double x = (double)c * scale + 6755399441055744.0;
+    return __double_as_longlong(x) - 0x4338000000000000LL;
+}
+
+// Stencil points k = 0..3 of base b along one axis that fall in [s, s+4): first k, count and
+// the sub-tile-local coordinate of the first one.  Cells are taken modulo n when `wrap`,
+// else rows outside [0, n) are dropped.
+__device__ __forceinline__ void overlap(int b, int s, int n, bool wrap, int& lo, int& cnt, int& loc0) {
+    lo = 4;
+    cnt = 0;
+    loc0 = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int c = b + k;
+        bool ok = true;
+        if (wrap) {
+            if (c >= n) c -= n;
+        } else {
+            ok = c >= 0 && c < n;
+        }
+        const bool in = ok && (unsigned)(c - s) < 4u;
+        if (in && lo == 4) {
+            lo = k;
+            loc0 = c - s;
+        }
+        cnt += in;
+    }
+}
+
+// floor(j / d) for 0 <= j < 64 and d in 1..4
+__device__ __forceinline__ int div_small(int j, int d) {
+    const int inv = d == 1 ? 65536 : (d == 2 ? 32768 : (d == 3 ? 21846 : 16384));
+    return (j * inv) >> 16;
+}
+
+__global__ void __launch_bounds__(SP_THREADS) k_ib_spread(IbArgs a) {
     __shared__ unsigned long long acc[3 * 64];
+    __shared__ int box[SP_BATCH];       // per node: lo, cnt, local origin for x, y, z (3 bits each)
+    __shared__ float wf[15][SP_BATCH];  // per node: weights w_x[4], w_y[4], w_z[4], F[3]
+    __shared__ int pre[SP_BATCH + 1];
+    __shared__ unsigned short owner[SP_WIN];
+    __shared__ int ncand, wsum[SP_THREADS / 64];
     const int nf = a.set.hdr->nflag;
     const int sexp = a.set.hdr->scale_exp;
     const bool nonfinite = a.set.hdr->nonfinite != 0;
     const double scale = ldexp(1.0, sexp), inv = ldexp(1.0, -sexp);
-    // the eight sub-tiles of a tile go to workgroups dealt to the same XCD (the dispatcher
-    // deals workgroups round-robin over 8 XCDs), so the tile's node records stay in one L2
-    const int b = blockIdx.x;
-    const int first = (b & ~63) | ((b & 7) << 3) | ((b >> 3) & 7);
-    for (int wi = first; wi < nf * 8; wi += gridDim.x) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int wi = blockIdx.x; wi < nf * 8; wi += gridDim.x) {
         const int slot = wi >> 3, sub = wi & 7;
-        for (int k = threadIdx.x; k < 3 * 64; k += blockDim.x) acc[k] = 0ull;
-        __syncthreads();
+        for (int k = tid; k < 3 * 64; k += SP_THREADS) acc[k] = 0ull;
         const int T = a.set.flag_list[slot];
         const Chan& ch = a.chan[a.set.flag_ch[slot]];
         const int t = (int)(T - ch.tile_off);
@@ -352,39 +403,105 @@ __global__ void __launch_bounds__(256) k_ib_spread(IbArgs a) {
         const int sz = (t / (ch.tnx * ch.tny)) * TILE + 4 * (sub >> 2);
         int64_t beg = a.set.slot_off[slot], end = a.set.slot_off[slot + 1];
         if (end > a.list_cap) end = a.list_cap;
-        for (int64_t k = beg + threadIdx.x; k < end; k += blockDim.x) {
-            const int64_t m = a.list[k];
-            const float* r = a.rec + m * REC;
-            Stencil s;
-            stencil_cells(ch, __float_as_int(r[0]), __float_as_int(r[1]), __float_as_int(r[2]), s);
-            uint32_t mx = 0, my = 0, mz = 0;
+        for (int64_t scan0 = beg; scan0 < end;) {
+            // 1. collect overlapping nodes (with their weights and force) into LDS
+            if (tid == 0) ncand = 0;
+            __syncthreads();
+            int64_t scan = scan0;
+            for (; scan < end; scan += SP_U * SP_THREADS) {
+                int64_t mm[SP_U];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                mx |= ((unsigned)(s.x[q] - sx) < 4u) << q;
-                my |= (s.yok[q] && (unsigned)(s.y[q] - sy) < 4u) << q;
-                mz |= ((unsigned)(s.z[q] - sz) < 4u) << q;
-            }
-            if (!mx || !my || !mz) continue;
-            const float F0 = r[16], F1 = r[17], F2 = r[18];
-            for (int cz4 = 0; cz4 < 4; ++cz4) {
-                if (!((mz >> cz4) & 1)) continue;
-                for (int cy4 = 0; cy4 < 4; ++cy4) {
-                    if (!((my >> cy4) & 1)) continue;
-                    const float wyz = r[8 + cy4] * r[12 + cz4];
-                    for (int cx4 = 0; cx4 < 4; ++cx4) {
-                        if (!((mx >> cx4) & 1)) continue;
-                        const float ww = r[4 + cx4] * wyz;
-                        const int loc = ((s.z[cz4] - sz) << 4) | ((s.y[cy4] - sy) << 2) | (s.x[cx4] - sx);
-                        atomicAdd(&acc[loc], (unsigned long long)(long long)rint((double)(ww * F0) * scale));
-                        atomicAdd(&acc[64 + loc], (unsigned long long)(long long)rint((double)(ww * F1) * scale));
-                        atomicAdd(&acc[128 + loc], (unsigned long long)(long long)rint((double)(ww * F2) * scale));
+                for (int u = 0; u < SP_U; ++u) {
+                    const int64_t k = scan + tid + u * SP_THREADS;
+                    mm[u] = k < end ? (int64_t)a.list[k] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < SP_U; ++u) {
+                    if (mm[u] < 0) continue;
+                    const int4 nb = a.nbase[mm[u]];
+                    int lx, cnx, ox, ly, cny, oy, lz, cnz, oz;
+                    overlap(nb.x, sx, ch.nx, true, lx, cnx, ox);
+                    overlap(nb.y, sy, ch.ny, !ch.walls, ly, cny, oy);
+                    overlap(nb.z, sz, ch.nz, true, lz, cnz, oz);
+                    if (cnx && cny && cnz) {
+                        const int q = atomicAdd(&ncand, 1);
+                        box[q] = lx | (cnx << 3) | (ox << 6) | (ly << 9) | (cny << 12) | (oy << 15) | (lz << 18) |
+                                 (cnz << 21) | (oz << 24);
+                        const float* r = a.rec + mm[u] * REC;
+#pragma unroll
+                        for (int e = 0; e < 15; ++e) wf[e][q] = r[4 + e];
                     }
                 }
+                __syncthreads();
+                const int nowc = ncand;  // every thread reads the count before the next pass appends
+                __syncthreads();
+                if (nowc > SP_BATCH - SP_U * SP_THREADS) {
+                    scan += SP_U * SP_THREADS;
+                    break;
+                }
+            }
+            scan0 = scan;
+            const int nc = ncand;
+            // 2. pair counts -> exclusive prefix (block scan, chunks of SP_THREADS)
+            int carry = 0;
+            for (int base = 0; base < nc; base += SP_THREADS) {
+                const int q = base + tid;
+                int v = 0;
+                if (q < nc) {
+                    const int b = box[q];
+                    v = ((b >> 3) & 7) * ((b >> 12) & 7) * ((b >> 21) & 7);
+                }
+                int incl = v;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int u = __shfl_up(incl, d, 64);
+                    if (lane >= d) incl += u;
+                }
+                if (lane == 63) wsum[wave] = incl;
+                __syncthreads();
+                int woff = 0;
+                for (int w = 0; w < wave; ++w) woff += wsum[w];
+                if (q < nc) pre[q] = carry + woff + incl - v;
+                int tot = 0;
+                for (int w = 0; w < SP_THREADS / 64; ++w) tot += wsum[w];
+                __syncthreads();
+                carry += tot;
+            }
+            if (tid == 0) pre[nc] = carry;
+            __syncthreads();
+            // 3. pairs, in windows of SP_WIN: an owner map (pair -> node) is filled for the
+            //    window, then consecutive threads take consecutive pairs, so the lanes of a
+            //    wavefront mostly cover one node's stencil points (different cells)
+            const int P = pre[nc];
+            for (int w0 = 0; w0 < P; w0 += SP_WIN) {
+                const int w1 = w0 + SP_WIN < P ? w0 + SP_WIN : P;
+                for (int c = tid; c < nc; c += SP_THREADS) {
+                    int q0 = pre[c], q1 = pre[c + 1];
+                    if (q0 < w0) q0 = w0;
+                    if (q1 > w1) q1 = w1;
+                    for (int q = q0; q < q1; ++q) owner[q - w0] = (unsigned short)c;
+                }
+                __syncthreads();
+                for (int p = w0 + tid; p < w1; p += SP_THREADS) {
+                    const int c = owner[p - w0];
+                    const int j = p - pre[c];
+                    const int b = box[c];
+                    const int cnx = (b >> 3) & 7, cny = (b >> 12) & 7;
+                    const int jx = div_small(j, cnx);
+                    const int jy = div_small(jx, cny);
+                    const int ix = j - jx * cnx, iy = jx - jy * cny, iz = jy;
+                    const int da = (b & 7) + ix, db = ((b >> 9) & 7) + iy, dc = ((b >> 18) & 7) + iz;
+                    const int loc = ((((b >> 24) & 7) + iz) << 4) | ((((b >> 15) & 7) + iy) << 2) | (((b >> 6) & 7) + ix);
+                    const float ww = wf[da][c] * (wf[4 + db][c] * wf[8 + dc][c]);
+                    atomicAdd(&acc[loc], (unsigned long long)fixed_round(ww * wf[12][c], scale));
+                    atomicAdd(&acc[64 + loc], (unsigned long long)fixed_round(ww * wf[13][c], scale));
+                    atomicAdd(&acc[128 + loc], (unsigned long long)fixed_round(ww * wf[14][c], scale));
+                }
+                __syncthreads();
             }
         }
-        __syncthreads();
         float* out = a.force + (int64_t)slot * (3 * TILE_CELLS);
-        for (int k = threadIdx.x; k < 3 * 64; k += blockDim.x) {
+        for (int k = tid; k < 3 * 64; k += SP_THREADS) {
             const int d = k >> 6, l = k & 63;
             const int lx = (sx & 7) + (l & 3), ly = (sy & 7) + ((l >> 2) & 3), lz = (sz & 7) + (l >> 4);
             out[d * TILE_CELLS + ((lz << 6) | (ly << 3) | lx)] =
@@ -399,9 +516,12 @@ hipError_t launch_ib_spread(lbm_ctx* c, const IbArgs& a) {
     if (a.n > 0) k_ib_bin<<<dim3(nb), dim3(256), 0, c->stream>>>(a);
     k_ib_scan<<<dim3(1), dim3(1024), 0, c->stream>>>(a);
     if (a.n > 0) k_ib_scatter<<<dim3(nb), dim3(256), 0, c->stream>>>(a);
-    int64_t g = 8 * c->max_slots < 8192 ? 8 * c->max_slots : 8192;
-    g = (g + 63) & ~int64_t(63);  // whole groups of 64 for the XCD-aware mapping
-    k_ib_spread<<<dim3((unsigned)g), dim3(256), 0, c->stream>>>(a);
+    // the number of flagged tiles is only known on the device: a grid of a few workgroups
+    // per CU walks the work items (launching one workgroup per possible item costs more in
+    // empty waves than the work itself)
+    int64_t g = 8 * c->max_slots < c->ib_grid ? 8 * c->max_slots : c->ib_grid;
+    if (g < 1) g = 1;
+    k_ib_spread<<<dim3((unsigned)g), dim3(SP_THREADS), 0, c->stream>>>(a);
     return hipGetLastError();
 }
 
@@ -418,7 +538,7 @@ __global__ void __launch_bounds__(512) k_ib_vel(IbArgs a) {
         const int t = (int)(T_ - ch.tile_off);
         const int ox = (t % ch.tnx) * TILE, oy = ((t / ch.tnx) % ch.tny) * TILE, oz = (t / (ch.tnx * ch.tny)) * TILE;
         const float* fb = a.force + (int64_t)slot * (3 * TILE_CELLS);
-        float* vb = a.vel + (int64_t)slot * (3 * TILE_CELLS);
+        float4* vb = (float4*)(a.vel + (int64_t)slot * (4 * TILE_CELLS));
         for (int l = threadIdx.x; l < TILE_CELLS; l += blockDim.x) {
             const int x = ox + (l & 7), y = oy + ((l >> 3) & 7), z = oz + (l >> 6);
             if (x >= ch.nx || y >= ch.ny || z >= ch.nz) continue;
@@ -428,9 +548,9 @@ __global__ void __launch_bounds__(512) k_ib_vel(IbArgs a) {
             float drho, jx, jy, jz;
             moments(g, drho, jx, jy, jz);
             const float ir = 1.0f / (1.0f + drho);
-            vb[l] = (jx + 0.5f * (ch.body[0] + fb[l])) * ir;
-            vb[TILE_CELLS + l] = (jy + 0.5f * (ch.body[1] + fb[TILE_CELLS + l])) * ir;
-            vb[2 * TILE_CELLS + l] = (jz + 0.5f * (ch.body[2] + fb[2 * TILE_CELLS + l])) * ir;
+            vb[l] = make_float4((jx + 0.5f * (ch.body[0] + fb[l])) * ir,
+                                (jy + 0.5f * (ch.body[1] + fb[TILE_CELLS + l])) * ir,
+                                (jz + 0.5f * (ch.body[2] + fb[2 * TILE_CELLS + l])) * ir, 0.0f);
         }
     }
 }
@@ -469,23 +589,30 @@ __global__ void __launch_bounds__(256) k_ib_gather(IbArgs a) {
                 b[d] = wrapi(base, dim);
             }
         }
-        Stencil s;
-        stencil_cells(ch, b[0], b[1], b[2], s);
-        const float wyz = w[1][bq] * w[2][cq];
-        const int y = s.y[bq], z = s.z[cq];
+        // this lane's stencil row (y index bq, z index cq), selected without dynamic indexing
+        const float wy = bq == 0 ? w[1][0] : (bq == 1 ? w[1][1] : (bq == 2 ? w[1][2] : w[1][3]));
+        const float wz = cq == 0 ? w[2][0] : (cq == 1 ? w[2][1] : (cq == 2 ? w[2][2] : w[2][3]));
+        const float wyz = wy * wz;
+        int y = b[1] + bq;
+        bool yok = true;
+        if (ch.walls) yok = y >= 0 && y < ch.ny;
+        else if (y >= ch.ny) y -= ch.ny;
+        int z = b[2] + cq;
+        if (z >= ch.nz) z -= ch.nz;
 #pragma unroll
         for (int ax = 0; ax < 4; ++ax) {
             const float ww = w[0][ax] * wyz;
             float v0, v1, v2;
-            if (!s.yok[bq]) {
+            if (!yok) {
                 const float* uw = y < 0 ? ch.uw_lo : ch.uw_hi;
                 v0 = uw[0]; v1 = uw[1]; v2 = uw[2];
             } else {
-                const int x = s.x[ax];
+                int x = b[0] + ax;
+                if (x >= ch.nx) x -= ch.nx;
                 const int slot = a.set.tile_slot[tile_of(ch, x, y, z)];
                 if (slot >= 0) {
-                    const float* vb = a.vel + (int64_t)slot * (3 * TILE_CELLS) + tile_local(x, y, z);
-                    v0 = vb[0]; v1 = vb[TILE_CELLS]; v2 = vb[2 * TILE_CELLS];
+                    const float4 vb = ((const float4*)(a.vel + (int64_t)slot * (4 * TILE_CELLS)))[tile_local(x, y, z)];
+                    v0 = vb.x; v1 = vb.y; v2 = vb.z;
                 } else {  // not under any spread stencil: no IB force here
                     const int32_t n = x + ch.nx * (y + ch.ny * z);
                     float g[Q];
@@ -519,7 +646,7 @@ __global__ void __launch_bounds__(256) k_ib_gather(IbArgs a) {
 
 template <class St>
 static void launch_interp_typed(lbm_ctx* c, const IbArgs& a) {
-    int64_t g = c->max_slots < 4096 ? c->max_slots : 4096;
+    int64_t g = c->max_slots < c->ib_grid / 2 ? c->max_slots : c->ib_grid / 2;
     if (g < 1) g = 1;
     k_ib_vel<St><<<dim3((unsigned)g), dim3(512), 0, c->stream>>>(a);
     if (a.n > 0) k_ib_gather<St><<<dim3((unsigned)((16 * a.n + 255) / 256)), dim3(256), 0, c->stream>>>(a);
@@ -569,15 +696,18 @@ __device__ __forceinline__ double dt3(const double a[3], const double b[3]) {
 //   d/dx0 = -|e| nA/|nA|^2,  d/dx3 = -|e| nB/|nB|^2,
 //   d/dx1 = -((x0-x2).e/|e|) nA/|nA|^2 - ((x3-x2).e/|e|) nB/|nB|^2,
 //   d/dx2 =  ((x0-x1).e/|e|) nA/|nA|^2 + ((x3-x1).e/|e|) nB/|nB|^2.
-__device__ double hinge(const double x[4][3], double grad[4][3], bool want_grad) {
+// Returns cos(theta) and sin(theta); the energy only needs
+// sin(theta - theta0) = sin(theta) cos(theta0) - cos(theta) sin(theta0).
+__device__ void hinge(const double x[4][3], double grad[4][3], bool want_grad, double& cth, double& sth) {
     double a[3], b[3], nA[3], nB[3], e[3], cr[3];
     sub(x[1], x[0], a); sub(x[2], x[0], b); crs(a, b, nA);
     sub(x[2], x[3], a); sub(x[1], x[3], b); crs(a, b, nB);
     sub(x[2], x[1], e);
     const double AA = dt3(nA, nA), BB = dt3(nB, nB), L = sqrt(dt3(e, e));
-    const double la = sqrt(AA), lb = sqrt(BB);
+    const double iab = 1.0 / sqrt(AA * BB);
     crs(nA, nB, cr);
-    const double theta = atan2(dt3(cr, e) / (la * lb * L), dt3(nA, nB) / (la * lb));
+    cth = dt3(nA, nB) * iab;
+    sth = dt3(cr, e) * iab / L;
     if (want_grad) {
         double t0[3], t3[3];
         sub(x[0], x[2], t0); sub(x[3], x[2], t3);
@@ -592,7 +722,6 @@ __device__ double hinge(const double x[4][3], double grad[4][3], bool want_grad)
             grad[2][d] = c2A * qA + c2B * qB;
         }
     }
-    return theta;
 }
 
 __global__ void k_mem_rest(ib_membrane m, const double* X) {
@@ -607,9 +736,11 @@ __global__ void k_mem_rest(ib_membrane m, const double* X) {
         }
     }
     if (i < m.nh) {
-        double x[4][3], gdummy[4][3];
+        double x[4][3], gdummy[4][3], c, sn;
         for (int k = 0; k < 4; ++k) ld3(X, m.n, m.hinges[4 * i + k], x[k]);
-        m.rest_theta[i] = hinge(x, gdummy, false);
+        hinge(x, gdummy, false, c, sn);
+        m.rest_cs[2 * i] = c;
+        m.rest_cs[2 * i + 1] = sn;
     }
 }
 
@@ -619,8 +750,9 @@ __global__ void __launch_bounds__(256) k_mem_hinges(ib_membrane m, const double*
     if (h >= m.nh) return;
     double x[4][3], gr[4][3];
     for (int k = 0; k < 4; ++k) ld3(X, m.n, m.hinges[4 * h + k], x[k]);
-    const double th = hinge(x, gr, true);
-    const double dE = m.k_bend * sin(th - m.rest_theta[h]);
+    double c, sn;
+    hinge(x, gr, true, c, sn);
+    const double dE = m.k_bend * (sn * m.rest_cs[2 * h] - c * m.rest_cs[2 * h + 1]);
     for (int k = 0; k < 4; ++k) {
         double* out = m.hinge_force + 3 * (int64_t)m.hinge_slot[4 * h + k];
         for (int d = 0; d < 3; ++d) out[d] = -dE * gr[k][d];
@@ -633,14 +765,16 @@ __global__ void k_mem_hinge_slots(ib_membrane m, int64_t nnz) {
     if (e < nnz) m.hinge_slot[m.hinge_inc[e]] = (int32_t)e;
 }
 
-// Per node: springs (CSR), the hinge forces of its incidences, tether.
+// Per node (8 lanes each, partial sums combined by a fixed butterfly): springs (CSR), the
+// hinge forces of its incidences, tether.
 __global__ void __launch_bounds__(256) k_mem_forces(ib_membrane m, const double* X, float* Fout) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m.n) return;
-    double xi[3], xj[3], r[3], F[3] = {0.0, 0.0, 0.0};
-    ld3(X, m.n, i, xi);
-    if (m.nbr_ptr) {
-        for (int e = m.nbr_ptr[i]; e < m.nbr_ptr[i + 1]; ++e) {
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    const int sl = threadIdx.x & 7;
+    const bool valid = i < m.n;
+    double xi[3] = {0.0, 0.0, 0.0}, xj[3], r[3], F[3] = {0.0, 0.0, 0.0};
+    if (valid) ld3(X, m.n, i, xi);
+    if (valid && m.nbr_ptr) {
+        for (int e = m.nbr_ptr[i] + sl; e < m.nbr_ptr[i + 1]; e += 8) {
             ld3(X, m.n, m.nbr_idx[e], xj);
             sub(xj, xi, r);
             const double len = sqrt(dt3(r, r));
@@ -648,16 +782,23 @@ __global__ void __launch_bounds__(256) k_mem_forces(ib_membrane m, const double*
             F[0] += s * r[0]; F[1] += s * r[1]; F[2] += s * r[2];
         }
     }
-    if (m.hinge_ptr && m.k_bend != 0.0) {
-        for (int e = m.hinge_ptr[i]; e < m.hinge_ptr[i + 1]; ++e) {
+    if (valid && m.hinge_ptr && m.k_bend != 0.0) {
+        for (int e = m.hinge_ptr[i] + sl; e < m.hinge_ptr[i + 1]; e += 8) {
             const double* hf = m.hinge_force + 3 * (int64_t)e;
             F[0] += hf[0]; F[1] += hf[1]; F[2] += hf[2];
         }
     }
-    if (m.anchors) {
-        for (int d = 0; d < 3; ++d) F[d] -= m.k_tether * (xi[d] - m.anchors[d * m.n + i]);
+#pragma unroll
+    for (int d = 1; d < 8; d <<= 1) {
+        F[0] += __shfl_xor(F[0], d, 64);
+        F[1] += __shfl_xor(F[1], d, 64);
+        F[2] += __shfl_xor(F[2], d, 64);
     }
-    for (int d = 0; d < 3; ++d) Fout[d * m.n + i] = (float)F[d];
+    if (valid && sl == 0) {
+        if (m.anchors)
+            for (int d = 0; d < 3; ++d) F[d] -= m.k_tether * (xi[d] - m.anchors[d * m.n + i]);
+        for (int d = 0; d < 3; ++d) Fout[d * m.n + i] = (float)F[d];
+    }
 }
 
 hipError_t launch_membrane_rest(const ib_membrane* m, const double* X_rest, hipStream_t s) {
@@ -675,7 +816,7 @@ hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* 
     if (m->n <= 0) return hipSuccess;
     if (m->hinge_ptr && m->k_bend != 0.0 && m->nh > 0)
         k_mem_hinges<<<dim3((unsigned)((m->nh + 255) / 256)), dim3(256), 0, s>>>(*m, X);
-    k_mem_forces<<<dim3((unsigned)((m->n + 255) / 256)), dim3(256), 0, s>>>(*m, X, F);
+    k_mem_forces<<<dim3((unsigned)((8 * m->n + 255) / 256)), dim3(256), 0, s>>>(*m, X, F);
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ struct IbHdr {
     uint32_t fmax_bits;  // max |F| over the nodes (float bits)
     int32_t scale_exp;   // fixed-point scale 2^scale_exp of the spread accumulation
     int32_t nonfinite;   // 1 if a force was Inf/NaN
+    int32_t pad[4];
 };
 
 // Device arrays of one tile set.  Two sets alternate between successive spreads so
@@ -73,10 +74,11 @@ struct IbArgs {
     int32_t nch;
     int32_t* rank;          // [n][27] packed rank of a node in each tile list it joins
     int32_t* blkbase;       // [ceil(n/256)][2048] per-block base of each hashed tile
+    int4* nbase;            // [n] stencil base (x, y, z) and channel of every node
 };
 
 struct Layout {
-    size_t chan, seg_ch, popA, popB, flags, node_ch, rec, rank, blkbase, sets[2][7], list, force, vel, total;
+    size_t chan, seg_ch, popA, popB, flags, node_ch, rec, rank, blkbase, nbase, sets[2][7], list, force, vel, total;
 };
 
 }  // namespace lbmib
@@ -108,6 +110,8 @@ struct lbm_ctx {
     int32_t* d_list = nullptr;
     int32_t* d_rank = nullptr;
     int32_t* d_blkbase = nullptr;
+    int4* d_nbase = nullptr;
+    int64_t ib_grid = 1024;  // workgroups of the grid-stride IB kernels (set from the CU count)
     float* d_force = nullptr;
     float* d_vel = nullptr;
     lbm_launch launch{256, 1, 0, 1, 0};

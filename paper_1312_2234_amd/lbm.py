@@ -43,7 +43,7 @@ class LbmLaunch(C.Structure):
 class IbMembrane(C.Structure):
     _fields_ = [("n", C.c_int64), ("nbr_ptr", C.c_void_p), ("nbr_idx", C.c_void_p), ("rest_len", C.c_void_p),
                 ("k_spring", C.c_double), ("hinge_ptr", C.c_void_p), ("hinge_inc", C.c_void_p),
-                ("hinges", C.c_void_p), ("rest_theta", C.c_void_p), ("hinge_slot", C.c_void_p),
+                ("hinges", C.c_void_p), ("rest_cs", C.c_void_p), ("hinge_slot", C.c_void_p),
                 ("hinge_force", C.c_void_p),
                 ("nh", C.c_int64), ("k_bend", C.c_double),
                 ("anchors", C.c_void_p), ("k_tether", C.c_double)]
@@ -341,11 +341,11 @@ class Membrane:
         if len(bodies.hinges) and bodies.k_bend != 0.0:
             hp, hi = inputs.csr_hinges(n, bodies.hinges)
             hpt, hit, ht = dev_i32(hp), dev_i32(hi), dev_i32(bodies.hinges.reshape(-1))
-            rt = torch.zeros(len(bodies.hinges), dtype=torch.float64, device=dev)
+            rt = torch.zeros(2 * len(bodies.hinges), dtype=torch.float64, device=dev)
             hf = torch.zeros(12 * len(bodies.hinges), dtype=torch.float64, device=dev)
             hs = torch.zeros(4 * len(bodies.hinges), dtype=torch.int32, device=dev)
             self._keep += [rt, hf, hs]
-            s.hinge_ptr, s.hinge_inc, s.hinges, s.rest_theta = hpt.data_ptr(), hit.data_ptr(), ht.data_ptr(), rt.data_ptr()
+            s.hinge_ptr, s.hinge_inc, s.hinges, s.rest_cs = hpt.data_ptr(), hit.data_ptr(), ht.data_ptr(), rt.data_ptr()
             s.hinge_force, s.hinge_slot = hf.data_ptr(), hs.data_ptr()
             s.nh = len(bodies.hinges)
         s.k_bend = float(bodies.k_bend)
