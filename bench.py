@@ -37,6 +37,11 @@ def make_workload(name):
         desc = ("shear channel 256x128x128, top wall u=0.05, tau=1.0, 16 oblate platelets "
                 "(6,2,6) x 2562 IB nodes, spring k=0.005 + bending 1e-4")
         return [ch], desc
+    if name == "batched":
+        chans = inputs.batched_channels(seed=0)
+        desc = ("64 independent shear channels, sizes uniform over {48x32x32, 64x48x48, 96x64x64, 128x64x64}, "
+                "1-8 platelets of 642/2562 IB nodes, u_top U(0.01,0.05), tau U(0.7,1.2)")
+        return chans, desc
     if name == "sphere":
         ch = inputs.poiseuille_sphere(seed=0)
         return [ch], "32^3 body-force channel, tau=0.8, tethered 642-node sphere"
@@ -103,8 +108,10 @@ def main():
 
     launch, _ = tune.apply_cached_or_tune(lat, retune=args.tune)
     lat.init()
-    b = channels[0].bodies
-    lat.set_nodes(b.n)
+    from paper_1312_2234_amd import inputs
+
+    b, offs = inputs.concat_bodies(channels)
+    lat.set_nodes(b.n, offs if len(channels) > 1 else None)
     mem = lbm.Membrane(b, device=dev)
     X = torch.from_numpy(b.X.copy()).to(dev)
     F = torch.zeros((3, b.n), dtype=torch.float32, device=dev)
@@ -174,7 +181,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes_read"] = half
         del src, dst
-    if not args.no_cpu_baseline and args.cpu_steps > 0:
+    if not args.no_cpu_baseline and args.cpu_steps > 0 and len(channels) == 1:
         del lat
         out["cpu_baseline"] = cpu_baseline(channels, args.kernel, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -293,3 +293,30 @@ def batched_channels(seed=0, nch=64, sizes=BATCH_SIZES):
         b = platelets(rng, nx, ny, nz, count, (6.0, 2.0, 6.0), nodes, band, 0.005, 1e-4)
         out.append(Channel(nx, ny, nz, tau, u_wall_hi=(u, 0.0, 0.0), init="shear", bodies=b))
     return out
+
+
+def concat_bodies(channels):
+    """Bodies of several channels in one global node numbering (channel order), and the
+    node offsets of the channels (len(channels) + 1 entries)."""
+    Xs, Xr, E, H, A, offs = [], [], [], [], [], [0]
+    off = 0
+    ks = set()
+    for ch in channels:
+        b = ch.bodies
+        Xs.append(b.X)
+        Xr.append(b.X_rest)
+        E.append(b.edges + off)
+        H.append(b.hinges + off)
+        if b.anchors is not None:
+            A.append(b.anchors)
+        ks.add((b.k_spring, b.k_bend, b.k_tether))
+        off += b.n
+        offs.append(off)
+    if len(ks) != 1:
+        raise ValueError("channels must share the membrane constants")
+    k_spring, k_bend, k_tether = ks.pop()
+    anchors = np.ascontiguousarray(np.concatenate(A, axis=1)) if A and len(A) == len(channels) else None
+    b = Bodies(X=np.ascontiguousarray(np.concatenate(Xs, axis=1)), X_rest=np.ascontiguousarray(np.concatenate(Xr, axis=1)),
+               edges=np.concatenate(E).astype(np.int32), hinges=np.concatenate(H).astype(np.int32), anchors=anchors,
+               k_spring=k_spring, k_bend=k_bend, k_tether=k_tether, body_offsets=offs)
+    return b, offs

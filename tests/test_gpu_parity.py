@@ -338,6 +338,34 @@ def test_multichannel_batch(orc, gpu):
         assert emax(gpu_fields(g, c)[1], o.moments()[1]) <= TOL32
 
 
+def test_multichannel_coupled_ib(orc, gpu):
+    """Several channels of different size, tau, wall speed and platelet count in one context
+    (one launch per kernel for all of them) against an independent oracle per channel."""
+    import torch
+
+    chans = [inputs.shear_platelets(seed=7, nx=48, ny=32, nz=32, count=1, nodes=642, tau=0.75, u_top=0.02,
+                                    y_band=(8.0, 12.0)),
+             inputs.shear_platelets(seed=8, nx=64, ny=48, nz=48, count=2, nodes=642, tau=1.1, u_top=0.04),
+             inputs.shear_platelets(seed=9, nx=40, ny=24, nz=36, count=1, nodes=642, tau=0.9, u_top=0.03,
+                                    y_band=(6.0, 10.0))]
+    b, offs = inputs.concat_bodies(chans)
+    g = gpu.Lattice(chans, kernel="cos", max_nodes=b.n, device=DEV)
+    g.init()
+    g.set_nodes(b.n, offs)
+    mem = gpu.Membrane(b, device=DEV)
+    X = T(b.X)
+    F = torch.zeros((3, b.n), dtype=torch.float32, device=DEV)
+    U = torch.zeros_like(F)
+    g.coupled_steps(mem, 20, X, F, U)
+    torch.cuda.synchronize()
+    Xg, Ug = N(X), N(U)
+    for c, ch in enumerate(chans):
+        o, Xo, Uo = run_oracle_coupled(orc, ch, "cos", 20)
+        assert emax(gpu_fields(g, c)[1], o.moments()[1]) <= TOL32
+        assert emax(Ug[:, offs[c]:offs[c + 1]], Uo) <= TOL32
+    assert g.error_flags() == 0
+
+
 @pytest.mark.parametrize("dims", [(45, 37, 29), (48, 20, 16)])
 @pytest.mark.parametrize("launch", [dict(block=64, xcd_remap=0), dict(block=1024, xcd_remap=1),
                                     dict(block=256, persistent=97), dict(block=512, nontemporal=1),
