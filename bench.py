@@ -15,8 +15,10 @@ Prints ONE JSON line.  Besides the contract fields it carries:
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -46,6 +48,35 @@ def make_workload(name):
         ch = inputs.poiseuille_sphere(seed=0)
         return [ch], "32^3 body-force channel, tau=0.8, tethered 642-node sphere"
     raise SystemExit("unknown workload " + name)
+
+
+# Sources of the lattice kernel: a counter summary under profiles/ applies only while they are
+# unchanged (their SHA-256 is recorded in the summary).
+KERNEL_SOURCES = ("paper_1312_2234_amd/csrc/lattice.hip", "paper_1312_2234_amd/csrc/lbm_device.h",
+                  "paper_1312_2234_amd/csrc/lbm_internal.h")
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(storage, workload):
+    """HBM bytes per lattice launch from the committed FETCH_SIZE / WRITE_SIZE summary for this
+    storage form and workload (counter readings scaled by the same counters' reading of a plain
+    copy of known size), or None if there is none or the kernel's sources changed since."""
+    path = os.path.join(ROOT, "profiles", "k_step_%s_%s_hbm_counters.md" % (storage, workload))
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    sha = re.search(r"^sources_sha256:\s*([0-9a-f]{64})", text, re.M)
+    val = re.search(r"^traffic_bytes_per_launch:\s*(\d+)", text, re.M)
+    if not sha or not val or sha.group(1) != kernel_sources_sha256():
+        return None
+    return int(val.group(1))
 
 
 def cpu_baseline(channels, kernel, steps):
@@ -167,19 +198,19 @@ def main():
         "error_flags": flags,
         "roofline": {"bound": "hbm", "kernel": "k_step (lattice step)", "achieved": round(achieved / 1e9, 1),
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
-                     "traffic": None, "bytes_per_launch": bytes_launch,
+                     "traffic": measured_traffic(args.storage, args.workload), "bytes_per_launch": bytes_launch,
                      "avg_launch_us": round(ms_lbm * 1e3, 2),
                      "copy_ceiling_GBps": round(ceiling / 1e9, 1),
                      "frac_of_copy_ceiling": round(achieved / ceiling, 4)},
     }
     if args.copy_probe:
         half = bytes_launch // 2  # read half, write half: the same bytes as one lattice launch
-        src = torch.empty(half, dtype=torch.uint8, device=dev)
+        src = torch.empty(half // 16 * 16, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         for _ in range(4):
-            dst.copy_(src)
+            lbm.stream_copy(src, dst, 0, 0)
         torch.cuda.synchronize()
-        out["copy_probe_bytes_read"] = half
+        out["copy_probe_bytes_read"] = src.numel()
         del src, dst
     if not args.no_cpu_baseline and args.cpu_steps > 0 and len(channels) == 1:
         del lat
