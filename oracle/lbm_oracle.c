@@ -181,13 +181,10 @@ void orc_moments(const orc_params* p, const double* f, const double* g, double* 
     }
 }
 
-/* One LBM time step, Eq. (16), (19), (20), (reading R4 at walls):
- * collide  f*_i(x) = f_i - (f_i - f_i^eq(rho, v))/tau + S_i(v, F),
- * stream   f_i(x, t+1) = f*_i(x - c_i); across a wall
- *          f_i(x, t+1) = f*_{opp(i)}(x) + 6 w_i rho_w c_i.u_w. */
-void orc_step(const orc_params* p, const double* f, const double* g, double* fout) {
-    int64_t nx = p->nx, ny = p->ny, nz = p->nz, N = nx * ny * nz;
-    double* fs = (double*)malloc(sizeof(double) * Q * N);
+/* Collision of one LBM time step, Eq. (16), (19), (20):
+ * f*_i(x) = f_i - (f_i - f_i^eq(rho, v))/tau + S_i(v, F) at every node. */
+void orc_collide(const orc_params* p, const double* f, const double* g, double* fs) {
+    int64_t N = (int64_t)p->nx * p->ny * p->nz;
 #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; ++n) {
         double r = 0.0, j[3] = {0, 0, 0}, F[3], v[3], feq[Q], S[Q];
@@ -204,6 +201,12 @@ void orc_step(const orc_params* p, const double* f, const double* g, double* fou
         for (int i = 0; i < Q; ++i)
             fs[i * N + n] = f[i * N + n] - (f[i * N + n] - feq[i]) / p->tau + S[i];
     }
+}
+
+/* Streaming of one LBM time step (reading R4 at walls):
+ * f_i(x, t+1) = f*_i(x - c_i); across a wall f_i(x, t+1) = f*_{opp(i)}(x) + 6 w_i rho_w c_i.u_w. */
+void orc_stream(const orc_params* p, const double* fs, double* fout) {
+    int64_t nx = p->nx, ny = p->ny, nz = p->nz, N = nx * ny * nz;
 #pragma omp parallel for schedule(static)
     for (int64_t z = 0; z < nz; ++z)
         for (int64_t y = 0; y < ny; ++y)
@@ -223,6 +226,40 @@ void orc_step(const orc_params* p, const double* f, const double* g, double* fou
                     }
                 }
             }
+}
+
+/* Inverse of orc_stream: every post-collision value reaches exactly one pre-collision
+ * slot of the next step (a permutation plus the constant wall term), so
+ * f*_i(x - c_i) = f_i(x, t+1), and across a wall f*_{opp(i)}(x) = f_i(x, t+1) - 6 w_i c_i.u_w. */
+void orc_unstream(const orc_params* p, const double* f, double* fs) {
+    int64_t nx = p->nx, ny = p->ny, nz = p->nz, N = nx * ny * nz;
+#pragma omp parallel for schedule(static)
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                int64_t n = x + nx * (y + ny * z);
+                for (int i = 0; i < Q; ++i) {
+                    int64_t ys = y - CV[i][1];
+                    if (p->walls && (ys < 0 || ys >= ny)) {
+                        const double* uw = ys < 0 ? p->uw_lo : p->uw_hi;
+                        double cu = CV[i][0] * uw[0] + CV[i][1] * uw[1] + CV[i][2] * uw[2];
+                        fs[opposite(i) * N + n] = f[i * N + n] - 6.0 * WT[i] * 1.0 * cu;
+                    } else {
+                        int64_t xs = wrap(x - CV[i][0], nx);
+                        int64_t zs = wrap(z - CV[i][2], nz);
+                        ys = wrap(ys, ny);
+                        fs[i * N + xs + nx * (ys + ny * zs)] = f[i * N + n];
+                    }
+                }
+            }
+}
+
+/* One LBM time step, Eq. (16), (19), (20), (reading R4 at walls): collide, then stream. */
+void orc_step(const orc_params* p, const double* f, const double* g, double* fout) {
+    int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    double* fs = (double*)malloc(sizeof(double) * Q * N);
+    orc_collide(p, f, g, fs);
+    orc_stream(p, fs, fout);
     free(fs);
 }
 

@@ -56,6 +56,9 @@ def lib():
         L.orc_init.argtypes = [pp, dp, dp, dp]
         L.orc_moments.argtypes = [pp, dp, dp, dp, dp]
         L.orc_step.argtypes = [pp, dp, dp, dp]
+        L.orc_collide.argtypes = [pp, dp, dp, dp]
+        L.orc_stream.argtypes = [pp, dp, dp]
+        L.orc_unstream.argtypes = [pp, dp, dp]
         L.orc_spread.argtypes = [pp, C.c_int32, C.c_int64, dp, dp, dp]
         L.orc_interp.argtypes = [pp, C.c_int32, C.c_int64, dp, dp, dp]
         L.orc_advance.argtypes = [C.c_int64, dp, dp]
@@ -164,6 +167,24 @@ class Lattice:
         for _ in range(nsteps):
             lib().orc_step(C.byref(self.p), _d(self.f), _d(self.g), _d(out))
             self.f, out = out, self.f
+
+    def collide(self):
+        """Post-collision populations f* of the current state (Eq. 16, 19, 20); no update."""
+        fs = np.empty_like(self.f)
+        lib().orc_collide(C.byref(self.p), _d(self.f), _d(self.g), _d(fs))
+        return fs
+
+    def stream_from(self, fs):
+        """Set the state to the streamed post-collision populations `fs` (with bounce-back)."""
+        fs = np.ascontiguousarray(fs, dtype=np.float64)
+        lib().orc_stream(C.byref(self.p), _d(fs), _d(self.f))
+
+    def unstream(self, f):
+        """Post-collision populations that streaming maps onto `f` (inverse of stream_from)."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        fs = np.empty_like(f)
+        lib().orc_unstream(C.byref(self.p), _d(f), _d(fs))
+        return fs
 
     def moments(self):
         rho = np.empty(self.shape)
