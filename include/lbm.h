@@ -205,6 +205,80 @@ lbm_status lbm_graph_capture(lbm_ctx* ctx, const ib_membrane* m /*host*/, int32_
                              float* F, float* U);
 lbm_status lbm_graph_launch(lbm_ctx* ctx, int32_t repeats);
 
+/* ---------------------------------------------------------------- learned closure
+ * An extension of the collision step (the paper has none): a small network corrects the
+ * post-collision non-conserved moments of the forced BGK update of Eq. (16), (19), (20).
+ *   m    = M_nc (f - f^eq(rho, v))  the 15 non-equilibrium moments of the pre-collision
+ *          state in the orthonormal D3Q19 moment basis M (Gram-Schmidt of the monomials
+ *          1, x, y, z, x^2, y^2, z^2, xy, xz, yz, x^2y, x^2z, y^2x, y^2z, z^2x, z^2y,
+ *          x^2y^2, x^2z^2, y^2z^2 of the lattice velocities; M_nc = rows 4..18)
+ *   raw  = (m, |F_IB|)              16 inputs; F_IB the spread force at the cell
+ *   x    = (raw - in_mean) * in_scale, rounded to bfloat16
+ *   y    = W3^T relu(W2^T relu(W1^T x + b1) + b2) + b3   (hidden activations bfloat16,
+ *          float32 accumulation on the matrix cores)
+ *   dm   = y[0:15] * out_scale[0:15]
+ *   f*   = f*_BGK + M_nc^T dm  if dm is finite and |dm|_2 <= c_guard |m|_2, else f*_BGK
+ *          (the node falls back to the plain step: LBM_FLAG_CLOSURE_FALLBACK, counted).
+ * Mass and momentum are untouched (M_nc is orthogonal to 1 and c).
+ * Parameters: float32, flat, in the order W1[16][64], b1[64], W2[64][64], b2[64],
+ * W3[64][16], b3[16] (W[in][out]); norm: in_mean[16], in_scale[16], out_scale[16]. */
+#define MLP_PARAMS 6288
+#define MLP_NORM 48
+#define MLP_PACKED_BYTES 23360 /* bf16 matrix-core fragments + biases + scaling */
+
+/* Convert params / norm (device) into the packed form the kernels read (device,
+ * MLP_PACKED_BYTES, caller-owned), on `stream`. */
+lbm_status mlp_pack(const float* params, const float* norm, float c_guard, void* packed, void* stream);
+
+/* Enable (packs params / norm into the context's workspace; the inputs may be freed once the
+ * stream has passed this call) or disable (enable = 0, pointers ignored) the closure in every
+ * later lbm_step / coupled step of the context. */
+lbm_status lbm_set_closure(lbm_ctx* ctx, const float* params, const float* norm, float c_guard, int32_t enable);
+
+/* Synchronise the stream; return the number of node updates that fell back to the plain
+ * step since the last call, then reset it. */
+lbm_status lbm_closure_guarded(lbm_ctx* ctx, uint64_t* count /*host*/);
+
+/* Network only (no guard): dm[b][k] = y_k * out_scale_k for B samples of raw inputs
+ * raw[B][16] (device), output dm[B][16] (device; lane 15 is the unused output). */
+lbm_status mlp_forward(const void* packed, const float* raw, int64_t B, float* dm, void* stream);
+
+/* Gradient of the training loss L = sum_b sum_{k<15} (y_bk - t_bk)^2 / (15 B), with
+ * t = target / out_scale, with respect to the flat parameters (grad[MLP_PARAMS], device) and
+ * the loss itself (loss[1], device, may be NULL).  Forward and backward run on the BF16
+ * matrix cores (float32 accumulation, the backward signals rounded to bfloat16); partial
+ * sums of every workgroup are reduced in a fixed order, so the result is reproducible bit
+ * for bit.  work: mlp_grad_workspace_bytes(B) bytes of device scratch. */
+size_t mlp_grad_workspace_bytes(int64_t B);
+lbm_status mlp_grad(const void* packed, const float* raw, const float* target, int64_t B, float* grad,
+                    float* loss, void* work, size_t work_bytes, void* stream);
+
+/* Adam (Kingma & Ba 2015) on n float32 parameters: m, v are the moment buffers (zero at
+ * step 1), step counts from 1. */
+lbm_status mlp_adam(float* params, const float* grad, float* m, float* v, int64_t n, int32_t step, float lr,
+                    float beta1, float beta2, float eps, void* stream);
+
+/* Input / output scaling from B training samples: in_mean = mean(raw), in_scale =
+ * 1/std(raw) (1 where std = 0), out_scale = rms(target) (1 where 0); norm[MLP_NORM] device.
+ * work: mlp_norm_workspace_bytes(B) bytes of device scratch; fixed-order reduction. */
+size_t mlp_norm_workspace_bytes(int64_t B);
+lbm_status mlp_norm(const float* raw, const float* target, int64_t B, float* norm, void* work, size_t work_bytes,
+                    void* stream);
+
+/* Training data.  lbm_restrict: 2x restriction (acoustic scaling, dt_c = 2 dt_f) of the
+ * current state of a one-channel fine context with even nx, ny, nz into coarse shifted
+ * pre-collision populations g_c = f_c - w ([19][Nc], paper order, Nc = nx ny nz / 8):
+ * rho_c and j_c are the 2x2x2 block means, f_c = f^eq(rho_c, j_c/rho_c) + (2 tau_c / tau_f)
+ * * mean(f - f^eq(rho, j/rho)) (Dupuis & Chopard rescaling), and the coarse IB force
+ * density F_c = 2 mean(F_IB) ([3][Nc]) from the fine context's latest spread.
+ * closure_targets: for one coarse step from g0 (force body + F) to g1 (both shifted
+ * pre-collision, [19][N]) on the coarse channel `coarse` (host): raw features feat[N][16]
+ * of g0 and targets target[N][16] = (M_nc (unstream(g1) - collide(g0)), 0), where unstream
+ * inverts the streaming and bounce-back of the coarse step exactly. */
+lbm_status lbm_restrict(lbm_ctx* fine, float tau_coarse, float* g_c, float* F_c);
+lbm_status closure_targets(const lbm_params* coarse /*host*/, const float* g0, const float* F, const float* g1,
+                           float* feat, float* target, void* stream);
+
 /* ---------------------------------------------------------------- launch tuning
  * Launch shape of the lattice kernel, chosen by the autotuner (defaults are valid). */
 typedef struct {

@@ -65,6 +65,7 @@ Layout layout_of(const lbm_params* p, int32_t nch, lbm_storage st, int64_t max_n
     L.popA = take(elem_size(st) * Q * 64 * sz.segs);
     L.popB = take(elem_size(st) * Q * 64 * sz.segs);
     L.flags = take(64);
+    L.closure = take(sizeof(MlpPacked));
     if (max_nodes > 0) {
         L.node_ch = take(sizeof(int32_t) * max_nodes);
         L.rec = take(sizeof(float) * 20 * max_nodes);
@@ -205,6 +206,7 @@ lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib
     c->pop[0] = c->ws + L.popA;
     c->pop[1] = c->ws + L.popB;
     c->d_flags = (uint32_t*)(c->ws + L.flags);
+    c->d_mlp = (MlpPacked*)(c->ws + L.closure);
     if (max_nodes > 0) {
         c->d_node_ch = (int32_t*)(c->ws + L.node_ch);
         c->d_rec = (float*)(c->ws + L.rec);
@@ -311,7 +313,7 @@ lbm_status lbm_step(lbm_ctx* c, int32_t nsteps) {
     if (!c || nsteps < 0) return LBM_ERR_ARG;
     for (int s = 0; s < nsteps; ++s) {
         LatArgs a = lat_args(c);
-        hipError_t e = launch_lattice(c, LK_STEP, a);
+        hipError_t e = c->closure ? launch_step_closure(c, a) : launch_lattice(c, LK_STEP, a);
         if (e != hipSuccess) return LBM_ERR_HIP;
         c->cur ^= 1;
     }
@@ -467,7 +469,8 @@ static lbm_status coupled(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, doub
         a.F = F;
         if (launch_ib_spread(c, a) != hipSuccess) return LBM_ERR_HIP;
         LatArgs la = lat_args(c);
-        if (launch_lattice(c, LK_STEP, la) != hipSuccess) return LBM_ERR_HIP;
+        hipError_t e = c->closure ? launch_step_closure(c, la) : launch_lattice(c, LK_STEP, la);
+        if (e != hipSuccess) return LBM_ERR_HIP;
         c->cur ^= 1;
         IbArgs b = ib_args(c, c->ibset);
         b.X = X;
@@ -548,6 +551,114 @@ lbm_status lbm_stream_copy(const void* src, void* dst, size_t bytes, int32_t var
     if (!src || !dst || (bytes & 15) || variant < 0 || variant > 1 || grid < 0) return LBM_ERR_ARG;
     if (((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return LBM_ERR_ARG;
     return hip_ok(launch_copy16((hipStream_t)stream, src, dst, (int64_t)bytes, variant, grid));
+}
+
+// ---------------------------------------------------------------- learned closure
+namespace {
+constexpr int64_t MLP_GRID = 1024;  // fixed workgroup counts: results do not depend on the GPU
+constexpr int64_t NORM_GRID = 1024;
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+}  // namespace
+
+lbm_status mlp_pack(const float* params, const float* norm, float c_guard, void* packed, void* stream) {
+    if (!params || !norm || !packed || !(c_guard >= 0.0f) || !aligned16(packed)) return LBM_ERR_ARG;
+    return hip_ok(launch_mlp_pack((hipStream_t)stream, params, norm, c_guard, (MlpPacked*)packed));
+}
+
+lbm_status lbm_set_closure(lbm_ctx* c, const float* params, const float* norm, float c_guard, int32_t enable) {
+    if (!c) return LBM_ERR_ARG;
+    if (!enable) {
+        c->closure = false;
+        return LBM_OK;
+    }
+    lbm_status st = mlp_pack(params, norm, c_guard, c->d_mlp, c->stream);
+    if (st == LBM_OK) c->closure = true;
+    return st;
+}
+
+lbm_status lbm_closure_guarded(lbm_ctx* c, uint64_t* count) {
+    if (!c || !count) return LBM_ERR_ARG;
+    unsigned long long h = 0;
+    hipError_t e = hipMemcpyAsync(&h, c->d_flags + 2, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return LBM_ERR_HIP;
+    *count = (uint64_t)h;
+    return hip_ok(launch_fill_i32(c->stream, (int32_t*)(c->d_flags + 2), 2, 0));
+}
+
+lbm_status mlp_forward(const void* packed, const float* raw, int64_t B, float* dm, void* stream) {
+    if (!packed || B < 0 || (B > 0 && (!raw || !dm))) return LBM_ERR_ARG;
+    if (!aligned16(packed)) return LBM_ERR_ARG;
+    return hip_ok(launch_mlp_forward((hipStream_t)stream, (const MlpPacked*)packed, raw, B, dm, MLP_GRID));
+}
+
+size_t mlp_grad_workspace_bytes(int64_t B) {
+    if (B < 1) return 0;
+    return (size_t)mlp_grad_blocks(B, MLP_GRID) * (MLP_PARAMS + 1) * sizeof(float);
+}
+
+lbm_status mlp_grad(const void* packed, const float* raw, const float* target, int64_t B, float* grad, float* loss,
+                    void* work, size_t work_bytes, void* stream) {
+    if (!packed || !raw || !target || !grad || !work || B < 1 || !aligned16(packed)) return LBM_ERR_ARG;
+    if (work_bytes < mlp_grad_workspace_bytes(B)) return LBM_ERR_ARG;
+    const int64_t nblk = mlp_grad_blocks(B, MLP_GRID);
+    return hip_ok(launch_mlp_grad((hipStream_t)stream, (const MlpPacked*)packed, raw, target, B, (float*)work, nblk,
+                                  grad, loss));
+}
+
+lbm_status mlp_adam(float* params, const float* grad, float* m, float* v, int64_t n, int32_t step, float lr,
+                    float beta1, float beta2, float eps, void* stream) {
+    if (!params || !grad || !m || !v || n < 0 || step < 1) return LBM_ERR_ARG;
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f)) return LBM_ERR_ARG;
+    if (n == 0) return LBM_OK;
+    return hip_ok(launch_adam((hipStream_t)stream, params, grad, m, v, n, step, lr, beta1, beta2, eps));
+}
+
+static int64_t norm_blocks(int64_t B) {
+    const int64_t nb = (B + 15) / 16;
+    return nb < NORM_GRID ? nb : NORM_GRID;
+}
+
+size_t mlp_norm_workspace_bytes(int64_t B) { return B < 1 ? 0 : (size_t)norm_blocks(B) * 48 * sizeof(double); }
+
+lbm_status mlp_norm(const float* raw, const float* target, int64_t B, float* norm, void* work, size_t work_bytes,
+                    void* stream) {
+    if (!raw || !target || !norm || !work || B < 1) return LBM_ERR_ARG;
+    if (work_bytes < mlp_norm_workspace_bytes(B)) return LBM_ERR_ARG;
+    return hip_ok(launch_norm((hipStream_t)stream, raw, target, B, (double*)work, (int)norm_blocks(B), norm));
+}
+
+lbm_status lbm_restrict(lbm_ctx* c, float tau_coarse, float* g_c, float* F_c) {
+    if (!c || !g_c || !F_c || !(tau_coarse > 0.5f)) return LBM_ERR_ARG;
+    if (c->nch != 1) return LBM_ERR_UNSUPPORTED;
+    const lbm_params& p = c->params[0];
+    if ((p.nx & 1) || (p.ny & 1) || (p.nz & 1)) return LBM_ERR_UNSUPPORTED;
+    LatArgs a = lat_args(c);
+    return hip_ok(launch_restrict(c, a, 2.0f * tau_coarse / p.tau, g_c, F_c));
+}
+
+lbm_status closure_targets(const lbm_params* coarse, const float* g0, const float* F, const float* g1, float* feat,
+                           float* target, void* stream) {
+    if (!valid_params(coarse, 1) || !g0 || !F || !g1 || !feat || !target) return LBM_ERR_ARG;
+    Chan ch;
+    memset(&ch, 0, sizeof(ch));
+    ch.nx = coarse->nx;
+    ch.ny = coarse->ny;
+    ch.nz = coarse->nz;
+    ch.walls = coarse->walls;
+    ch.ncell = (int64_t)coarse->nx * coarse->ny * coarse->nz;
+    fast_div((uint32_t)ch.nx, ch.mx, ch.sx);
+    fast_div((uint32_t)ch.ny, ch.my, ch.sy);
+    ch.tau = coarse->tau;
+    ch.omega = 1.0f / coarse->tau;
+    ch.guo = 1.0f - 0.5f / coarse->tau;
+    for (int q = 0; q < 3; ++q) {
+        ch.body[q] = coarse->body_force[q];
+        ch.uw_lo[q] = coarse->u_wall_lo[q];
+        ch.uw_hi[q] = coarse->u_wall_hi[q];
+    }
+    return hip_ok(launch_targets((hipStream_t)stream, ch, g0, F, g1, feat, target));
 }
 
 }  // extern "C"

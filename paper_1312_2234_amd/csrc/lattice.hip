@@ -14,46 +14,6 @@
 
 namespace lbmib {
 
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
-    const int64_t per = G >> 3, rem = G & 7, x = b & 7;
-    return x * per + (x < rem ? x : rem) + (b >> 3);
-}
-
-// Iterate the segments assigned to this wavefront; body(ch, n) runs for every valid cell.
-template <class Body>
-__device__ __forceinline__ void for_cells(const LatArgs& a, Body body) {
-    const int wpb = blockDim.x >> 6;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int64_t G = gridDim.x;
-    int64_t L = a.remap ? xcd_remap(blockIdx.x, G) : (int64_t)blockIdx.x;
-    for (;; L += G) {
-        const int64_t seg = L * wpb + wave;
-        if (seg >= a.nseg) break;
-        const int c = a.seg_ch[seg];
-        const Chan& ch = a.chan[c];
-        const int64_t n = (seg - ch.seg_off) * 64 + lane;
-        if (n < ch.ncell) body(ch, (int32_t)n);
-        if (!a.persistent) break;
-    }
-}
-
-__device__ __forceinline__ void ib_force(const LatArgs& a, const Chan& ch, int x, int y, int z, float& Fx,
-                                         float& Fy, float& Fz) {
-    Fx = ch.body[0];
-    Fy = ch.body[1];
-    Fz = ch.body[2];
-    if (a.tile_slot) {
-        const int slot = a.tile_slot[tile_of(ch, x, y, z)];
-        if (slot >= 0) {
-            const float* fb = a.force + (int64_t)slot * (3 * TILE_CELLS) + tile_local(x, y, z);
-            Fx += fb[0];
-            Fy += fb[TILE_CELLS];
-            Fz += fb[2 * TILE_CELLS];
-        }
-    }
-}
-
 // ---------------------------------------------------------------- one LBM step
 // For every cell: pull (with bounce-back), moments (Eq. (17)-(18)), v = (j + F/2)/rho,
 // shifted equilibrium of Eq. (20), Guo source of Eq. (19) (minus sign on the c_s^2 I
@@ -72,19 +32,11 @@ __global__ void __launch_bounds__(1024) k_step(LatArgs a) {
         float drho, jx, jy, jz, Fx, Fy, Fz;
         moments(g, drho, jx, jy, jz);
         ib_force(a, ch, x, y, z, Fx, Fy, Fz);
-        const float rho = 1.0f + drho;
-        const float ir = 1.0f / rho;
-        const float vx = (jx + 0.5f * Fx) * ir, vy = (jy + 0.5f * Fy) * ir, vz = (jz + 0.5f * Fz) * ir;
-        const float vv15 = 1.5f * (vx * vx + vy * vy + vz * vz);
-        const float vF3 = 3.0f * (vx * Fx + vy * Fy + vz * Fz);
+        const CellState cs = cell_state(drho, jx, jy, jz, Fx, Fy, Fz);
         const float om = ch.omega, guo = ch.guo;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const float cu = cx(i) * vx + cy(i) * vy + cz(i) * vz;
-            const float cF = cx(i) * Fx + cy(i) * Fy + cz(i) * Fz;
-            const float geq = wgt(i) * (drho + rho * (3.0f * cu + 4.5f * cu * cu - vv15));
-            const float S = wgt(i) * guo * (3.0f * cF + 9.0f * cu * cF - vF3);
-            const float gn = g[i] - om * (g[i] - geq) + S;
+            const float gn = bgk_c(i, g[i], cs, om, guo);
             if (NT)
                 St::st_nt(d + pidx(i, n), gn);
             else
@@ -176,34 +128,22 @@ __global__ void __launch_bounds__(256) k_step_v(LatArgs a) {
                 }
             }
         }
-        float drho[V], rho[V], vx[V], vy[V], vz[V], vv15[V], vF3[V];
+        CellState cs[V];
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             float gk[Q];
 #pragma unroll
             for (int i = 0; i < Q; ++i) gk[i] = g[i][k];
-            float jx, jy, jz;
-            moments(gk, drho[k], jx, jy, jz);
-            rho[k] = 1.0f + drho[k];
-            const float ir = 1.0f / rho[k];
-            vx[k] = (jx + 0.5f * Fx[k]) * ir;
-            vy[k] = (jy + 0.5f * Fy[k]) * ir;
-            vz[k] = (jz + 0.5f * Fz[k]) * ir;
-            vv15[k] = 1.5f * (vx[k] * vx[k] + vy[k] * vy[k] + vz[k] * vz[k]);
-            vF3[k] = 3.0f * (vx[k] * Fx[k] + vy[k] * Fy[k] + vz[k] * Fz[k]);
+            float drho, jx, jy, jz;
+            moments(gk, drho, jx, jy, jz);
+            cs[k] = cell_state(drho, jx, jy, jz, Fx[k], Fy[k], Fz[k]);
         }
         const float om = ch.omega, guo = ch.guo;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             float out[V];
 #pragma unroll
-            for (int k = 0; k < V; ++k) {
-                const float cu = cx(i) * vx[k] + cy(i) * vy[k] + cz(i) * vz[k];
-                const float cF = cx(i) * Fx[k] + cy(i) * Fy[k] + cz(i) * Fz[k];
-                const float geq = wgt(i) * (drho[k] + rho[k] * (3.0f * cu + 4.5f * cu * cu - vv15[k]));
-                const float S = wgt(i) * guo * (3.0f * cF + 9.0f * cu * cF - vF3[k]);
-                out[k] = g[i][k] - om * (g[i][k] - geq) + S;
-            }
+            for (int k = 0; k < V; ++k) out[k] = bgk_c(i, g[i][k], cs[k], om, guo);
             stv<St, V, NT>(d + pidx(i, n0), out);
         }
         if (!a.persistent) break;
@@ -211,33 +151,6 @@ __global__ void __launch_bounds__(256) k_step_v(LatArgs a) {
 }
 
 // ---------------------------------------------------------------- initial state
-// Shifted equilibrium of Eq. (20) at rho = 1 + drho and velocity u.
-__device__ __forceinline__ float geq_i(int i, float drho, float ux, float uy, float uz) {
-    const float rho = 1.0f + drho;
-    const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
-    return wgt(i) * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * (ux * ux + uy * uy + uz * uz)));
-}
-
-// Cell reached from (x,y,z) along +c_i (x, z periodic; y periodic only without walls).
-// Returns false if +c_i leaves through a wall.
-__device__ __forceinline__ bool step_out(const Chan& ch, int i, int x, int y, int z, int32_t& m) {
-    int xs = x + cx(i), ys = y + cy(i), zs = z + cz(i);
-    if (ys < 0 || ys >= ch.ny) {
-        if (ch.walls) return false;
-        ys = ys < 0 ? ys + ch.ny : ys - ch.ny;
-    }
-    xs = xs < 0 ? xs + ch.nx : (xs >= ch.nx ? xs - ch.nx : xs);
-    zs = zs < 0 ? zs + ch.nz : (zs >= ch.nz ? zs - ch.nz : zs);
-    m = xs + ch.nx * (ys + ch.ny * zs);
-    return true;
-}
-
-__device__ __forceinline__ float wall_term(const Chan& ch, int i) {
-    // population i leaving through the wall on its own side: c_iy = +1 -> upper, -1 -> lower
-    const float* u = cy(i) > 0 ? ch.uw_hi : ch.uw_lo;
-    return 6.0f * wgt(i) * (cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2]);
-}
-
 // Un-stream: store s_i(x) such that the next pull yields the wanted pre-collision state
 // h_i at every cell: s_i(x) = h_i(x + c_i), or h_opp(i)(x) + 6 w_i c_i.u_w when x + c_i
 // is beyond a wall (the inverse of the bounce-back in `pull`).

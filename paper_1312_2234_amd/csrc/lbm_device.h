@@ -180,6 +180,89 @@ __device__ __forceinline__ void moments(const float g[Q], float& drho, float& jx
     drho = r; jx = a; jy = b; jz = c;
 }
 
+// Shifted equilibrium of Eq. (20) at rho = 1 + drho and velocity u.
+__device__ __forceinline__ float geq_i(int i, float drho, float ux, float uy, float uz) {
+    const float rho = 1.0f + drho;
+    const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+    return wgt(i) * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * (ux * ux + uy * uy + uz * uz)));
+}
+
+// Cell reached from (x,y,z) along +c_i (x, z periodic; y periodic only without walls).
+// Returns false if +c_i leaves through a wall.
+__device__ __forceinline__ bool step_out(const Chan& ch, int i, int x, int y, int z, int32_t& m) {
+    int xs = x + cx(i), ys = y + cy(i), zs = z + cz(i);
+    if (ys < 0 || ys >= ch.ny) {
+        if (ch.walls) return false;
+        ys = ys < 0 ? ys + ch.ny : ys - ch.ny;
+    }
+    xs = xs < 0 ? xs + ch.nx : (xs >= ch.nx ? xs - ch.nx : xs);
+    zs = zs < 0 ? zs + ch.nz : (zs >= ch.nz ? zs - ch.nz : zs);
+    m = xs + ch.nx * (ys + ch.ny * zs);
+    return true;
+}
+
+__device__ __forceinline__ float wall_term(const Chan& ch, int i) {
+    // population i leaving through the wall on its own side: c_iy = +1 -> upper, -1 -> lower
+    const float* u = cy(i) > 0 ? ch.uw_hi : ch.uw_lo;
+    return 6.0f * wgt(i) * (cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2]);
+}
+
+// ---------------------------------------------------------------- forced BGK collision
+// Eq. (16) with the equilibrium of Eq. (20) and the Guo source of Eq. (19) (minus sign on
+// the c_s^2 I term), in shifted variables.  Every rounding is fixed here (explicit fused
+// multiply-adds, no contraction left to the compiler), so that each kernel applying the
+// collision -- the plain step, its vector form and the closure step -- gives the same bits.
+struct CellState {
+    float drho, rho, vx, vy, vz, Fx, Fy, Fz, vv15, vF3;
+};
+
+// v = (j + F/2) / rho, 1.5 v.v and 3 v.F
+__device__ __forceinline__ CellState cell_state(float drho, float jx, float jy, float jz, float Fx, float Fy,
+                                                float Fz) {
+#pragma clang fp contract(off)
+    CellState s;
+    s.drho = drho;
+    s.rho = 1.0f + drho;
+    const float ir = 1.0f / s.rho;
+    s.vx = fmaf(0.5f, Fx, jx) * ir;
+    s.vy = fmaf(0.5f, Fy, jy) * ir;
+    s.vz = fmaf(0.5f, Fz, jz) * ir;
+    s.Fx = Fx;
+    s.Fy = Fy;
+    s.Fz = Fz;
+    s.vv15 = 1.5f * fmaf(s.vx, s.vx, fmaf(s.vy, s.vy, s.vz * s.vz));
+    s.vF3 = 3.0f * fmaf(s.vx, Fx, fmaf(s.vy, Fy, s.vz * Fz));
+    return s;
+}
+
+// c_i . (x, y, z) for the compile-time direction i (additions only)
+__device__ __forceinline__ float cdot(int i, float x, float y, float z) {
+#pragma clang fp contract(off)
+    float r = 0.0f;
+    bool any = false;
+    if (cx(i) != 0) { r = cx(i) > 0 ? x : -x; any = true; }
+    if (cy(i) != 0) { r = any ? (cy(i) > 0 ? r + y : r - y) : (cy(i) > 0 ? y : -y); any = true; }
+    if (cz(i) != 0) { r = any ? (cz(i) > 0 ? r + z : r - z) : (cz(i) > 0 ? z : -z); any = true; }
+    return r;
+}
+
+// shifted equilibrium w_i (drho + rho (3 c.v + 4.5 (c.v)^2 - 1.5 v.v))
+__device__ __forceinline__ float geq_c(int i, const CellState& s) {
+#pragma clang fp contract(off)
+    const float cu = cdot(i, s.vx, s.vy, s.vz);
+    return wgt(i) * fmaf(s.rho, fmaf(fmaf(4.5f, cu, 3.0f), cu, -s.vv15), s.drho);
+}
+
+// post-collision shifted population g - (g - geq)/tau + S_i
+__device__ __forceinline__ float bgk_c(int i, float g, const CellState& s, float om, float guo) {
+#pragma clang fp contract(off)
+    const float cu = cdot(i, s.vx, s.vy, s.vz);
+    const float cF = cdot(i, s.Fx, s.Fy, s.Fz);
+    const float geq = geq_c(i, s);
+    const float S = (wgt(i) * guo) * fmaf(fmaf(9.0f, cu, 3.0f), cF, -s.vF3);
+    return fmaf(-om, g - geq, g) + S;
+}
+
 // IB force-field lookup: tile of the cell -> slot (or -1) -> [3][512] block.
 __device__ __forceinline__ int64_t tile_of(const Chan& ch, int x, int y, int z) {
     return ch.tile_off + (x >> 3) + (int64_t)ch.tnx * ((y >> 3) + (int64_t)ch.tny * (z >> 3));

@@ -77,8 +77,63 @@ struct IbArgs {
     int4* nbase;            // [n] stencil base (x, y, z) and channel of every node
 };
 
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
+    const int64_t per = G >> 3, rem = G & 7, x = b & 7;
+    return x * per + (x < rem ? x : rem) + (b >> 3);
+}
+
+// Iterate the segments assigned to this wavefront; body(ch, n) runs for every valid cell.
+template <class Body>
+__device__ __forceinline__ void for_cells(const LatArgs& a, Body body) {
+    const int wpb = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t G = gridDim.x;
+    int64_t L = a.remap ? xcd_remap(blockIdx.x, G) : (int64_t)blockIdx.x;
+    for (;; L += G) {
+        const int64_t seg = L * wpb + wave;
+        if (seg >= a.nseg) break;
+        const int c = a.seg_ch[seg];
+        const Chan& ch = a.chan[c];
+        const int64_t n = (seg - ch.seg_off) * 64 + lane;
+        if (n < ch.ncell) body(ch, (int32_t)n);
+        if (!a.persistent) break;
+    }
+}
+
+__device__ __forceinline__ void ib_force(const LatArgs& a, const Chan& ch, int x, int y, int z, float& Fx,
+                                         float& Fy, float& Fz) {
+    Fx = ch.body[0];
+    Fy = ch.body[1];
+    Fz = ch.body[2];
+    if (a.tile_slot) {
+        const int slot = a.tile_slot[tile_of(ch, x, y, z)];
+        if (slot >= 0) {
+            const float* fb = a.force + (int64_t)slot * (3 * TILE_CELLS) + tile_local(x, y, z);
+            Fx += fb[0];
+            Fy += fb[TILE_CELLS];
+            Fz += fb[2 * TILE_CELLS];
+        }
+    }
+}
+
+// Packed learned-closure network (device): BF16 weight fragments in the matrix-core
+// operand order, FP32 biases and the input / output scaling.
+constexpr int MLP_NIN = 16, MLP_NH = 64, MLP_NOUT = 16, MLP_NNC = 15;
+constexpr int MLP_NFRAG = 24;      // forward: 4 (16x64) + 16 (64x64) + 4 (64x16) tiles of 16x16
+constexpr int MLP_NFRAG_ALL = 44;  // + backward: 4 (W3) + 16 (W2) transposed tiles
+struct MlpPacked {
+    uint16_t frag[MLP_NFRAG_ALL][64][4];  // lane-major A operands, 4 bf16 per lane
+    float bias[MLP_NH + MLP_NH + MLP_NOUT];
+    float norm[3 * MLP_NIN];          // in_mean[16], in_scale[16], out_scale[16]
+    float c_guard;
+    float pad[15];
+};
+static_assert(sizeof(MlpPacked) == MLP_PACKED_BYTES, "packed network size");
+
 struct Layout {
-    size_t chan, seg_ch, popA, popB, flags, node_ch, rec, rank, blkbase, nbase, sets[2][7], list, force, vel, total;
+    size_t chan, seg_ch, popA, popB, flags, closure, node_ch, rec, rank, blkbase, nbase, sets[2][7], list, force,
+        vel, total;
 };
 
 }  // namespace lbmib
@@ -115,6 +170,8 @@ struct lbm_ctx {
     float* d_force = nullptr;
     float* d_vel = nullptr;
     lbm_launch launch{256, 1, 0, 1, 0};
+    lbmib::MlpPacked* d_mlp = nullptr;
+    bool closure = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
 };
@@ -134,5 +191,21 @@ hipError_t launch_ib_interp(lbm_ctx* c, const IbArgs& a);
 hipError_t launch_ib_advance(hipStream_t s, int64_t n, double* X, const float* U);
 hipError_t launch_membrane_rest(const ib_membrane* m, const double* X_rest, hipStream_t s);
 hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* F, hipStream_t s);
+
+// closure.hip
+hipError_t launch_mlp_pack(hipStream_t s, const float* params, const float* norm, float c_guard, MlpPacked* P);
+hipError_t launch_step_closure(lbm_ctx* c, const LatArgs& a);
+hipError_t launch_mlp_forward(hipStream_t s, const MlpPacked* P, const float* raw, int64_t B, float* dm,
+                              int64_t grid_max);
+int64_t mlp_grad_blocks(int64_t B, int64_t grid_max);
+hipError_t launch_mlp_grad(hipStream_t s, const MlpPacked* P, const float* raw, const float* tgt, int64_t B,
+                           float* partial, int64_t nblk, float* grad, float* loss);
+hipError_t launch_adam(hipStream_t s, float* th, const float* g, float* m, float* v, int64_t n, int step, float lr,
+                       float b1, float b2, float eps);
+hipError_t launch_norm(hipStream_t s, const float* raw, const float* tgt, int64_t B, double* part, int nblk,
+                       float* norm);
+hipError_t launch_restrict(lbm_ctx* c, const LatArgs& a, float resc, float* gc, float* Fc);
+hipError_t launch_targets(hipStream_t s, const Chan& ch, const float* g0, const float* F, const float* g1,
+                          float* feat, float* target);
 
 }  // namespace lbmib

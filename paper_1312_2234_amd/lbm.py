@@ -25,8 +25,14 @@ EXPORTS = [
     "lbm_set_populations", "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_wall_stress",
     "lbm_error_flags", "lbm_status_string", "ib_membrane_rest", "ib_membrane_forces",
     "lbm_coupled_steps", "lbm_graph_capture", "lbm_graph_launch", "lbm_set_launch", "lbm_get_launch",
-    "lbm_stream_copy",
+    "lbm_stream_copy", "mlp_pack", "lbm_set_closure", "lbm_closure_guarded", "mlp_forward",
+    "mlp_grad_workspace_bytes", "mlp_grad", "mlp_adam", "mlp_norm_workspace_bytes", "mlp_norm",
+    "lbm_restrict", "closure_targets",
 ]
+
+MLP_PARAMS, MLP_NORM, MLP_PACKED_BYTES = 6288, 48, 23360
+_SIZE_FNS = ("lbm_workspace_bytes", "lbm_state_bytes", "lbm_status_string", "mlp_grad_workspace_bytes",
+             "mlp_norm_workspace_bytes")
 
 
 class LbmParams(C.Structure):
@@ -91,8 +97,22 @@ def lib():
         L.lbm_set_launch.argtypes = [vp, C.POINTER(LbmLaunch)]
         L.lbm_get_launch.argtypes = [vp, C.POINTER(LbmLaunch)]
         L.lbm_stream_copy.argtypes = [vp, vp, C.c_size_t, i32, i64, vp]
+        f32 = C.c_float
+        L.mlp_pack.argtypes = [vp, vp, f32, vp, vp]
+        L.lbm_set_closure.argtypes = [vp, vp, vp, f32, i32]
+        L.lbm_closure_guarded.argtypes = [vp, C.POINTER(C.c_uint64)]
+        L.mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.mlp_grad_workspace_bytes.argtypes = [i64]
+        L.mlp_grad_workspace_bytes.restype = C.c_size_t
+        L.mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp, C.c_size_t, vp]
+        L.mlp_adam.argtypes = [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp]
+        L.mlp_norm_workspace_bytes.argtypes = [i64]
+        L.mlp_norm_workspace_bytes.restype = C.c_size_t
+        L.mlp_norm.argtypes = [vp, vp, i64, vp, vp, C.c_size_t, vp]
+        L.lbm_restrict.argtypes = [vp, f32, vp, vp]
+        L.closure_targets.argtypes = [P, vp, vp, vp, vp, vp, vp]
         for name in EXPORTS:
-            if name not in ("lbm_workspace_bytes", "lbm_state_bytes", "lbm_status_string"):
+            if name not in _SIZE_FNS:
                 getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -290,6 +310,31 @@ class Lattice:
         with self.ordered:
             _check(lib().lbm_graph_launch(self.h, int(repeats)), "lbm_graph_launch")
 
+    # -- learned closure
+    def set_closure(self, params=None, norm=None, c_guard=1.0, enable=True):
+        """Enable the learned closure with float32 device tensors params[6288], norm[48]
+        (or disable it with enable=False)."""
+        with self.ordered:
+            _check(lib().lbm_set_closure(self.h, _ptr(params) if enable else None, _ptr(norm) if enable else None,
+                                         float(c_guard), 1 if enable else 0), "lbm_set_closure")
+
+    def closure_guarded(self):
+        n = C.c_uint64()
+        with self.ordered:
+            _check(lib().lbm_closure_guarded(self.h, C.byref(n)), "lbm_closure_guarded")
+        return n.value
+
+    def restrict(self, tau_coarse):
+        """2x restriction of the current state: (shifted populations [19, Nc], force [3, Nc])."""
+        t = self.torch
+        ch = self.channels[0]
+        nc = (ch.nx // 2) * (ch.ny // 2) * (ch.nz // 2)
+        g = t.empty((19, nc), dtype=t.float32, device=self.device)
+        F = t.empty((3, nc), dtype=t.float32, device=self.device)
+        with self.ordered:
+            _check(lib().lbm_restrict(self.h, float(tau_coarse), _ptr(g), _ptr(F)), "lbm_restrict")
+        return g, F
+
     def set_launch(self, block=256, xcd_remap=1, persistent=0, nontemporal=0, vec=0):
         cfg = LbmLaunch(block, xcd_remap, persistent, nontemporal, vec)
         _check(lib().lbm_set_launch(self.h, C.byref(cfg)), "lbm_set_launch")
@@ -309,6 +354,76 @@ def stream_copy(src, dst, variant=0, grid=0):
     assert src.numel() * src.element_size() == dst.numel() * dst.element_size()
     _check(lib().lbm_stream_copy(_ptr(src), _ptr(dst), src.numel() * src.element_size(), int(variant), int(grid),
                                  _stream_ptr(torch, src.device)), "lbm_stream_copy")
+
+
+# ----------------------------------------------------------------- network (training side)
+def _cur(torch, t):
+    return _stream_ptr(torch, t.device)
+
+
+def mlp_pack(params, norm, c_guard=1.0):
+    """Packed network (uint8 device tensor of MLP_PACKED_BYTES) for mlp_forward / mlp_grad."""
+    import torch
+
+    P = torch.empty(MLP_PACKED_BYTES, dtype=torch.uint8, device=params.device)
+    _check(lib().mlp_pack(_ptr(params), _ptr(norm), float(c_guard), _ptr(P), _cur(torch, params)), "mlp_pack")
+    return P
+
+
+def mlp_forward(packed, raw):
+    """dm[B, 16] = network(raw[B, 16]) * out_scale (no guard)."""
+    import torch
+
+    dm = torch.empty_like(raw)
+    _check(lib().mlp_forward(_ptr(packed), _ptr(raw), raw.shape[0], _ptr(dm), _cur(torch, raw)), "mlp_forward")
+    return dm
+
+
+def mlp_grad(packed, raw, target, work=None):
+    """(grad[6288], loss[1]) of the masked mean-square loss on B samples."""
+    import torch
+
+    B = raw.shape[0]
+    nbytes = lib().mlp_grad_workspace_bytes(B)
+    if work is None or work.numel() < nbytes:
+        work = torch.empty(nbytes, dtype=torch.uint8, device=raw.device)
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=raw.device)
+    loss = torch.empty(1, dtype=torch.float32, device=raw.device)
+    _check(lib().mlp_grad(_ptr(packed), _ptr(raw), _ptr(target), B, _ptr(grad), _ptr(loss), _ptr(work), nbytes,
+                          _cur(torch, raw)), "mlp_grad")
+    return grad, loss
+
+
+def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    import torch
+
+    _check(lib().mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), int(step), float(lr),
+                          float(beta1), float(beta2), float(eps), _cur(torch, params)), "mlp_adam")
+
+
+def mlp_norm(raw, target):
+    """norm[48] = (in_mean, in_scale, out_scale) of a training set."""
+    import torch
+
+    B = raw.shape[0]
+    nbytes = lib().mlp_norm_workspace_bytes(B)
+    work = torch.empty(nbytes, dtype=torch.uint8, device=raw.device)
+    norm = torch.empty(MLP_NORM, dtype=torch.float32, device=raw.device)
+    _check(lib().mlp_norm(_ptr(raw), _ptr(target), B, _ptr(norm), _ptr(work), nbytes, _cur(torch, raw)), "mlp_norm")
+    return norm
+
+
+def closure_targets(coarse, g0, F, g1):
+    """(feat[N, 16], target[N, 16]) of one coarse step; coarse is an inputs.Channel-like."""
+    import torch
+
+    N = coarse.nx * coarse.ny * coarse.nz
+    feat = torch.empty((N, 16), dtype=torch.float32, device=g0.device)
+    tgt = torch.empty((N, 16), dtype=torch.float32, device=g0.device)
+    p = params_of(coarse)
+    _check(lib().closure_targets(C.byref(p), _ptr(g0), _ptr(F), _ptr(g1), _ptr(feat), _ptr(tgt), _cur(torch, g0)),
+           "closure_targets")
+    return feat, tgt
 
 
 class Membrane:

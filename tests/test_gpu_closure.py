@@ -1,0 +1,325 @@
+"""Learned closure on the GPU (BF16 matrix cores, through the C ABI) against the FP64
+closure reference on the same seeded inputs.
+
+Tolerances.  The reference rounds the network inputs and hidden activations to bfloat16
+where the GPU does, so the network itself differs only by float32 accumulation, except at
+an input or activation whose float32 (GPU) and float64 (reference) values straddle a
+bfloat16 rounding point: there the two round to neighbouring bfloat16 values (2^-8
+relative), which moves that cell's output by at most about 2^-8 of its size.  The
+non-equilibrium moments are small differences of float32 populations, so their float32
+noise reaches 1e-5 of their spread and such straddles are common for small standardised
+inputs (whose rounding steps are small too).  The tests bound the median cell error by
+float32 rounding, the maximum by a few rounding steps, and check exact conservation.  Populations are float32 (weight-shifted): a state passed
+in through lbm_set_populations carries up to 2^-24 * 1/3 of rounding.  Gradients: the
+backward signals are rounded to bfloat16 on the GPU (the reference keeps them exact), so
+each gradient tensor agrees to about 2^-8 relative; the bound is 1e-2 (per tensor, L2).
+"""
+import numpy as np
+import pytest
+
+from oracle import closure_oracle as co
+from paper_1312_2234_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def T(x, dtype=np.float32):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dtype)).to(DEV)
+
+
+def N(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def theta_bf16(rng, scale=0.3, zero_last=False):
+    W1 = rng.normal(0, scale, (16, 64))
+    b1 = rng.normal(0, 0.1, 64)
+    W2 = rng.normal(0, scale / 2, (64, 64))
+    b2 = rng.normal(0, 0.1, 64)
+    W3 = np.zeros((64, 16)) if zero_last else rng.normal(0, scale / 2, (64, 16))
+    b3 = np.zeros(16) if zero_last else rng.normal(0, 0.05, 16)
+    th = np.concatenate([a.ravel() for a in (W1, b1, W2, b2, W3, b3)])
+    # weights as the GPU holds them (bfloat16); biases stay float32
+    th32 = th.astype(np.float32).astype(np.float64)
+    wmask = np.ones(co.NPARAM, bool)
+    for lo, hi in ((1024, 1088), (5184, 5248), (6272, 6288)):
+        wmask[lo:hi] = False
+    th32[wmask] = co.bf16_round(th32[wmask])
+    return th32
+
+
+def make_state(orc, ch, seed, warm=6):
+    """Oracle lattice with a developed non-equilibrium part: random velocity field, a few
+    plain steps; the populations are rounded to float32 (what the GPU receives)."""
+    rng = np.random.default_rng(seed)
+    o = orc.Lattice(ch.nx, ch.ny, ch.nz, ch.tau, walls=ch.walls, body=ch.body, u_wall_lo=ch.u_wall_lo,
+                    u_wall_hi=ch.u_wall_hi)
+    o.init(u=rng.normal(0, 0.02, (3, ch.nz, ch.ny, ch.nx)))
+    o.step(warm)
+    o.f[...] = o.f.astype(np.float32).astype(np.float64)
+    return o
+
+
+def norm_for(o, out_frac):
+    raw = co.raw_features(o.f, o.g, np.array(o.p.body[:]))
+    mean = raw.mean(axis=0)
+    sd = raw.std(axis=0)
+    scale = np.where(sd > 0, 1.0 / np.where(sd > 0, sd, 1.0), 1.0)
+    rms = np.sqrt((raw[:, :15] ** 2).mean(axis=0))
+    out = np.concatenate([out_frac * rms, [1.0]])
+    nrm = dict(in_mean=mean.astype(np.float32).astype(np.float64), in_scale=scale.astype(np.float32).astype(np.float64),
+               out_scale=out.astype(np.float32).astype(np.float64))
+    flat = np.concatenate([nrm["in_mean"], nrm["in_scale"], nrm["out_scale"]])
+    return nrm, flat
+
+
+CH = inputs.Channel(40, 24, 20, 0.75, body=(2e-6, 0, 0), u_wall_hi=(0.04, 0, 0.01))
+
+
+def gpu_lattice(gpu, ch, o):
+    g = gpu.Lattice([ch], device=DEV)
+    g.set_populations(T(o.f.reshape(-1)))
+    return g
+
+
+def shifted(pop, ch):
+    w = np.asarray(co.velocities()[1])
+    return pop.reshape(19, ch.nz, ch.ny, ch.nx) - w[:, None, None, None]
+
+
+def test_zero_last_layer_is_bitwise_plain_step(orc, gpu):
+    o = make_state(orc, CH, 1)
+    rng = np.random.default_rng(11)
+    th = theta_bf16(rng, zero_last=True)
+    _, flat = norm_for(o, 0.2)
+    a = gpu_lattice(gpu, CH, o)
+    b = gpu_lattice(gpu, CH, o)
+    b.set_closure(T(th), T(flat), 1.0)
+    a.step(3)
+    b.step(3)
+    assert np.array_equal(N(a.get_state()), N(b.get_state()))
+    assert b.closure_guarded() == 0
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_closure_step_matches_oracle(orc, gpu, seed):
+    o = make_state(orc, CH, seed)
+    rng = np.random.default_rng(100 + seed)
+    th = theta_bf16(rng)
+    nrm, flat = norm_for(o, 0.2)
+    body = np.array(o.p.body[:])
+    dF, _ = co.correction(o.f, o.g, body, th, nrm, c_guard=1e30, bf16=True)
+    plain = orc.Lattice(CH.nx, CH.ny, CH.nz, CH.tau, walls=True, body=CH.body, u_wall_hi=CH.u_wall_hi)
+    plain.f[...] = o.f
+    plain.step(1)
+    g = gpu_lattice(gpu, CH, o)
+    gp = gpu_lattice(gpu, CH, o)
+    g.set_closure(T(th), T(flat), 1e30)
+    co.closure_step(o, th, nrm, c_guard=1e30, bf16=True)
+    g.step(1)
+    gp.step(1)
+    got = shifted(N(g.populations()), CH)
+    ref = shifted(o.f, CH)
+    size = np.abs(dF).max()
+    assert size > 1e-6 and np.abs(ref - shifted(plain.f, CH)).max() > 0.5 * size  # the correction matters
+    cell_err = np.abs(got - ref).max(axis=0)
+    med, err = np.median(cell_err), cell_err.max()
+    print("closure step: max|dF| %.3e, median cell err %.3e, max err %.3e" % (size, med, err))
+    # most cells: float32 rounding; where an input or activation lies within float32 noise of
+    # a bfloat16 rounding point the two sides may round it to neighbouring values
+    assert med <= 1e-4 * size + 6e-8
+    assert err <= 4e-3 * size + 6e-8
+    # the GPU correction leaves the total mass unchanged (bounce-back conserves mass; it
+    # exchanges momentum with the walls, so only the oracle pins per-cell momentum)
+    d = (got - shifted(N(gp.populations()), CH)).reshape(19, -1).astype(np.float64)
+    assert abs(d.sum()) <= 1e-6 * np.abs(d).sum()
+    # several steps: the per-step differences above accumulate (and feed back into the next
+    # step's inputs); for a correction of 20% of the non-equilibrium moments the velocity
+    # stays within 1e-4 (the plain float32 lattice is held to 1e-5)
+    for _ in range(9):
+        co.closure_step(o, th, nrm, c_guard=1e30, bf16=True)
+    g.step(9)
+    _, v = g.moments_channel(0)
+    _, vr = o.moments()
+    e = np.abs(N(v) - vr).max() / np.abs(vr).max()
+    print("10 closure steps: e_max %.3e" % e)
+    assert e <= 1e-4
+    assert g.error_flags() == 0
+
+
+def test_guard_falls_back_to_plain_step(orc, gpu):
+    o = make_state(orc, CH, 4)
+    th = theta_bf16(np.random.default_rng(5))
+    nrm, flat = norm_for(o, 0.2)
+    flat_big = flat.copy()
+    flat_big[32:47] = 1e6  # |dm| far above |m| everywhere
+    a = gpu_lattice(gpu, CH, o)
+    b = gpu_lattice(gpu, CH, o)
+    b.set_closure(T(th), T(flat_big), 1.0)
+    a.step(1)
+    b.step(1)
+    assert np.array_equal(N(a.get_state()), N(b.get_state()))
+    assert b.closure_guarded() == CH.nx * CH.ny * CH.nz
+    assert b.error_flags() & gpu.FLAG_CLOSURE_FALLBACK
+    # a moderate guard: the GPU rejects the nodes the reference rejects (away from ties)
+    ob = make_state(orc, CH, 4)
+    c_guard = 0.15
+    raw = co.raw_features(ob.f, ob.g, np.array(ob.p.body[:]))
+    y, _ = co.mlp_forward(co.standardise(raw, nrm), th, bf16=True)
+    dm = y[:, :15] * nrm["out_scale"][None, :15]
+    ratio = np.sqrt((dm ** 2).sum(1)) / np.sqrt((raw[:, :15] ** 2).sum(1))
+    near = np.abs(ratio - c_guard) < 1e-3 * c_guard
+    c = gpu_lattice(gpu, CH, ob)
+    c.set_closure(T(th), T(flat), c_guard)
+    c.step(1)
+    n_gpu = c.closure_guarded()
+    n_ref = int((ratio > c_guard).sum())
+    assert 0 < n_ref < ratio.size
+    assert abs(n_gpu - n_ref) <= int(near.sum())
+
+
+@pytest.mark.parametrize("B", [1, 63, 1000, 4097])
+def test_mlp_forward_matches_oracle(gpu, B):
+    rng = np.random.default_rng(B)
+    th = theta_bf16(rng)
+    raw = rng.normal(0, 1, (B, 16)) * np.linspace(0.5, 2, 16)
+    nrm = dict(in_mean=rng.normal(0, 0.1, 16).astype(np.float32).astype(float),
+               in_scale=rng.uniform(0.5, 2, 16).astype(np.float32).astype(float),
+               out_scale=rng.uniform(0.5, 2, 16).astype(np.float32).astype(float))
+    flat = np.concatenate([nrm["in_mean"], nrm["in_scale"], nrm["out_scale"]])
+    raw32 = raw.astype(np.float32).astype(float)
+    P = gpu.mlp_pack(T(th), T(flat))
+    dm = N(gpu.mlp_forward(P, T(raw32)))
+    # the GPU standardises in float32; so does this reference input
+    x = ((raw32 - nrm["in_mean"]).astype(np.float32) * nrm["in_scale"].astype(np.float32)).astype(float)
+    y, _ = co.mlp_forward(x, th, bf16=True)
+    ref = y * nrm["out_scale"]
+    err = np.abs(dm - ref).max() / np.abs(ref).max()
+    print("mlp forward B=%d: rel err %.3e" % (B, err))
+    assert err <= 2e-3
+    assert np.median(np.abs(dm - ref)) <= 1e-5 * np.abs(ref).max()
+
+
+def test_mlp_grad_matches_oracle_and_is_deterministic(gpu):
+    B = 3000
+    rng = np.random.default_rng(7)
+    th = theta_bf16(rng)
+    raw = rng.normal(0, 1, (B, 16))
+    tgt = rng.normal(0, 0.5, (B, 16))
+    tgt[:, 15] = 0.0
+    nrm = dict(in_mean=np.zeros(16), in_scale=np.ones(16), out_scale=np.full(16, 0.5))
+    flat = np.concatenate([nrm["in_mean"], nrm["in_scale"], nrm["out_scale"]])
+    raw32, tgt32 = raw.astype(np.float32).astype(float), tgt.astype(np.float32).astype(float)
+    P = gpu.mlp_pack(T(th), T(flat))
+    g1, l1 = gpu.mlp_grad(P, T(raw32), T(tgt32))
+    g2, l2 = gpu.mlp_grad(P, T(raw32), T(tgt32))
+    assert np.array_equal(N(g1), N(g2)) and np.array_equal(N(l1), N(l2))
+    y, cache = co.mlp_forward(raw32, th, bf16=True)
+    t = tgt32 / 0.5
+    ref = co.mlp_backward(y, t, cache, th)
+    lref = co.loss(y, t)
+    assert abs(N(l1)[0] - lref) <= 1e-4 * lref
+    got = co.unpack(N(g1))
+    for name, a, b in zip(("W1", "b1", "W2", "b2", "W3", "b3"), got, co.unpack(ref)):
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        print("grad %s: rel L2 %.3e" % (name, rel))
+        assert rel <= 1e-2
+
+
+def test_adam_matches_oracle(gpu):
+    rng = np.random.default_rng(8)
+    n = 6288
+    th = rng.normal(0, 1, n).astype(np.float32).astype(float)
+    m = np.zeros(n)
+    v = np.zeros(n)
+    tg, mg, vg = T(th), T(m), T(v)
+    for step in range(1, 4):
+        grad = rng.normal(0, 1e-2, n).astype(np.float32).astype(float)
+        th, m, v = co.adam(th, grad, m, v, step, lr=1e-3)
+        gpu.mlp_adam(tg, T(grad), mg, vg, step, lr=1e-3)
+    assert np.abs(N(tg) - th).max() <= 1e-6 * np.abs(th).max()
+
+
+def test_norm_statistics(gpu):
+    rng = np.random.default_rng(9)
+    B = 5001
+    raw = (rng.normal(0, 1, (B, 16)) * np.arange(1, 17) + np.arange(16)).astype(np.float32)
+    raw[:, 3] = 2.5  # constant column: scale 1
+    tgt = (rng.normal(0, 1, (B, 16)) * 1e-4).astype(np.float32)
+    tgt[:, 15] = 0.0
+    nrm = N(gpu.mlp_norm(T(raw), T(tgt)))
+    r, t = raw.astype(float), tgt.astype(float)
+    sd = r.std(axis=0)
+    assert np.allclose(nrm[:16], r.mean(axis=0), rtol=1e-6, atol=1e-6)
+    assert np.allclose(nrm[16:32][sd > 0], 1 / sd[sd > 0], rtol=1e-5)
+    assert nrm[16 + 3] == 1.0
+    rms = np.sqrt((t ** 2).mean(axis=0))
+    assert np.allclose(nrm[32:47], rms[:15], rtol=1e-6)
+    assert nrm[47] == 1.0
+
+
+def test_restriction_matches_oracle(orc, gpu):
+    fine = inputs.Channel(16, 12, 8, 1.0, body=(1e-6, 0, 0), u_wall_hi=(0.05, 0, 0))
+    o = make_state(orc, fine, 12)
+    g = gpu_lattice(gpu, fine, o)
+    gc, Fc = g.restrict(0.75)
+    fc, _, _ = co.restrict(o.f, o.g, o.p.body[:], 1.0, 0.75)
+    w = np.asarray(co.velocities()[1])
+    ref = (fc - w[:, None, None, None]).reshape(19, -1)
+    err = np.abs(N(gc) - ref).max()
+    print("restriction: max err %.3e (max|g_c| %.3e)" % (err, np.abs(ref).max()))
+    assert err <= 1e-7
+    assert np.abs(N(Fc)).max() == 0.0
+
+
+def test_restricted_ib_force_matches_oracle(orc, gpu):
+    fine = inputs.Channel(32, 24, 16, 1.0, u_wall_hi=(0.05, 0, 0))
+    rng = np.random.default_rng(13)
+    n = 300
+    X = np.stack([rng.uniform(0, 32, n), rng.uniform(2, 21, n), rng.uniform(0, 16, n)])
+    F = rng.normal(0, 1e-3, (3, n))
+    o = make_state(orc, fine, 14)
+    o.spread(X, F.astype(np.float32).astype(float))
+    g = gpu_lattice(gpu, fine, o)
+    g2 = gpu.Lattice([fine], max_nodes=n, device=DEV)
+    g2.set_populations(T(o.f.reshape(-1)))
+    g2.set_nodes(n)
+    g2.spread(T(X, np.float64), T(F))
+    _, Fc = g2.restrict(0.75)
+    _, gref, _ = co.restrict(o.f, o.g, (0, 0, 0), 1.0, 0.75)
+    err = np.abs(N(Fc) - gref.reshape(3, -1)).max() / np.abs(gref).max()
+    print("restricted force: rel err %.3e" % err)
+    assert err <= 1e-5
+    del g
+
+
+def test_targets_match_oracle_and_recover_a_correction(orc, gpu):
+    coarse = inputs.Channel(20, 16, 12, 0.75, body=(2e-6, 0, 0), u_wall_hi=(0.04, 0, 0.01))
+    o = make_state(orc, coarse, 15)
+    rng = np.random.default_rng(16)
+    o.g[...] = rng.normal(0, 1e-4, o.g.shape).astype(np.float32).astype(float)
+    th = theta_bf16(rng)
+    nrm, _ = norm_for(o, 0.2)
+    f0, g0 = o.f.copy(), o.g.copy()
+    body = np.array(o.p.body[:])
+    dF, _ = co.correction(f0, g0, body, th, nrm, c_guard=1e30)
+    co.closure_step(o, th, nrm, c_guard=1e30)
+    f1 = o.f.astype(np.float32).astype(float)
+    raw_ref, dm_ref = co.targets(o, f0, g0, f1)
+    w = np.asarray(co.velocities()[1])[:, None]
+    s0 = f0.reshape(19, -1) - w
+    s1 = f1.reshape(19, -1) - w
+    feat, tgt = gpu.closure_targets(coarse, T(s0), T(g0.reshape(3, -1)), T(s1))
+    feat, tgt = N(feat), N(tgt)
+    M = co.moment_basis()
+    dm_applied = (M[4:] @ dF).T
+    bound = 64 * 2.0 ** -24 * np.abs(s1).max()
+    err_t = np.abs(tgt[:, :15] - dm_ref).max()
+    print("targets: max err %.3e, bound %.3e, max|dm| %.3e" % (err_t, bound, np.abs(dm_ref).max()))
+    assert err_t <= bound
+    assert np.abs(tgt[:, :15] - dm_applied).max() <= bound + 1e-8 * np.abs(dm_applied).max()
+    assert np.all(tgt[:, 15] == 0)
+    assert np.abs(feat - raw_ref).max() <= 64 * 2.0 ** -24 * max(np.abs(s0).max(), np.abs(raw_ref).max())
