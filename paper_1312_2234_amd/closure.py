@@ -1,0 +1,284 @@
+"""Learned collision closure: training-data generation, training and evaluation.
+
+The coarse lattice (2x coarser in space and time, acoustic scaling) runs the plain forced
+BGK step plus a learned correction of its non-conserved moments (the closure of the C ABI:
+lbm_set_closure).  The network is trained to reproduce one coarse step of the restricted
+fine-lattice flow:
+
+  data     fine channel 256x128x128 (tau_f = 1.0) with 16 platelets of 2562 nodes, top wall
+           speed U ~ U(0.02, 0.05) per seed; after a spin-up, snapshot pairs
+           (f_f(t), f_f(t + 2 dt_f)) every `every` fine steps, restricted to the coarse
+           lattice (lbm_restrict) and turned into (features, target moments) by
+           closure_targets -- all on the GPU;
+  training mean-square loss on the 15 target moments, Adam, minibatches of contiguous
+           coarse cells from random snapshots (mlp_grad / mlp_adam on the matrix cores);
+           validation on held-out seeds;
+  eval     the same suspension on the fine lattice (reference), on the plain coarse lattice
+           and on the learned coarse lattice; errors of the bottom-wall shear stress and of
+           the platelet centroid velocities against the (restricted) fine reference, and the
+           throughput of each run.
+
+Every computation runs in the library's kernels; this module only sequences the calls,
+holds the tensors and draws the random minibatch positions.
+
+    python -m paper_1312_2234_amd.closure --out results.json [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+
+from . import inputs, lbm
+
+TAU_F = 1.0
+TAU_C = 0.75
+
+
+def _nodes_setup(lat, ch, dev):
+    import torch
+
+    b = ch.bodies
+    lat.set_nodes(b.n)
+    mem = lbm.Membrane(b, device=dev)
+    X = torch.from_numpy(b.X.copy()).to(dev)
+    F = torch.zeros((3, b.n), dtype=torch.float32, device=dev)
+    U = torch.zeros_like(F)
+    return mem, X, F, U
+
+
+def generate(seeds, u_range=(0.02, 0.05), spinup=400, snapshots=25, every=80, dev="cuda:0", count=16,
+             fine=(256, 128, 128), log=print):
+    """Training pairs of the given seeds: returns (feat [S, Nc, 16], target [S, Nc, 16]) as
+    device tensors (S = len(seeds) * snapshots)."""
+    import torch
+
+    feats, tgts = None, None
+    k = 0
+    for seed in seeds:
+        u_top = float(np.random.default_rng(10_000 + seed).uniform(*u_range))
+        chf, chc = inputs.coarse_fine_pair(seed, u_top=u_top, count=count, fine=fine, tau_f=TAU_F)
+        lat = lbm.Lattice([chf], max_nodes=chf.bodies.n, device=dev)
+        lat.init()
+        mem, X, F, U = _nodes_setup(lat, chf, dev)
+        lat.coupled_steps(mem, spinup, X, F, U)
+        nc = chc.nx * chc.ny * chc.nz
+        if feats is None:
+            S = len(seeds) * snapshots
+            feats = torch.empty((S, nc, 16), dtype=torch.float32, device=dev)
+            tgts = torch.empty((S, nc, 16), dtype=torch.float32, device=dev)
+        for s in range(snapshots):
+            # time t: the force of step t is spread, the state is f(t)
+            mem.forces(X, F)
+            lat.spread(X, F)
+            g0, Fc = lat.restrict(TAU_C)
+            lat.step(1)
+            lat.interp(X, U)
+            lat.advance(X, U)
+            lat.coupled_steps(mem, 1, X, F, U)
+            g1, _ = lat.restrict(TAU_C)
+            lbm.closure_targets(chc, g0, Fc, g1, out=(feats[k], tgts[k]))
+            k += 1
+            lat.coupled_steps(mem, every - 2, X, F, U)
+        flags = lat.error_flags()
+        log("seed %d: U = %.4f, %d snapshot pairs, flags %d" % (seed, u_top, snapshots, flags))
+        del lat
+    return feats, tgts
+
+
+def init_params(rng, dev):
+    """He-normal hidden layers, small output layer, zero biases (flat MLP_PARAMS layout)."""
+    import torch
+
+    W1 = rng.normal(0, np.sqrt(2.0 / 16), (16, 64))
+    W2 = rng.normal(0, np.sqrt(2.0 / 64), (64, 64))
+    W3 = rng.normal(0, 0.01, (64, 16))
+    th = np.concatenate([W1.ravel(), np.zeros(64), W2.ravel(), np.zeros(64), W3.ravel(), np.zeros(16)])
+    return torch.from_numpy(th.astype(np.float32)).to(dev)
+
+
+# Output lanes of the network and the moment rows they correct: lanes 0-5 are the second-
+# order rows 4-9 (normal and shear stresses, which set the viscosity), lanes 6-14 the third-
+# and fourth-order rows 10-18.
+HYDRO_LANES = range(0, 6)
+
+
+def train(feat, tgt, vfeat, vtgt, steps=3000, batch=65536, lr=1e-3, seed=0, log=print, log_every=500,
+          higher_only=False):
+    """Adam on minibatches of `batch` contiguous coarse cells of random training snapshots.
+    With higher_only the second-order moments are left to the BGK relaxation: their targets
+    are scaled away in training (out_scale -> huge, so the standardised target is ~0) and
+    their output scale is 0 at inference.  Returns (params, norm, history, seconds)."""
+    import torch
+
+    dev = feat.device
+    S, nc, _ = feat.shape
+    flat_f = feat.view(-1, 16)
+    flat_t = tgt.view(-1, 16)
+    norm = lbm.mlp_norm(flat_f, flat_t)
+    if higher_only:
+        for k in HYDRO_LANES:
+            norm[32 + k] = 1e30
+    params = init_params(np.random.default_rng(seed), dev)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    rng = np.random.default_rng(seed + 1)
+    work = torch.empty(lbm.lib().mlp_grad_workspace_bytes(batch), dtype=torch.uint8, device=dev)
+    hist = []
+    vf, vt = vfeat.view(-1, 16), vtgt.view(-1, 16)
+    vwork = torch.empty(lbm.lib().mlp_grad_workspace_bytes(vf.shape[0]), dtype=torch.uint8, device=dev)
+
+    def val_loss():
+        P = lbm.mlp_pack(params, norm)
+        return float(lbm.mlp_grad(P, vf, vt, vwork)[1].item())
+
+    hist.append((0, None, val_loss()))
+    t0 = time.perf_counter()
+    for step in range(1, steps + 1):
+        s = int(rng.integers(S))
+        o = int(rng.integers(nc - batch + 1))
+        P = lbm.mlp_pack(params, norm)
+        grad, loss = lbm.mlp_grad(P, feat[s, o:o + batch], tgt[s, o:o + batch], work)
+        lbm.mlp_adam(params, grad, m, v, step, lr=lr)
+        if step % log_every == 0 or step == steps:
+            tl = float(loss.item())
+            vl = val_loss()
+            hist.append((step, tl, vl))
+            log("step %d: train loss %.4f, validation loss %.4f (%.1f s)" % (step, tl, vl, time.perf_counter() - t0))
+    torch.cuda.synchronize()
+    if higher_only:
+        for k in HYDRO_LANES:
+            norm[32 + k] = 0.0
+    return params, norm, hist, time.perf_counter() - t0
+
+
+def _centroid_velocity(U, offsets):
+    Un = U.detach().cpu().numpy().astype(np.float64)
+    return np.stack([Un[:, a:b].mean(axis=1) for a, b in zip(offsets[:-1], offsets[1:])])
+
+
+def _run(lat, mem, X, F, U, steps, sample_every, wall_shape):
+    """Coupled steps with the wall stress and platelet centroid velocities sampled over the
+    last quarter of the run; returns (mean bottom-wall sigma_xy [nz, nx], mean centroid
+    velocities [bodies, 3], seconds of the timed stepping)."""
+    import torch
+
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wss, vel, ns = 0.0, 0.0, 0
+    elapsed = 0.0
+    done = 0
+    start_sampling = steps - steps // 4
+    while done < steps:
+        k = min(sample_every, steps - done)
+        torch.cuda.synchronize()
+        ev0.record(lat.stream)
+        lat.coupled_steps(mem, k, X, F, U)
+        ev1.record(lat.stream)
+        torch.cuda.synchronize()
+        elapsed += ev0.elapsed_time(ev1) * 1e-3
+        done += k
+        if done > start_sampling:
+            lo, _ = lat.wall_stress()
+            nz, nx = wall_shape
+            wss = wss + lo[: nz * nx].view(nz, nx).double().cpu().numpy()
+            vel = vel + _centroid_velocity(U, mem.offsets)
+            ns += 1
+    return wss / ns, vel / ns, elapsed
+
+
+def evaluate(params, norm, seeds, u_top=0.05, coarse_steps=2000, sample_every=50, dev="cuda:0", count=16,
+             fine=(256, 128, 128), c_guard=1.0, log=print):
+    """Fine reference vs plain coarse vs learned coarse on held-out seeds."""
+    out = []
+    for seed in seeds:
+        chf, chc = inputs.coarse_fine_pair(seed, u_top=u_top, count=count, fine=fine, tau_f=TAU_F)
+        res = {"seed": seed, "u_top": u_top}
+        runs = {}
+        for name, ch, steps, closure in (("fine", chf, 2 * coarse_steps, False), ("plain", chc, coarse_steps, False),
+                                         ("learned", chc, coarse_steps, True)):
+            lat = lbm.Lattice([ch], max_nodes=ch.bodies.n, device=dev)
+            lat.init()
+            mem, X, F, U = _nodes_setup(lat, ch, dev)
+            mem.offsets = ch.bodies.body_offsets
+            if closure:
+                lat.set_closure(params, norm, c_guard)
+            every = sample_every * (2 if name == "fine" else 1)
+            wss, vel, secs = _run(lat, mem, X, F, U, steps, every, (ch.nz, ch.nx))
+            runs[name] = (wss, vel)
+            res[name + "_mlups"] = ch.cells * steps / secs / 1e6
+            res[name + "_flags"] = lat.error_flags()
+            if closure:
+                res["guarded_updates"] = lat.closure_guarded()
+            del lat
+        wf, vf = runs["fine"]
+        wf_c = wf.reshape(chc.nz, 2, chc.nx, 2).mean(axis=(1, 3))  # fine wall stress on coarse cells
+        base = float(np.mean(wf_c))  # the mean (Couette) part
+        for name in ("plain", "learned"):
+            w, v = runs[name]
+            res[name + "_wss_rel_l2"] = float(np.linalg.norm(w - wf_c) / np.linalg.norm(wf_c))
+            res[name + "_wss_dev_rel_l2"] = float(np.linalg.norm((w - np.mean(w)) - (wf_c - base)) /
+                                                  max(np.linalg.norm(wf_c - base), 1e-300))
+            res[name + "_wss_mean_rel"] = float(abs(np.mean(w) - base) / abs(base))
+            res[name + "_vel_rel_l2"] = float(np.linalg.norm(v - vf) / np.linalg.norm(vf))
+        log("seed %d: " % seed + ", ".join("%s %.4g" % (k, v) for k, v in res.items() if isinstance(v, float)))
+        out.append(res)
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--quick", action="store_true", help="small run (smoke size)")
+    ap.add_argument("--train-seeds", type=int, default=8)
+    ap.add_argument("--val-seeds", type=int, default=1)
+    ap.add_argument("--eval-seeds", type=int, default=2)
+    ap.add_argument("--snapshots", type=int, default=25)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--coarse-steps", type=int, default=2000)
+    ap.add_argument("--higher-only", action="store_true", help="correct only moments above second order")
+    ap.add_argument("--c-guard", type=float, default=1.0)
+    args = ap.parse_args(argv)
+
+    import torch
+
+    def log(msg):
+        print(msg, flush=True)
+
+    kw = {}
+    if args.quick:
+        kw = dict(fine=(64, 48, 32), count=2)
+        args.train_seeds, args.val_seeds, args.eval_seeds = 2, 1, 1
+        args.snapshots, args.steps, args.coarse_steps = 4, 200, 200
+    t0 = time.perf_counter()
+    train_seeds = list(range(args.train_seeds))
+    val_seeds = list(range(100, 100 + args.val_seeds))
+    eval_seeds = list(range(200, 200 + args.eval_seeds))
+    feat, tgt = generate(train_seeds, snapshots=args.snapshots, log=log, **kw)
+    vfeat, vtgt = generate(val_seeds, snapshots=max(2, args.snapshots // 5), log=log, **kw)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    log("data: %d training samples, %d validation samples, %.1f s" % (feat.shape[0] * feat.shape[1],
+                                                                       vfeat.shape[0] * vfeat.shape[1], t_data))
+    params, norm, hist, t_train = train(feat, tgt, vfeat, vtgt, steps=args.steps,
+                                        batch=min(65536, feat.shape[1]), log=log,
+                                        log_every=max(1, args.steps // 6), higher_only=args.higher_only)
+    nsamp = args.steps * min(65536, feat.shape[1])
+    log("training: %d steps, %.1f s, %.1f M samples/s" % (args.steps, t_train, nsamp / t_train / 1e6))
+    del feat, tgt
+    ev = evaluate(params, norm, eval_seeds, coarse_steps=args.coarse_steps, log=log, c_guard=args.c_guard, **kw)
+    rep = {"train_seeds": train_seeds, "val_seeds": val_seeds, "eval_seeds": eval_seeds,
+           "snapshots_per_seed": args.snapshots, "adam_steps": args.steps, "history": hist,
+           "train_seconds": t_train, "data_seconds": t_data, "train_samples_per_s": nsamp / t_train,
+           "eval": ev, "norm": norm.cpu().numpy().tolist(), "higher_only": args.higher_only,
+           "c_guard": args.c_guard}
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(rep, f, indent=1)
+        torch.save({"params": params.cpu(), "norm": norm.cpu()}, args.out.rsplit(".", 1)[0] + "_weights.pt")
+    return rep
+
+
+if __name__ == "__main__":
+    main()

@@ -275,6 +275,35 @@ def shear_platelets(seed=0, nx=256, ny=128, nz=128, count=16, nodes=2562, semi_a
     return Channel(nx, ny, nz, tau, u_wall_hi=(u_top, 0.0, 0.0), init="shear", bodies=b)
 
 
+def coarse_fine_pair(seed=0, u_top=0.05, count=16, fine=(256, 128, 128), tau_f=1.0, nodes_f=2562,
+                     nodes_c=1282, semi_axes=(6.0, 2.0, 6.0), k_spring=0.005, k_bend=1e-4, y_band=(8.0, 20.0)):
+    """The same platelet suspension on a fine lattice and on the 2x coarser one (acoustic
+    scaling: dx_c = 2 dx_f, dt_c = 2 dt_f, so lattice velocities are equal and
+    tau_c = 1/2 + (tau_f - 1/2)/2).  Platelet centres are drawn once in fine units; a fine
+    point x_f sits at x_c = (x_f - 1/2)/2 on the coarse lattice (cell centres at integers on
+    both).  Coarse platelets have half the semi-axes and `nodes_c` nodes; their spring and
+    bending constants follow the same scaling (membrane stiffness k dt^2/(rho dx^3) halves,
+    bending energy k_b dt^2/(rho dx^5) drops by 8).  Returns (fine Channel, coarse Channel)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = fine
+    a = np.asarray(semi_axes, float)
+    y_lo = -0.5 + y_band[0]
+    y_hi = min(-0.5 + y_band[1], ny - 0.5 - a[1] - 2.0)
+    cen = place_bodies(rng, nx, nz, count, float(a.max()) + 2.0, y_lo, y_hi)
+    Vf = _topology(nodes_f)[0]
+    Vc = _topology(nodes_c)[0]
+    Xf, Ef, Hf, Of = _concat([(Vf * a[None, :] + c[None, :], nodes_f) for c in cen])
+    Xc, Ec, Hc, Oc = _concat([(Vc * (a / 2)[None, :] + ((c - 0.5) / 2)[None, :], nodes_c) for c in cen])
+    bf = Bodies(X=Xf, X_rest=Xf.copy(), edges=Ef, hinges=Hf, anchors=None, k_spring=k_spring, k_bend=k_bend,
+                body_offsets=Of)
+    bc = Bodies(X=Xc, X_rest=Xc.copy(), edges=Ec, hinges=Hc, anchors=None, k_spring=k_spring / 2,
+                k_bend=k_bend / 8, body_offsets=Oc)
+    tau_c = 0.5 + (tau_f - 0.5) / 2
+    chf = Channel(nx, ny, nz, tau_f, u_wall_hi=(u_top, 0.0, 0.0), init="shear", bodies=bf)
+    chc = Channel(nx // 2, ny // 2, nz // 2, tau_c, u_wall_hi=(u_top, 0.0, 0.0), init="shear", bodies=bc)
+    return chf, chc
+
+
 BATCH_SIZES = [(48, 32, 32), (64, 48, 48), (96, 64, 64), (128, 64, 64)]
 
 

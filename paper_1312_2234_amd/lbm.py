@@ -413,13 +413,18 @@ def mlp_norm(raw, target):
     return norm
 
 
-def closure_targets(coarse, g0, F, g1):
-    """(feat[N, 16], target[N, 16]) of one coarse step; coarse is an inputs.Channel-like."""
+def closure_targets(coarse, g0, F, g1, out=None):
+    """(feat[N, 16], target[N, 16]) of one coarse step; coarse is an inputs.Channel-like;
+    `out` optionally gives the two (contiguous) output tensors."""
     import torch
 
     N = coarse.nx * coarse.ny * coarse.nz
-    feat = torch.empty((N, 16), dtype=torch.float32, device=g0.device)
-    tgt = torch.empty((N, 16), dtype=torch.float32, device=g0.device)
+    if out is None:
+        feat = torch.empty((N, 16), dtype=torch.float32, device=g0.device)
+        tgt = torch.empty((N, 16), dtype=torch.float32, device=g0.device)
+    else:
+        feat, tgt = out
+        assert feat.shape == (N, 16) and tgt.shape == (N, 16)
     p = params_of(coarse)
     _check(lib().closure_targets(C.byref(p), _ptr(g0), _ptr(F), _ptr(g1), _ptr(feat), _ptr(tgt), _cur(torch, g0)),
            "closure_targets")
