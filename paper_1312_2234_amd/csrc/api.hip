@@ -51,6 +51,16 @@ Sizes sizes_of(const lbm_params* p, int32_t nch, int64_t max_nodes) {
     return s;
 }
 
+// Partial blocks of split spread tiles: a split tile has more than SP_CHUNK nodes, so a list
+// of list_cap entries has at most 2 list_cap / SP_CHUNK chunks in split tiles.
+int64_t part_cap_of(const Sizes& sz) {
+    const int64_t c = 2 * sz.list_cap / SP_CHUNK + 64;
+    return c < SP_PART_MAX ? c : SP_PART_MAX;
+}
+
+// Spread work items: one per flagged tile plus one per further SP_CHUNK list entries.
+int64_t max_items_of(const Sizes& sz) { return sz.slots + sz.list_cap / SP_CHUNK + 1; }
+
 Layout layout_of(const lbm_params* p, int32_t nch, lbm_storage st, int64_t max_nodes, Sizes& sz) {
     sz = sizes_of(p, nch, max_nodes);
     Layout L{};
@@ -80,10 +90,14 @@ Layout layout_of(const lbm_params* p, int32_t nch, lbm_storage st, int64_t max_n
             L.sets[k][4] = take(sizeof(int32_t) * sz.slots);           // fill
             L.sets[k][5] = take(sizeof(int32_t) * (sz.slots + 1));     // slot_off
             L.sets[k][6] = take(sizeof(IbHdr));                        // header
+            L.sets[k][7] = take(sizeof(int32_t) * (sz.slots + 1));     // chunk_off
+            L.sets[k][8] = take(sizeof(int32_t) * sz.slots);           // big
         }
         L.list = take(sizeof(int32_t) * sz.list_cap);
         L.force = take(sizeof(float) * 3 * TILE_CELLS * sz.slots);
         L.vel = take(sizeof(float) * 4 * TILE_CELLS * sz.slots);
+        L.part = take(sizeof(unsigned long long) * 3 * TILE_CELLS * part_cap_of(sz));
+        L.item_slot = take(sizeof(int32_t) * max_items_of(sz));
 
     }
     L.total = off;
@@ -133,6 +147,10 @@ IbArgs ib_args(lbm_ctx* c, int set) {
     a.rank = c->d_rank;
     a.blkbase = c->d_blkbase;
     a.nbase = c->d_nbase;
+    a.part = c->d_part;
+    a.part_cap = c->part_cap;
+    a.item_slot = c->d_item_slot;
+    a.max_items = c->max_items;
     return a;
 }
 
@@ -218,6 +236,8 @@ lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib
             c->set[k].fill = (int32_t*)(c->ws + L.sets[k][4]);
             c->set[k].slot_off = (int32_t*)(c->ws + L.sets[k][5]);
             c->set[k].hdr = (IbHdr*)(c->ws + L.sets[k][6]);
+            c->set[k].chunk_off = (int32_t*)(c->ws + L.sets[k][7]);
+            c->set[k].big = (int32_t*)(c->ws + L.sets[k][8]);
         }
         c->d_list = (int32_t*)(c->ws + L.list);
         c->d_rank = (int32_t*)(c->ws + L.rank);
@@ -225,6 +245,10 @@ lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib
         c->d_nbase = (int4*)(c->ws + L.nbase);
         c->d_force = (float*)(c->ws + L.force);
         c->d_vel = (float*)(c->ws + L.vel);
+        c->d_part = (unsigned long long*)(c->ws + L.part);
+        c->part_cap = part_cap_of(sz);
+        c->d_item_slot = (int32_t*)(c->ws + L.item_slot);
+        c->max_items = max_items_of(sz);
     }
 
     // channel descriptors and the segment map
@@ -274,6 +298,7 @@ lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib
             if (st == LBM_OK) st = hip_ok(launch_fill_i32(c->stream, c->set[k].slot_off, sz.slots + 1, 0));
             if (st == LBM_OK)
                 st = hip_ok(launch_fill_i32(c->stream, (int32_t*)c->set[k].hdr, sizeof(IbHdr) / 4, 0));
+            if (st == LBM_OK) st = hip_ok(launch_fill_i32(c->stream, c->set[k].chunk_off, sz.slots + 1, 0));
         }
 
     }

@@ -251,8 +251,8 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 }
 
 __global__ void __launch_bounds__(1024) k_ib_scan(IbArgs a) {
-    __shared__ int wsum[16];
-    __shared__ int carry;
+    __shared__ int wsum[3][16];
+    __shared__ int carry[3];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // clear the tile set used by the spread before last
     const int nfo = a.other.hdr->nflag;
@@ -262,32 +262,53 @@ __global__ void __launch_bounds__(1024) k_ib_scan(IbArgs a) {
         a.other.tile_slot[T] = -1;
     }
     const int nf = a.set.hdr->nflag;
-    if (tid == 0) carry = 0;
+    if (tid < 3) carry[tid] = 0;
     __syncthreads();  // every thread has read the other set's count before it is reset below
+    // three exclusive prefixes over the flagged tiles: list offsets (node count), spread
+    // work items (chunks of SP_CHUNK nodes) and the partial blocks of split tiles
     for (int base = 0; base < nf; base += blockDim.x) {
         const int k = base + tid;
         const int v = k < nf ? a.set.cnt[a.set.flag_list[k]] : 0;
-        const int incl = wave_incl_scan(v);
-        if (lane == 63) wsum[wave] = incl;
+        const int nch = k < nf ? (v > SP_CHUNK ? (v + SP_CHUNK - 1) / SP_CHUNK : 1) : 0;
+        const int val[3] = {v, nch, nch > 1 ? nch : 0};
+        int incl[3], excl[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            incl[j] = wave_incl_scan(val[j]);
+            if (lane == 63) wsum[j][wave] = incl[j];
+        }
         __syncthreads();
         if (wave == 0) {
             const int nw = blockDim.x >> 6;
-            int x = lane < nw ? wsum[lane] : 0;
-            x = wave_incl_scan(x);
-            if (lane < nw) wsum[lane] = x;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                int x = lane < nw ? wsum[j][lane] : 0;
+                x = wave_incl_scan(x);
+                if (lane < nw) wsum[j][lane] = x;
+            }
         }
         __syncthreads();
-        const int excl = carry + (wave ? wsum[wave - 1] : 0) + incl - v;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) excl[j] = carry[j] + (wave ? wsum[j][wave - 1] : 0) + incl[j] - val[j];
         if (k < nf) {
-            a.set.slot_off[k] = excl;
+            a.set.slot_off[k] = excl[0];
             a.set.tile_slot[a.set.flag_list[k]] = k;
+            a.set.chunk_off[k] = excl[1];
+            a.set.big[k] = (val[2] && (int64_t)excl[2] + val[2] <= a.part_cap) ? excl[2] : -1;
+            for (int j = 0; j < nch && (int64_t)excl[1] + j < a.max_items; ++j) a.item_slot[excl[1] + j] = k;
         }
         __syncthreads();
-        if (tid == blockDim.x - 1) carry = excl + v;
+        if (tid == blockDim.x - 1)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) carry[j] = excl[j] + val[j];
         __syncthreads();
     }
     if (tid == 0) {
-        a.set.slot_off[nf] = carry;
+        const int total = carry[0];
+        a.set.slot_off[nf] = total;
+        a.set.chunk_off[nf] = carry[1];
+        a.set.hdr->nchunk = (int64_t)carry[1] < a.max_items ? carry[1] : (int)a.max_items;
+        a.other.hdr->nchunk = 0;
         a.other.hdr->nflag = 0;
         a.other.hdr->fmax_bits = 0;
         a.other.hdr->nonfinite = 0;
@@ -304,11 +325,14 @@ __global__ void __launch_bounds__(1024) k_ib_scan(IbArgs a) {
             frexpf(fm, &e);  // fm < 2^e
             int L = 1;
             while ((1ll << L) < a.n) ++L;
-            s = 62 - e - L;           // sum of <= n contributions below 2^59
-            if (s > 51 - e) s = 51 - e;  // one contribution below 2^48 (exact rounding trick)
+            // one contribution |w_x w_y w_z F| <= max|F|/8 < 2^(e-3) stays below 2^31 after
+            // scaling (so it converts exactly through int32), and a sum of <= n of them stays
+            // below 2^62; the quantum is 2^-34 max|F| or finer
+            s = 34 - e;
+            if (s > 65 - e - L) s = 65 - e - L;
         }
         a.set.hdr->scale_exp = s;
-        if (carry > a.list_cap) atomicOr(a.flags, LBM_FLAG_LIST_OVERFLOW);
+        if (total > a.list_cap) atomicOr(a.flags, LBM_FLAG_LIST_OVERFLOW);
     }
 }
 
@@ -330,184 +354,128 @@ __global__ void __launch_bounds__(256) k_ib_scatter(IbArgs a) {
 }
 
 // ---------------------------------------------------------------- spread (LDS, fixed point)
-// Work item = (flagged 8x8x8 tile, one of its eight 4x4x4 sub-tiles); the item owns the 64
-// cells of its sub-tile, so no item needs another's result.  The item scans the tile's node
-// list (stencil bases from the compact `nbase` array), keeps the nodes whose stencil box
-// overlaps the sub-tile together with the overlap box, turns the overlapping (node, point)
-// pairs into one flat index space by a block prefix sum, and lets every thread take an
-// equal contiguous range of pairs.  Each pair adds w_x w_y w_z F to a 64-bit fixed-point
-// LDS accumulator; integer sums are exact, so the result does not depend on the order in
-// which nodes were listed.
-constexpr int SP_THREADS = 1024;  // 16 wavefronts per item hide the LDS latency of the pair loop
-constexpr int SP_U = 1;           // list entries a thread loads at once while collecting
-constexpr int SP_BATCH = 1024;    // overlapping nodes held in LDS at a time (>= SP_U * SP_THREADS)
-constexpr int SP_WIN = 4096;     // pairs per owner-map window
+// Work item = one chunk of up to SP_CHUNK nodes of a flagged 8x8x8 tile's node list.  The
+// chunk's node records are staged in LDS; then each wavefront takes one node at a time with
+// lane = stencil point (x = lane & 3, y = (lane >> 2) & 3, z = lane >> 4): the lanes whose
+// cell lies in the tile (and not inside a wall) add w_x w_y w_z F to a 64-bit fixed-point
+// LDS accumulator of the tile's 512 cells.  A tile of one chunk writes its force block
+// directly; each chunk of a longer list stores its fixed-point partial block, and a second
+// kernel adds the tile's blocks and writes the force block.  Integer sums are exact, so the
+// result does not depend on the order in which nodes were listed or chunks ran.
+constexpr int SP_THREADS = 512;   // 8 wavefronts per work item (four work items per CU)
+constexpr int SP_BATCH = 256;     // node records staged at a time (>= SP_CHUNK)
 
-__device__ __forceinline__ long long fixed_round(float c, double scale) {
-    // round-to-nearest of c * scale for |c * scale| < 2^51: add 1.5 * 2^52 in double
-    const double x = (double)c * scale + 6755399441055744.0;
-    return __double_as_longlong(x) - 0x4338000000000000LL;
-}
-
-// Stencil points k = 0..3 of base b along one axis that fall in [s, s+4): first k, count and
-// the sub-tile-local coordinate of the first one.  Cells are taken modulo n when `wrap`,
-// else rows outside [0, n) are dropped.
-__device__ __forceinline__ void overlap(int b, int s, int n, bool wrap, int& lo, int& cnt, int& loc0) {
-    lo = 4;
-    cnt = 0;
-    loc0 = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        int c = b + k;
-        bool ok = true;
-        if (wrap) {
-            if (c >= n) c -= n;
-        } else {
-            ok = c >= 0 && c < n;
-        }
-        const bool in = ok && (unsigned)(c - s) < 4u;
-        if (in && lo == 4) {
-            lo = k;
-            loc0 = c - s;
-        }
-        cnt += in;
-    }
-}
-
-// floor(j / d) for 0 <= j < 64 and d in 1..4
-__device__ __forceinline__ int div_small(int j, int d) {
-    const int inv = d == 1 ? 65536 : (d == 2 ? 32768 : (d == 3 ? 21846 : 16384));
-    return (j * inv) >> 16;
+__device__ __forceinline__ unsigned long long fixed_round(float c, float scale) {
+    // round-to-nearest-even of c * scale (a power of two: the product is exact) for
+    // |c * scale| < 2^31, sign-extended to 64 bits
+    return (unsigned long long)(long long)(int)__builtin_rintf(c * scale);
 }
 
 __global__ void __launch_bounds__(SP_THREADS) k_ib_spread(IbArgs a) {
-    __shared__ unsigned long long acc[3 * 64];
-    __shared__ int box[SP_BATCH];       // per node: lo, cnt, local origin for x, y, z (3 bits each)
-    __shared__ float wf[15][SP_BATCH];  // per node: weights w_x[4], w_y[4], w_z[4], F[3]
-    __shared__ int pre[SP_BATCH + 1];
-    __shared__ unsigned short owner[SP_WIN];
-    __shared__ int ncand, wsum[SP_THREADS / 64];
-    const int nf = a.set.hdr->nflag;
+    __shared__ unsigned long long acc[3 * TILE_CELLS];
+    __shared__ int4 base[SP_BATCH];         // stencil base x, y, z of each staged node
+    __shared__ float4 wrec[SP_BATCH][4];    // w_x[4], w_y[4], w_z[4], (F, pad)
+    const int nwork = a.set.hdr->nchunk;
     const int sexp = a.set.hdr->scale_exp;
     const bool nonfinite = a.set.hdr->nonfinite != 0;
-    const double scale = ldexp(1.0, sexp), inv = ldexp(1.0, -sexp);
+    const float scale = ldexpf(1.0f, sexp);
+    const double inv = ldexp(1.0, -sexp);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int wi = blockIdx.x; wi < nf * 8; wi += gridDim.x) {
-        const int slot = wi >> 3, sub = wi & 7;
-        for (int k = tid; k < 3 * 64; k += SP_THREADS) acc[k] = 0ull;
+    const int ix = lane & 3, iy = (lane >> 2) & 3, iz = lane >> 4;
+    for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
+        const int slot = a.item_slot[wi];
+        const int c = wi - a.set.chunk_off[slot];
+        const int nch = a.set.chunk_off[slot + 1] - a.set.chunk_off[slot];
+        const int bigid = a.set.big[slot];
+        const bool split = nch > 1 && bigid >= 0;
+        if (nch > 1 && bigid < 0 && c != 0) continue;  // no accumulator left: chunk 0 takes the list
+        int64_t beg = a.set.slot_off[slot], end = a.set.slot_off[slot + 1];
+        if (split) {
+            beg += (int64_t)c * SP_CHUNK;
+            if (end > beg + SP_CHUNK) end = beg + SP_CHUNK;
+        }
+        if (end > a.list_cap) end = a.list_cap;
+        for (int k = tid; k < 3 * TILE_CELLS; k += SP_THREADS) acc[k] = 0ull;
         const int T = a.set.flag_list[slot];
         const Chan& ch = a.chan[a.set.flag_ch[slot]];
         const int t = (int)(T - ch.tile_off);
-        const int sx = (t % ch.tnx) * TILE + 4 * (sub & 1);
-        const int sy = ((t / ch.tnx) % ch.tny) * TILE + 4 * ((sub >> 1) & 1);
-        const int sz = (t / (ch.tnx * ch.tny)) * TILE + 4 * (sub >> 2);
-        int64_t beg = a.set.slot_off[slot], end = a.set.slot_off[slot + 1];
-        if (end > a.list_cap) end = a.list_cap;
-        for (int64_t scan0 = beg; scan0 < end;) {
-            // 1. collect overlapping nodes (with their weights and force) into LDS
-            if (tid == 0) ncand = 0;
+        const int tx0 = (t % ch.tnx) * TILE;
+        const int ty0 = ((t / ch.tnx) % ch.tny) * TILE;
+        const int tz0 = (t / (ch.tnx * ch.tny)) * TILE;
+        const bool wrap_y = !ch.walls;
+        for (int64_t b0 = beg; b0 < end; b0 += SP_BATCH) {
+            const int nb = (int)(end - b0 < SP_BATCH ? end - b0 : SP_BATCH);
+            __syncthreads();  // the previous batch is consumed (and acc is cleared)
+            for (int k = tid; k < nb; k += SP_THREADS) {
+                const int64_t m = a.list[b0 + k];
+                const float4* r = (const float4*)(a.rec + m * REC);
+                const float4 r0 = r[0];
+                base[k] = make_int4(__float_as_int(r0.x), __float_as_int(r0.y), __float_as_int(r0.z), 0);
+                wrec[k][0] = r[1];
+                wrec[k][1] = r[2];
+                wrec[k][2] = r[3];
+                wrec[k][3] = r[4];
+            }
             __syncthreads();
-            int64_t scan = scan0;
-            for (; scan < end; scan += SP_U * SP_THREADS) {
-                int64_t mm[SP_U];
-#pragma unroll
-                for (int u = 0; u < SP_U; ++u) {
-                    const int64_t k = scan + tid + u * SP_THREADS;
-                    mm[u] = k < end ? (int64_t)a.list[k] : -1;
+            for (int q = wave; q < nb; q += SP_THREADS / 64) {
+                const int4 bq = base[q];
+                int cx = bq.x + ix, cy = bq.y + iy, cz = bq.z + iz;
+                if (cx >= ch.nx) cx -= ch.nx;
+                if (cz >= ch.nz) cz -= ch.nz;
+                bool ok = true;
+                if (wrap_y) {
+                    if (cy >= ch.ny) cy -= ch.ny;
+                } else {
+                    ok = cy >= 0 && cy < ch.ny;
                 }
-#pragma unroll
-                for (int u = 0; u < SP_U; ++u) {
-                    if (mm[u] < 0) continue;
-                    const int4 nb = a.nbase[mm[u]];
-                    int lx, cnx, ox, ly, cny, oy, lz, cnz, oz;
-                    overlap(nb.x, sx, ch.nx, true, lx, cnx, ox);
-                    overlap(nb.y, sy, ch.ny, !ch.walls, ly, cny, oy);
-                    overlap(nb.z, sz, ch.nz, true, lz, cnz, oz);
-                    if (cnx && cny && cnz) {
-                        const int q = atomicAdd(&ncand, 1);
-                        box[q] = lx | (cnx << 3) | (ox << 6) | (ly << 9) | (cny << 12) | (oy << 15) | (lz << 18) |
-                                 (cnz << 21) | (oz << 24);
-                        const float* r = a.rec + mm[u] * REC;
-#pragma unroll
-                        for (int e = 0; e < 15; ++e) wf[e][q] = r[4 + e];
-                    }
-                }
-                __syncthreads();
-                const int nowc = ncand;  // every thread reads the count before the next pass appends
-                __syncthreads();
-                if (nowc > SP_BATCH - SP_U * SP_THREADS) {
-                    scan += SP_U * SP_THREADS;
-                    break;
+                const int lx = cx - tx0, ly = cy - ty0, lz = cz - tz0;
+                if (ok && (unsigned)lx < (unsigned)TILE && (unsigned)ly < (unsigned)TILE && (unsigned)lz < (unsigned)TILE) {
+                    const float* w = (const float*)wrec[q];
+                    const float ww = w[ix] * (w[4 + iy] * w[8 + iz]);
+                    const int loc = (lz << 6) | (ly << 3) | lx;
+                    atomicAdd(&acc[loc], fixed_round(ww * w[12], scale));
+                    atomicAdd(&acc[TILE_CELLS + loc], fixed_round(ww * w[13], scale));
+                    atomicAdd(&acc[2 * TILE_CELLS + loc], fixed_round(ww * w[14], scale));
                 }
             }
-            scan0 = scan;
-            const int nc = ncand;
-            // 2. pair counts -> exclusive prefix (block scan, chunks of SP_THREADS)
-            int carry = 0;
-            for (int base = 0; base < nc; base += SP_THREADS) {
-                const int q = base + tid;
-                int v = 0;
-                if (q < nc) {
-                    const int b = box[q];
-                    v = ((b >> 3) & 7) * ((b >> 12) & 7) * ((b >> 21) & 7);
-                }
-                int incl = v;
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const int u = __shfl_up(incl, d, 64);
-                    if (lane >= d) incl += u;
-                }
-                if (lane == 63) wsum[wave] = incl;
-                __syncthreads();
-                int woff = 0;
-                for (int w = 0; w < wave; ++w) woff += wsum[w];
-                if (q < nc) pre[q] = carry + woff + incl - v;
-                int tot = 0;
-                for (int w = 0; w < SP_THREADS / 64; ++w) tot += wsum[w];
-                __syncthreads();
-                carry += tot;
-            }
-            if (tid == 0) pre[nc] = carry;
-            __syncthreads();
-            // 3. pairs, in windows of SP_WIN: an owner map (pair -> node) is filled for the
-            //    window, then consecutive threads take consecutive pairs, so the lanes of a
-            //    wavefront mostly cover one node's stencil points (different cells)
-            const int P = pre[nc];
-            for (int w0 = 0; w0 < P; w0 += SP_WIN) {
-                const int w1 = w0 + SP_WIN < P ? w0 + SP_WIN : P;
-                for (int c = tid; c < nc; c += SP_THREADS) {
-                    int q0 = pre[c], q1 = pre[c + 1];
-                    if (q0 < w0) q0 = w0;
-                    if (q1 > w1) q1 = w1;
-                    for (int q = q0; q < q1; ++q) owner[q - w0] = (unsigned short)c;
-                }
-                __syncthreads();
-                for (int p = w0 + tid; p < w1; p += SP_THREADS) {
-                    const int c = owner[p - w0];
-                    const int j = p - pre[c];
-                    const int b = box[c];
-                    const int cnx = (b >> 3) & 7, cny = (b >> 12) & 7;
-                    const int jx = div_small(j, cnx);
-                    const int jy = div_small(jx, cny);
-                    const int ix = j - jx * cnx, iy = jx - jy * cny, iz = jy;
-                    const int da = (b & 7) + ix, db = ((b >> 9) & 7) + iy, dc = ((b >> 18) & 7) + iz;
-                    const int loc = ((((b >> 24) & 7) + iz) << 4) | ((((b >> 15) & 7) + iy) << 2) | (((b >> 6) & 7) + ix);
-                    const float ww = wf[da][c] * (wf[4 + db][c] * wf[8 + dc][c]);
-                    atomicAdd(&acc[loc], (unsigned long long)fixed_round(ww * wf[12][c], scale));
-                    atomicAdd(&acc[64 + loc], (unsigned long long)fixed_round(ww * wf[13][c], scale));
-                    atomicAdd(&acc[128 + loc], (unsigned long long)fixed_round(ww * wf[14][c], scale));
-                }
-                __syncthreads();
-            }
-        }
-        float* out = a.force + (int64_t)slot * (3 * TILE_CELLS);
-        for (int k = tid; k < 3 * 64; k += SP_THREADS) {
-            const int d = k >> 6, l = k & 63;
-            const int lx = (sx & 7) + (l & 3), ly = (sy & 7) + ((l >> 2) & 3), lz = (sz & 7) + (l >> 4);
-            out[d * TILE_CELLS + ((lz << 6) | (ly << 3) | lx)] =
-                nonfinite ? __builtin_nanf("") : (float)((double)(long long)acc[k] * inv);
         }
         __syncthreads();
+        float* out = a.force + (int64_t)slot * (3 * TILE_CELLS);
+        if (!split) {
+            for (int k = tid; k < 3 * TILE_CELLS; k += SP_THREADS)
+                out[k] = nonfinite ? __builtin_nanf("") : (float)((double)(long long)acc[k] * inv);
+        } else {
+            // this chunk's partial block; k_ib_merge adds the tile's blocks
+            unsigned long long* pb = a.part + ((int64_t)bigid + c) * (3 * TILE_CELLS);
+            for (int k = tid; k < 3 * TILE_CELLS; k += SP_THREADS) pb[k] = acc[k];
+        }
+        __syncthreads();
+    }
+}
+
+// Force blocks of split tiles: the sum of their chunks' partial blocks (chunk order).
+constexpr int MG_THREADS = 512;
+__global__ void __launch_bounds__(MG_THREADS) k_ib_merge(IbArgs a) {
+    const int nf = a.set.hdr->nflag;
+    const bool nonfinite = a.set.hdr->nonfinite != 0;
+    const double inv = ldexp(1.0, -a.set.hdr->scale_exp);
+    for (int slot = blockIdx.x; slot < nf; slot += gridDim.x) {
+        const int bigid = a.set.big[slot];
+        if (bigid < 0) continue;
+        const int nch = a.set.chunk_off[slot + 1] - a.set.chunk_off[slot];
+        const unsigned long long* pb = a.part + (int64_t)bigid * (3 * TILE_CELLS);
+        float* out = a.force + (int64_t)slot * (3 * TILE_CELLS);
+        for (int k = threadIdx.x; k < 3 * TILE_CELLS; k += MG_THREADS) {
+            unsigned long long v = 0ull;
+            for (int j0 = 0; j0 < nch; j0 += 8) {
+                unsigned long long t[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) t[u] = j0 + u < nch ? pb[(int64_t)(j0 + u) * (3 * TILE_CELLS) + k] : 0ull;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v += t[u];
+            }
+            out[k] = nonfinite ? __builtin_nanf("") : (float)((double)(long long)v * inv);
+        }
     }
 }
 
@@ -516,12 +484,14 @@ hipError_t launch_ib_spread(lbm_ctx* c, const IbArgs& a) {
     if (a.n > 0) k_ib_bin<<<dim3(nb), dim3(256), 0, c->stream>>>(a);
     k_ib_scan<<<dim3(1), dim3(1024), 0, c->stream>>>(a);
     if (a.n > 0) k_ib_scatter<<<dim3(nb), dim3(256), 0, c->stream>>>(a);
-    // the number of flagged tiles is only known on the device: a grid of a few workgroups
-    // per CU walks the work items (launching one workgroup per possible item costs more in
-    // empty waves than the work itself)
-    int64_t g = 8 * c->max_slots < c->ib_grid ? 8 * c->max_slots : c->ib_grid;
+    // the number of work items is only known on the device: a grid of a few workgroups per
+    // CU walks them (launching one workgroup per possible item costs more in empty waves
+    // than the work itself)
+    int64_t g = c->max_items < c->ib_grid ? c->max_items : c->ib_grid;
     if (g < 1) g = 1;
     k_ib_spread<<<dim3((unsigned)g), dim3(SP_THREADS), 0, c->stream>>>(a);
+    const int64_t gm = c->max_slots < c->ib_grid ? c->max_slots : c->ib_grid;
+    k_ib_merge<<<dim3((unsigned)(gm < 1 ? 1 : gm)), dim3(MG_THREADS), 0, c->stream>>>(a);
     return hipGetLastError();
 }
 

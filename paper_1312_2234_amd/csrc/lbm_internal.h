@@ -16,7 +16,8 @@ struct IbHdr {
     uint32_t fmax_bits;  // max |F| over the nodes (float bits)
     int32_t scale_exp;   // fixed-point scale 2^scale_exp of the spread accumulation
     int32_t nonfinite;   // 1 if a force was Inf/NaN
-    int32_t pad[4];
+    int32_t nchunk;      // spread work items (node-list chunks) of the flagged tiles
+    int32_t pad[3];
 };
 
 // Device arrays of one tile set.  Two sets alternate between successive spreads so
@@ -28,8 +29,17 @@ struct IbSet {
     int32_t* flag_ch;    // [max_slots] channel of each slot
     int32_t* fill;       // [max_slots] fill counters of the node lists
     int32_t* slot_off;   // [max_slots+1] list offsets
+    int32_t* chunk_off;  // [max_slots+1] first spread work item of each slot
+    int32_t* big;        // [max_slots] first partial block of a slot split into several work
+                         // items, -1 if the slot is one work item
     IbHdr* hdr;
 };
+
+// Spreading splits a tile's node list into chunks of SP_CHUNK nodes; each chunk of a split
+// tile stores its exact fixed-point partial sums in one of `part_cap` partial blocks, and a
+// merge kernel adds them up.
+constexpr int SP_CHUNK = 256;
+constexpr int64_t SP_PART_MAX = 16384;
 
 // Arguments of the lattice kernels (walk over 64-cell segments of all channels).
 struct LatArgs {
@@ -75,6 +85,10 @@ struct IbArgs {
     int32_t* rank;          // [n][27] packed rank of a node in each tile list it joins
     int32_t* blkbase;       // [ceil(n/256)][2048] per-block base of each hashed tile
     int4* nbase;            // [n] stencil base (x, y, z) and channel of every node
+    unsigned long long* part;  // [part_cap][3][512] fixed-point partial sums of split tiles' chunks
+    int64_t part_cap;
+    int32_t* item_slot;     // [max_items] slot of each spread work item
+    int64_t max_items;
 };
 
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
@@ -132,8 +146,8 @@ struct MlpPacked {
 static_assert(sizeof(MlpPacked) == MLP_PACKED_BYTES, "packed network size");
 
 struct Layout {
-    size_t chan, seg_ch, popA, popB, flags, closure, node_ch, rec, rank, blkbase, nbase, sets[2][7], list, force,
-        vel, total;
+    size_t chan, seg_ch, popA, popB, flags, closure, node_ch, rec, rank, blkbase, nbase, sets[2][9], list, force,
+        vel, part, item_slot, total;
 };
 
 }  // namespace lbmib
@@ -166,6 +180,10 @@ struct lbm_ctx {
     int32_t* d_rank = nullptr;
     int32_t* d_blkbase = nullptr;
     int4* d_nbase = nullptr;
+    unsigned long long* d_part = nullptr;
+    int64_t part_cap = 0;
+    int32_t* d_item_slot = nullptr;
+    int64_t max_items = 0;
     int64_t ib_grid = 1024;  // workgroups of the grid-stride IB kernels (set from the CU count)
     float* d_force = nullptr;
     float* d_vel = nullptr;
