@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lbm-only-steps", type=int, default=200)
     ap.add_argument("--tune", action="store_true", help="re-time the lattice kernel's launch shapes")
+    ap.add_argument("--launch", default=None,
+                    help="lattice launch shape as JSON, e.g. '{\"block\": 256, \"xcd_remap\": 0}' (skips the tuner cache)")
     ap.add_argument("--closure", action="store_true",
                     help="run the step with the learned closure (seeded weights; throughput only)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -156,7 +158,11 @@ def main():
     lat.init()
     from paper_1312_2234_amd import tune
 
-    launch, _ = tune.apply_cached_or_tune(lat, retune=args.tune)
+    if args.launch:
+        cfg = dict(tune.DEFAULT, **json.loads(args.launch))
+        lat.set_launch(**cfg)
+    else:
+        tune.apply_cached_or_tune(lat, retune=args.tune)
     lat.init()
     if args.closure:
         lat.set_closure(*closure_weights(torch, dev), 1.0)

@@ -80,7 +80,8 @@ Layout layout_of(const lbm_params* p, int32_t nch, lbm_storage st, int64_t max_n
         L.node_ch = take(sizeof(int32_t) * max_nodes);
         L.rec = take(sizeof(float) * 20 * max_nodes);
         L.rank = take(sizeof(int32_t) * 27 * max_nodes);
-        L.blkbase = take(sizeof(int32_t) * 2048 * ((max_nodes + 255) / 256));
+        L.blkbase = take(sizeof(int32_t) * HS * ((max_nodes + 255) / 256));
+        L.blkmax = take(sizeof(uint32_t) * ((max_nodes + 255) / 256));
         L.nbase = take(sizeof(int4) * max_nodes);
         for (int k = 0; k < 2; ++k) {
             L.sets[k][0] = take(sizeof(int32_t) * sz.tiles);           // cnt
@@ -150,6 +151,7 @@ IbArgs ib_args(lbm_ctx* c, int set) {
     a.part = c->d_part;
     a.part_cap = c->part_cap;
     a.item_slot = c->d_item_slot;
+    a.blkmax = c->d_blkmax;
     a.max_items = c->max_items;
     return a;
 }
@@ -248,6 +250,7 @@ lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib
         c->d_part = (unsigned long long*)(c->ws + L.part);
         c->part_cap = part_cap_of(sz);
         c->d_item_slot = (int32_t*)(c->ws + L.item_slot);
+        c->d_blkmax = (uint32_t*)(c->ws + L.blkmax);
         c->max_items = max_items_of(sz);
     }
 
@@ -501,6 +504,7 @@ static lbm_status coupled(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, doub
         b.X = X;
         b.U = U;
         b.Xout = X;  // X <- X + U, fused into the gather
+        b.use_rec = 1;  // X is the spread's X
         if (launch_ib_interp(c, b) != hipSuccess) return LBM_ERR_HIP;
         (void)n;
     }

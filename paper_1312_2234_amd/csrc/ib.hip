@@ -103,7 +103,6 @@ __device__ __forceinline__ void stencil_cells(const Chan& ch, int bx, int by, in
 // in `blkbase`) plus its rank inside the block (kept packed in `rank`).  With nodes numbered
 // along the surface a block touches a few tiles, so global atomics drop from one per
 // (node, tile) to a few per block.
-constexpr int HS = 2048;   // hash entries per block
 constexpr int MAXT = 27;   // most tiles a 4x4x4 stencil can touch
 
 __device__ __forceinline__ int chan_of_tile(const Chan* chan, int nch, int64_t T) {
@@ -193,7 +192,7 @@ __global__ void __launch_bounds__(256) k_ib_bin(IbArgs a) {
         }
         int32_t* rk = a.rank + m * MAXT;
         for_tiles(ch, b[0], b[1], b[2], [&](int q, int64_t T) {
-            int h = (int)(((uint32_t)T * 2654435761u) >> 21) & (HS - 1);
+            int h = (int)(((uint32_t)T * 2654435761u) >> (32 - HS_BITS)) & (HS - 1);
             int packed = INT32_MIN;
             for (int probe = 0; probe < 64; ++probe) {
                 const int old = atomicCAS(&hkey[h], -1, (int)T);
@@ -219,15 +218,15 @@ __global__ void __launch_bounds__(256) k_ib_bin(IbArgs a) {
     }
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = __uint_as_float(ub);
     __syncthreads();
+    // only the entries in use are read back (by the scatter)
     int32_t* bb = a.blkbase + (int64_t)blockIdx.x * HS;
     for (int e = threadIdx.x; e < HS; e += blockDim.x) {
         const int T = hkey[e];
-        int base = 0;
         if (T >= 0) {
-            base = atomicAdd(&a.set.cnt[T], hcnt[e]);
+            const int base = atomicAdd(&a.set.cnt[T], hcnt[e]);
             if (base == 0) append_flagged(a, T);
+            bb[e] = base;
         }
-        bb[e] = base;
     }
     if (threadIdx.x == 0) {
         uint32_t mx = 0;
@@ -235,7 +234,7 @@ __global__ void __launch_bounds__(256) k_ib_bin(IbArgs a) {
             const uint32_t v = __float_as_uint(wmax[k]);
             mx = v > mx ? v : mx;
         }
-        atomicMax(&a.set.hdr->fmax_bits, mx);
+        a.blkmax[blockIdx.x] = mx;  // reduced by the scan
     }
 }
 
@@ -303,7 +302,26 @@ __global__ void __launch_bounds__(1024) k_ib_scan(IbArgs a) {
             for (int j = 0; j < 3; ++j) carry[j] = excl[j] + val[j];
         __syncthreads();
     }
+    // max |F| over the bin blocks' maxima (float bits order like the values; NaN/Inf above all)
+    __shared__ uint32_t fmx[16];
+    {
+        const int nbk = (int)((a.n + 255) / 256);
+        uint32_t mx = 0;
+        for (int k = tid; k < nbk; k += blockDim.x) {
+            const uint32_t v = a.blkmax[k];
+            mx = v > mx ? v : mx;
+        }
+        for (int d = 32; d >= 1; d >>= 1) {
+            const uint32_t o = __shfl_xor(mx, d, 64);
+            mx = o > mx ? o : mx;
+        }
+        if (lane == 0) fmx[wave] = mx;
+        __syncthreads();
+    }
     if (tid == 0) {
+        uint32_t mxall = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mxall = fmx[w] > mxall ? fmx[w] : mxall;
+        a.set.hdr->fmax_bits = mxall;
         const int total = carry[0];
         a.set.slot_off[nf] = total;
         a.set.chunk_off[nf] = carry[1];
@@ -541,24 +559,41 @@ __global__ void __launch_bounds__(256) k_ib_gather(IbArgs a) {
     double X[3] = {0.0, 0.0, 0.0};
     const bool valid = m < a.n;
     if (valid) {
-        const int c = a.node_ch[m];
-        const Chan& ch = a.chan[c];
         float w[3][4];
         int b[3];
-        for (int d = 0; d < 3; ++d) {
-            X[d] = a.X[d * a.n + m];
-            const int dim = d == 0 ? ch.nx : (d == 1 ? ch.ny : ch.nz);
-            const bool finite = isfinite(X[d]) && fabs(X[d]) < 1e9;
-            int64_t base = finite ? ib_weights(a.kernel, X[d], w[d]) : 0;
-            if (!finite) w[d][0] = w[d][1] = w[d][2] = w[d][3] = 0.0f;
-            if (d == 1 && ch.walls) {
-                if (base < -4) base = -4;
-                if (base > ch.ny) base = ch.ny;
-                b[d] = (int)base;
-            } else {
-                b[d] = wrapi(base, dim);
+        int c;
+        if (a.use_rec) {
+            // positions unchanged since the spread: its node record holds base and weights
+            const float4* r = (const float4*)(a.rec + m * REC);
+            const float4 r0 = r[0], rx = r[1], ry = r[2], rz = r[3];
+            b[0] = __float_as_int(r0.x);
+            b[1] = __float_as_int(r0.y);
+            b[2] = __float_as_int(r0.z);
+            c = __float_as_int(r0.w);
+            w[0][0] = rx.x; w[0][1] = rx.y; w[0][2] = rx.z; w[0][3] = rx.w;
+            w[1][0] = ry.x; w[1][1] = ry.y; w[1][2] = ry.z; w[1][3] = ry.w;
+            w[2][0] = rz.x; w[2][1] = rz.y; w[2][2] = rz.z; w[2][3] = rz.w;
+            if (a.Xout)
+                for (int d = 0; d < 3; ++d) X[d] = a.X[d * a.n + m];
+        } else {
+            c = a.node_ch[m];
+            const Chan& ch = a.chan[c];
+            for (int d = 0; d < 3; ++d) {
+                X[d] = a.X[d * a.n + m];
+                const int dim = d == 0 ? ch.nx : (d == 1 ? ch.ny : ch.nz);
+                const bool finite = isfinite(X[d]) && fabs(X[d]) < 1e9;
+                int64_t base = finite ? ib_weights(a.kernel, X[d], w[d]) : 0;
+                if (!finite) w[d][0] = w[d][1] = w[d][2] = w[d][3] = 0.0f;
+                if (d == 1 && ch.walls) {
+                    if (base < -4) base = -4;
+                    if (base > ch.ny) base = ch.ny;
+                    b[d] = (int)base;
+                } else {
+                    b[d] = wrapi(base, dim);
+                }
             }
         }
+        const Chan& ch = a.chan[c];
         // this lane's stencil row (y index bq, z index cq), selected without dynamic indexing
         const float wy = bq == 0 ? w[1][0] : (bq == 1 ? w[1][1] : (bq == 2 ? w[1][2] : w[1][3]));
         const float wz = cq == 0 ? w[2][0] : (cq == 1 ? w[2][1] : (cq == 2 ? w[2][2] : w[2][3]));

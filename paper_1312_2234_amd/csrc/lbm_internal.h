@@ -39,6 +39,9 @@ struct IbSet {
 // tile stores its exact fixed-point partial sums in one of `part_cap` partial blocks, and a
 // merge kernel adds them up.
 constexpr int SP_CHUNK = 256;
+// Binning: per-block LDS hash of tile counts (HS entries).
+constexpr int HS_BITS = 9;
+constexpr int HS = 1 << HS_BITS;
 constexpr int64_t SP_PART_MAX = 16384;
 
 // Arguments of the lattice kernels (walk over 64-cell segments of all channels).
@@ -81,12 +84,14 @@ struct IbArgs {
     uint32_t* flags;
     const void* pop;        // current stored populations (interpolation)
     int32_t kernel;         // ib_kernel
+    int32_t use_rec;        // interpolation at the positions of the latest spread: reuse its node records
     int32_t nch;
     int32_t* rank;          // [n][27] packed rank of a node in each tile list it joins
     int32_t* blkbase;       // [ceil(n/256)][2048] per-block base of each hashed tile
     int4* nbase;            // [n] stencil base (x, y, z) and channel of every node
     unsigned long long* part;  // [part_cap][3][512] fixed-point partial sums of split tiles' chunks
     int64_t part_cap;
+    uint32_t* blkmax;       // [ceil(n/256)] max |F| (float bits) of each bin block
     int32_t* item_slot;     // [max_items] slot of each spread work item
     int64_t max_items;
 };
@@ -147,7 +152,7 @@ static_assert(sizeof(MlpPacked) == MLP_PACKED_BYTES, "packed network size");
 
 struct Layout {
     size_t chan, seg_ch, popA, popB, flags, closure, node_ch, rec, rank, blkbase, nbase, sets[2][9], list, force,
-        vel, part, item_slot, total;
+        vel, part, item_slot, blkmax, total;
 };
 
 }  // namespace lbmib
@@ -183,6 +188,7 @@ struct lbm_ctx {
     unsigned long long* d_part = nullptr;
     int64_t part_cap = 0;
     int32_t* d_item_slot = nullptr;
+    uint32_t* d_blkmax = nullptr;
     int64_t max_items = 0;
     int64_t ib_grid = 1024;  // workgroups of the grid-stride IB kernels (set from the CU count)
     float* d_force = nullptr;
