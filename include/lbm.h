@@ -289,6 +289,14 @@ typedef struct {
     int32_t vec;         /* cells per lane: 0/1 scalar step; 2 or 4 = vector step (aligned V-wide
                             accesses, 256-thread workgroups), used when every channel has
                             nx % V == 0 and nx*ny*nz % (64 V) == 0, else the scalar step runs */
+    int32_t overlap;     /* coupled steps only: 1 = the lattice update with the body force alone runs
+                            on a second stream, overlapped with the previous interpolation and the
+                            force / spread pipeline, then the cells of the flagged IB tiles are
+                            updated again with their force (the same values as the fused update,
+                            bit for bit); 0 = one fused update after the spread.  Ignored while
+                            the learned closure is enabled.  Default 0: on MI355X the
+                            bandwidth-bound update occupies every CU and the latency-bound IB
+                            kernels beside it slow down more than the overlap gains. */
 } lbm_launch;
 
 lbm_status lbm_set_launch(lbm_ctx* ctx, const lbm_launch* cfg /*host*/);

@@ -125,6 +125,9 @@ LatArgs lat_args(lbm_ctx* c) {
     if (c->max_nodes > 0) {
         a.tile_slot = c->set[c->ibset].tile_slot;
         a.force = c->d_force;
+        a.flag_list = c->set[c->ibset].flag_list;
+        a.flag_ch = c->set[c->ibset].flag_ch;
+        a.hdr = c->set[c->ibset].hdr;
     }
     return a;
 }
@@ -305,6 +308,12 @@ lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib
         }
 
     }
+    if (st == LBM_OK && max_nodes > 0) {
+        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_state, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_far, hipEventDisableTiming) != hipSuccess)
+            st = LBM_ERR_HIP;
+    }
     if (st == LBM_OK) {
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess &&
@@ -312,7 +321,7 @@ lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib
             c->ib_grid = 4 * (int64_t)cus;
     }
     if (st != LBM_OK) {
-        delete c;
+        lbm_destroy(c);
         return st;
     }
     *out = c;
@@ -322,6 +331,13 @@ lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib
 lbm_status lbm_destroy(lbm_ctx* c) {
     if (!c) return LBM_OK;
     hipError_t e = hipStreamSynchronize(c->stream);
+    if (c->side) {
+        const hipError_t e2 = hipStreamSynchronize(c->side);
+        if (e == hipSuccess) e = e2;
+        hipStreamDestroy(c->side);
+    }
+    if (c->ev_state) hipEventDestroy(c->ev_state);
+    if (c->ev_far) hipEventDestroy(c->ev_far);
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     if (c->graph) hipGraphDestroy(c->graph);
     delete c;
@@ -484,8 +500,32 @@ lbm_status ib_membrane_forces(const ib_membrane* m, const double* X, float* F, v
     return hip_ok(launch_membrane_forces(m, X, F, (hipStream_t)stream));
 }
 
+// Lattice update of the whole context with the body force alone, on the second stream,
+// once the state it reads is complete on the main stream.
+static hipError_t far_update(lbm_ctx* c) {
+    hipError_t e = hipEventRecord(c->ev_state, c->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_state, 0);
+    if (e != hipSuccess) return e;
+    LatArgs la = lat_args(c);
+    la.tile_slot = nullptr;
+    la.force = nullptr;
+    hipStream_t main = c->stream;
+    c->stream = c->side;
+    e = launch_lattice(c, LK_STEP, la);
+    c->stream = main;
+    if (e == hipSuccess) e = hipEventRecord(c->ev_far, c->side);
+    return e;
+}
+
+// Fig. 1, `nsteps` times: forces -> spread -> lattice update -> interpolation (+ move).
+// With the overlapped schedule, the update of step s+1 away from the IB tiles (body force
+// only) is issued on the second stream right after step s's update, so it runs during the
+// interpolation of step s and the force / spread pipeline of step s+1; step s+1 then waits
+// for it and updates the flagged tiles' cells with their force.  Both buffers are only
+// read by everything that runs concurrently with the far update except its own output.
 static lbm_status coupled(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, double* X, float* F, float* U) {
-    const int64_t n = c->n_nodes;
+    const bool ov = c->launch.overlap && c->side && !c->closure && nsteps > 0;
+    if (ov && far_update(c) != hipSuccess) return LBM_ERR_HIP;
     for (int s = 0; s < nsteps; ++s) {
         if (m) {
             hipError_t e = launch_membrane_forces(m, X, F, c->stream);
@@ -497,16 +537,22 @@ static lbm_status coupled(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, doub
         a.F = F;
         if (launch_ib_spread(c, a) != hipSuccess) return LBM_ERR_HIP;
         LatArgs la = lat_args(c);
-        hipError_t e = c->closure ? launch_step_closure(c, la) : launch_lattice(c, LK_STEP, la);
+        hipError_t e;
+        if (ov) {
+            e = hipStreamWaitEvent(c->stream, c->ev_far, 0);
+            if (e == hipSuccess) e = launch_step_tiles(c, la);
+        } else {
+            e = c->closure ? launch_step_closure(c, la) : launch_lattice(c, LK_STEP, la);
+        }
         if (e != hipSuccess) return LBM_ERR_HIP;
         c->cur ^= 1;
+        if (ov && s + 1 < nsteps && far_update(c) != hipSuccess) return LBM_ERR_HIP;
         IbArgs b = ib_args(c, c->ibset);
         b.X = X;
         b.U = U;
         b.Xout = X;  // X <- X + U, fused into the gather
         b.use_rec = 1;  // X is the spread's X
         if (launch_ib_interp(c, b) != hipSuccess) return LBM_ERR_HIP;
-        (void)n;
     }
     return LBM_OK;
 }
@@ -564,7 +610,8 @@ lbm_status lbm_set_launch(lbm_ctx* c, const lbm_launch* cfg) {
     const int b = cfg->block;
     if (b != 64 && b != 128 && b != 256 && b != 512 && b != 1024) return LBM_ERR_ARG;
     if (cfg->persistent < 0 || (cfg->xcd_remap != 0 && cfg->xcd_remap != 1) ||
-        (cfg->nontemporal != 0 && cfg->nontemporal != 1) || cfg->vec < 0 || cfg->vec > 4 || cfg->vec == 3)
+        (cfg->nontemporal != 0 && cfg->nontemporal != 1) || cfg->vec < 0 || cfg->vec > 4 || cfg->vec == 3 ||
+        (cfg->overlap != 0 && cfg->overlap != 1))
         return LBM_ERR_ARG;
     c->launch = *cfg;
     return LBM_OK;

@@ -45,6 +45,37 @@ __global__ void __launch_bounds__(1024) k_step(LatArgs a) {
     });
 }
 
+// The same update for the cells of the flagged IB tiles only (one workgroup of 512 threads
+// per tile, one cell per thread), with their force.  Used after a full update with the body
+// force alone: it overwrites exactly the cells whose IB force may be nonzero, with the
+// values the fused update produces.
+template <class St>
+__global__ void __launch_bounds__(TILE_CELLS) k_step_tiles(LatArgs a) {
+    using T = typename St::T;
+    const int nf = a.hdr->nflag;
+    const int l = threadIdx.x;
+    for (int slot = blockIdx.x; slot < nf; slot += gridDim.x) {
+        const Chan& ch = a.chan[a.flag_ch[slot]];
+        const int t = (int)(a.flag_list[slot] - ch.tile_off);
+        const int x = (t % ch.tnx) * TILE + (l & 7);
+        const int y = ((t / ch.tnx) % ch.tny) * TILE + ((l >> 3) & 7);
+        const int z = (t / (ch.tnx * ch.tny)) * TILE + (l >> 6);
+        if (x >= ch.nx || y >= ch.ny || z >= ch.nz) continue;
+        const int32_t n = x + ch.nx * (y + ch.ny * z);
+        const T* s = (const T*)a.src + ch.pop_off;
+        T* d = (T*)a.dst + ch.pop_off;
+        float g[Q];
+        pull<St>(s, ch, ch.ncell, n, x, y, z, g);
+        float drho, jx, jy, jz, Fx, Fy, Fz;
+        moments(g, drho, jx, jy, jz);
+        ib_force(a, ch, x, y, z, Fx, Fy, Fz);
+        const CellState cs = cell_state(drho, jx, jy, jz, Fx, Fy, Fz);
+        const float om = ch.omega, guo = ch.guo;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) St::st(d + pidx(i, n), bgk_c(i, g[i], cs, om, guo));
+    }
+}
+
 // Vector form of the same step: V consecutive cells of one x-row per lane (nx % V == 0,
 // every channel a whole number of 64V-cell units), so every population is read and written
 // with one aligned V-wide access per lane and a wavefront covers 64V consecutive cells of
@@ -407,6 +438,18 @@ hipError_t launch_lattice(lbm_ctx* c, int which, const LatArgs& a) {
         case LBM_STORE_BF16: return launch_typed<StBF16>(c, which, a);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_step_tiles(lbm_ctx* c, const LatArgs& a) {
+    int64_t g = c->max_slots < c->ib_grid ? c->max_slots : c->ib_grid;
+    if (g < 1) g = 1;
+    const dim3 grid((unsigned)g), block(TILE_CELLS);
+    switch (c->storage) {
+        case LBM_STORE_F32: k_step_tiles<StF32><<<grid, block, 0, c->stream>>>(a); break;
+        case LBM_STORE_F16: k_step_tiles<StF16><<<grid, block, 0, c->stream>>>(a); break;
+        case LBM_STORE_BF16: k_step_tiles<StBF16><<<grid, block, 0, c->stream>>>(a); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_wss(lbm_ctx* c, const LatArgs& a, int64_t total) {

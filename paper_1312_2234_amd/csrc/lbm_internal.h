@@ -53,6 +53,9 @@ struct LatArgs {
     void* dst;              // next buffer (lbm_step) or unused
     const int32_t* tile_slot;  // IB tile -> slot of the current force field, or null
     const float* force;        // [slots][3][512]
+    const int32_t* flag_list;  // flagged tiles of the current force field (tile update)
+    const int32_t* flag_ch;
+    const IbHdr* hdr;
     int32_t remap;          // XCD-aware block order
     int32_t persistent;     // loop over blocks
     // auxiliary inputs / outputs of the non-step kernels
@@ -193,7 +196,9 @@ struct lbm_ctx {
     int64_t ib_grid = 1024;  // workgroups of the grid-stride IB kernels (set from the CU count)
     float* d_force = nullptr;
     float* d_vel = nullptr;
-    lbm_launch launch{256, 1, 0, 1, 0};
+    lbm_launch launch{256, 1, 0, 1, 0, 0};
+    hipStream_t side = nullptr;         // second stream of the overlapped coupled step
+    hipEvent_t ev_state = nullptr, ev_far = nullptr;
     lbmib::MlpPacked* d_mlp = nullptr;
     bool closure = false;
     hipGraph_t graph = nullptr;
@@ -204,6 +209,7 @@ namespace lbmib {
 
 // lattice.hip
 hipError_t launch_lattice(lbm_ctx* c, int which, const LatArgs& a);
+hipError_t launch_step_tiles(lbm_ctx* c, const LatArgs& a);
 enum { LK_STEP = 0, LK_INIT, LK_MOMENTS, LK_GETF, LK_SETF, LK_WSS };
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
 hipError_t launch_wss(lbm_ctx* c, const LatArgs& a, int64_t total);

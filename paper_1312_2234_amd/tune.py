@@ -15,7 +15,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(_HERE, "tuned_launch.json")
 
-DEFAULT = dict(block=256, xcd_remap=1, persistent=0, nontemporal=1, vec=0)
+DEFAULT = dict(block=256, xcd_remap=1, persistent=0, nontemporal=1, vec=0, overlap=0)
 
 
 def candidates(n_cu=256):
@@ -46,7 +46,7 @@ def arch_name(torch, device):
 def time_launch(lat, cfg, steps=20, warmup=3):
     """Average time (ms) of one lattice step with launch shape `cfg` (the state advances)."""
     torch = lat.torch
-    lat.set_launch(**cfg)
+    lat.set_launch(**dict(DEFAULT, **cfg))
     lat.step(warmup)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -66,7 +66,7 @@ def tune(lat, steps=20, cands=None, verbose=False):
         if verbose:
             print("%.4f ms  %s" % (ms, cfg), flush=True)
     table.sort(key=lambda t: t[0])
-    best = table[0][1]
+    best = dict(DEFAULT, **table[0][1])
     lat.set_launch(**best)
     return best, table
 
@@ -102,6 +102,7 @@ def apply_cached_or_tune(lat, steps=20, verbose=False, retune=False):
     """Use the cached launch for this size class if there is one, else tune and cache."""
     cfg = None if retune else load(lat)
     if cfg is not None:
+        cfg = dict(DEFAULT, **cfg)
         lat.set_launch(**cfg)
         return cfg, None
     best, table = tune(lat, steps=steps, verbose=verbose)
