@@ -238,6 +238,9 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--coarse-steps", type=int, default=2000)
     ap.add_argument("--higher-only", action="store_true", help="correct only moments above second order")
+    ap.add_argument("--weights", default=None, help="evaluate saved weights (a *_weights.pt of a run) only")
+    ap.add_argument("--alpha", type=float, nargs="*", default=[1.0],
+                    help="evaluate with the correction scaled by these factors")
     ap.add_argument("--c-guard", type=float, default=1.0)
     args = ap.parse_args(argv)
 
@@ -255,28 +258,42 @@ def main(argv=None):
     train_seeds = list(range(args.train_seeds))
     val_seeds = list(range(100, 100 + args.val_seeds))
     eval_seeds = list(range(200, 200 + args.eval_seeds))
-    feat, tgt = generate(train_seeds, snapshots=args.snapshots, log=log, **kw)
-    vfeat, vtgt = generate(val_seeds, snapshots=max(2, args.snapshots // 5), log=log, **kw)
-    torch.cuda.synchronize()
-    t_data = time.perf_counter() - t0
-    log("data: %d training samples, %d validation samples, %.1f s" % (feat.shape[0] * feat.shape[1],
-                                                                       vfeat.shape[0] * vfeat.shape[1], t_data))
-    params, norm, hist, t_train = train(feat, tgt, vfeat, vtgt, steps=args.steps,
-                                        batch=min(65536, feat.shape[1]), log=log,
-                                        log_every=max(1, args.steps // 6), higher_only=args.higher_only)
-    nsamp = args.steps * min(65536, feat.shape[1])
-    log("training: %d steps, %.1f s, %.1f M samples/s" % (args.steps, t_train, nsamp / t_train / 1e6))
-    del feat, tgt
-    ev = evaluate(params, norm, eval_seeds, coarse_steps=args.coarse_steps, log=log, c_guard=args.c_guard, **kw)
+    if args.weights:
+        w = torch.load(args.weights, weights_only=True)
+        params, norm = w["params"].to("cuda:0"), w["norm"].to("cuda:0")
+        hist, t_train, t_data, nsamp = [], 0.0, 0.0, 0
+    else:
+        feat, tgt = generate(train_seeds, snapshots=args.snapshots, log=log, **kw)
+        vfeat, vtgt = generate(val_seeds, snapshots=max(2, args.snapshots // 5), log=log, **kw)
+        torch.cuda.synchronize()
+        t_data = time.perf_counter() - t0
+        log("data: %d training samples, %d validation samples, %.1f s" % (feat.shape[0] * feat.shape[1],
+                                                                           vfeat.shape[0] * vfeat.shape[1], t_data))
+        params, norm, hist, t_train = train(feat, tgt, vfeat, vtgt, steps=args.steps,
+                                            batch=min(65536, feat.shape[1]), log=log,
+                                            log_every=max(1, args.steps // 6), higher_only=args.higher_only)
+        nsamp = args.steps * min(65536, feat.shape[1])
+        log("training: %d steps, %.1f s, %.1f M samples/s" % (args.steps, t_train, nsamp / t_train / 1e6))
+        del feat, tgt
+    ev = []
+    for alpha in args.alpha:
+        na = norm.clone()
+        na[32:48] *= alpha  # output scale: the correction times alpha
+        log("alpha %.3g:" % alpha)
+        for r in evaluate(params, na, eval_seeds, coarse_steps=args.coarse_steps, log=log, c_guard=args.c_guard, **kw):
+            r["alpha"] = alpha
+            ev.append(r)
     rep = {"train_seeds": train_seeds, "val_seeds": val_seeds, "eval_seeds": eval_seeds,
            "snapshots_per_seed": args.snapshots, "adam_steps": args.steps, "history": hist,
-           "train_seconds": t_train, "data_seconds": t_data, "train_samples_per_s": nsamp / t_train,
+           "train_seconds": t_train, "data_seconds": t_data,
+           "train_samples_per_s": nsamp / t_train if t_train else None,
            "eval": ev, "norm": norm.cpu().numpy().tolist(), "higher_only": args.higher_only,
            "c_guard": args.c_guard}
     if args.out:
         with open(args.out, "w") as f:
             json.dump(rep, f, indent=1)
-        torch.save({"params": params.cpu(), "norm": norm.cpu()}, args.out.rsplit(".", 1)[0] + "_weights.pt")
+        if not args.weights:
+            torch.save({"params": params.cpu(), "norm": norm.cpu()}, args.out.rsplit(".", 1)[0] + "_weights.pt")
     return rep
 
 

@@ -247,7 +247,9 @@ __global__ void __launch_bounds__(256) k_step_cl(LatArgs a, const MlpPacked* __r
                                                  unsigned long long* guarded) {
     using T = typename St::T;
     __shared__ WaveStage stage[4];
+    __shared__ unsigned int blk_bad;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) blk_bad = 0u;  // first read after the barriers of the first pass
     FwdW W;
     load_fwd(P, W);
     const float* nrm = P->norm;
@@ -313,11 +315,14 @@ __global__ void __launch_bounds__(256) k_step_cl(LatArgs a, const MlpPacked* __r
                     St::st(dst + pidx(i, n), gn);
             }
             const uint64_t bad = __ballot(!ok);
-            if (bad && lane == __ffsll((unsigned long long)bad) - 1) {
-                atomicOr(flags, LBM_FLAG_CLOSURE_FALLBACK);
-                atomicAdd(guarded, (unsigned long long)__popcll(bad));
-            }
+            if (bad && lane == __ffsll((unsigned long long)bad) - 1) atomicAdd(&blk_bad, (unsigned)__popcll(bad));
         }
+    }
+    // one global update per workgroup for the fallback count (the loop is uniform)
+    __syncthreads();
+    if (threadIdx.x == 0 && blk_bad) {
+        atomicOr(flags, LBM_FLAG_CLOSURE_FALLBACK);
+        atomicAdd(guarded, (unsigned long long)blk_bad);
     }
 }
 
