@@ -241,6 +241,9 @@ def main(argv=None):
     ap.add_argument("--weights", default=None, help="evaluate saved weights (a *_weights.pt of a run) only")
     ap.add_argument("--alpha", type=float, nargs="*", default=[1.0],
                     help="evaluate with the correction scaled by these factors")
+    ap.add_argument("--select-alpha", action="store_true",
+                    help="run the --alpha candidates on the validation seeds, keep the one with the lowest "
+                         "wall-stress error, and evaluate only that one on the held-out seeds")
     ap.add_argument("--c-guard", type=float, default=1.0)
     args = ap.parse_args(argv)
 
@@ -275,8 +278,23 @@ def main(argv=None):
         nsamp = args.steps * min(65536, feat.shape[1])
         log("training: %d steps, %.1f s, %.1f M samples/s" % (args.steps, t_train, nsamp / t_train / 1e6))
         del feat, tgt
+    alphas = list(args.alpha)
+    selection = None
+    if args.select_alpha:
+        scores = []
+        for alpha in alphas:
+            na = norm.clone()
+            na[32:48] *= alpha
+            log("validation, alpha %.3g:" % alpha)
+            rs = evaluate(params, na, val_seeds, coarse_steps=args.coarse_steps, log=log, c_guard=args.c_guard, **kw)
+            scores.append((float(np.mean([r["learned_wss_rel_l2"] for r in rs])), alpha, rs))
+        best = min(scores, key=lambda t: t[0])
+        selection = {"candidates": [(a, sc) for sc, a, _ in scores], "chosen": best[1],
+                     "plain_wss_rel_l2": float(np.mean([r["plain_wss_rel_l2"] for r in best[2]]))}
+        log("selected alpha %.3g on the validation seeds" % best[1])
+        alphas = [best[1]]
     ev = []
-    for alpha in args.alpha:
+    for alpha in alphas:
         na = norm.clone()
         na[32:48] *= alpha  # output scale: the correction times alpha
         log("alpha %.3g:" % alpha)
@@ -287,7 +305,8 @@ def main(argv=None):
            "snapshots_per_seed": args.snapshots, "adam_steps": args.steps, "history": hist,
            "train_seconds": t_train, "data_seconds": t_data,
            "train_samples_per_s": nsamp / t_train if t_train else None,
-           "eval": ev, "norm": norm.cpu().numpy().tolist(), "higher_only": args.higher_only,
+           "eval": ev, "alpha_selection": selection, "norm": norm.cpu().numpy().tolist(),
+           "higher_only": args.higher_only,
            "c_guard": args.c_guard}
     if args.out:
         with open(args.out, "w") as f:
