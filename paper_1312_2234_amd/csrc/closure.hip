@@ -106,11 +106,15 @@ __device__ __forceinline__ short bf16_bits(float f) {
     return __builtin_bit_cast(short, b);
 }
 
+// relu, then bfloat16: round first, then clamp the bit patterns as int16 (a negative
+// bfloat16 is a negative int16, -0 included), one packed max per two values; the same
+// result as rounding relu(a) for every finite a
 __device__ __forceinline__ bf4 relu_bf16(acc4 a) {
     bf4 r;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) r[k] = bf16_bits(a[k] > 0.0f ? a[k] : 0.0f);
-    return r;
+    for (int k = 0; k < 4; ++k) r[k] = bf16_bits(a[k]);
+    const bf4 z = {0, 0, 0, 0};
+    return __builtin_elementwise_max(r, z);
 }
 
 __device__ __forceinline__ acc4 mfma(bf4 a, bf4 b, acc4 c) {
@@ -242,8 +246,9 @@ __device__ __forceinline__ void mlp_wave(const FwdW& W, WaveStage& S, const floa
 // The lattice step of k_step (pull, moments, Guo-forced BGK, aligned store) with the
 // learned correction added before the store.  Workgroups of 256 threads walk the
 // segments four at a time with a uniform trip count (the LDS transposes use barriers).
+// (at most 168 registers: three wavefronts per SIMD hide more of the population loads)
 template <class St, bool NT>
-__global__ void __launch_bounds__(256) k_step_cl(LatArgs a, const MlpPacked* __restrict__ P, uint32_t* flags,
+__global__ void __launch_bounds__(256, 3) k_step_cl(LatArgs a, const MlpPacked* __restrict__ P, uint32_t* flags,
                                                  unsigned long long* guarded) {
     using T = typename St::T;
     __shared__ WaveStage stage[4];
