@@ -227,6 +227,131 @@ def evaluate(params, norm, seeds, u_top=0.05, coarse_steps=2000, sample_every=50
     return out
 
 
+def _patch_mean(w, patches=(16, 32)):
+    """Wall-stress field [nz, nx] averaged over a fixed grid of wall patches (z, x), the same
+    physical areas at every resolution."""
+    nz, nx = w.shape
+    pz, px = patches
+    return w.reshape(pz, nz // pz, px, nx // px).mean(axis=(1, 3))
+
+
+def _graph_rate(lat, mem, X, F, U, steps=200, warmup=10):
+    """Coupled steps per second of the 2-step HIP graph replay (the benchmark's schedule)."""
+    import torch
+
+    lat.graph_capture(mem, 2, X, F, U)
+    lat.graph_launch(warmup // 2)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(lat.stream)
+    lat.graph_launch(steps // 2)
+    ev1.record(lat.stream)
+    torch.cuda.synchronize()
+    return (steps // 2) * 2 / (ev0.elapsed_time(ev1) * 1e-3)
+
+
+def _interp_log(xs, ys, y):
+    """x at which the piecewise log-log line through (xs, ys) (ys decreasing) reaches y, or
+    None outside the measured range."""
+    for (x0, y0), (x1, y1) in zip(zip(xs, ys), zip(xs[1:], ys[1:])):
+        if min(y0, y1) <= y <= max(y0, y1) and y0 != y1:
+            t = (np.log(y) - np.log(y0)) / (np.log(y1) - np.log(y0))
+            return float(np.exp(np.log(x0) + t * (np.log(x1) - np.log(x0))))
+    return None
+
+
+def ladder(params, norm, seeds, sizes=(128, 160, 192, 224, 256), storages=("f16", "bf16"), fine_steps=4000,
+           fine_every=80, c_guard=1.0, dev="cuda:0", fine=(256, 128, 128), count=16, log=print):
+    """Throughput at a fixed wall-stress error.  Plain float32 runs of the same suspension at
+    several resolutions (acoustic scaling, equal physical time: fine_steps * r steps), the
+    learned closure at the coarsest, and the 16-bit storage forms at the finest; every error
+    against the finest float32 run.  The bottom-wall shear stress, averaged over the last
+    quarter of the run at the same physical times, is compared on a 16 x 32 grid of wall
+    patches (8 x 8 cells at the finest resolution); centroid velocities of the platelets likewise.  Throughput is the HIP-graph
+    coupled-step rate, also as fine-equivalent cell updates (cells / r^3 per step, 1 / r fine
+    steps per step: MLUPS / r^4).  The plain error-vs-resolution curve, interpolated in
+    log-log, gives the plain resolution (and its throughput) that matches each other run's
+    error."""
+    import torch
+
+    sizes = sorted(sizes)
+    top = sizes[-1]
+    if top != fine[0]:
+        raise ValueError("the finest rung must be the fine lattice")
+    patches = (fine[2] // 8, fine[0] // 8)
+    per_seed = []
+    for seed in seeds:
+        rungs = inputs.resolution_ladder(seed, sizes, count=count, fine=fine)
+        specs = [("plain%d" % n, n, "f32", False) for n in sizes]
+        if params is not None:
+            specs.append(("learned%d" % sizes[0], sizes[0], "f32", True))
+        specs += [("%s%d" % (st, top), top, st, False) for st in storages]
+        res = {}
+        for name, n, st, closure in specs:
+            ch, r = rungs[n]
+            lat = lbm.Lattice([ch], storage=st, max_nodes=ch.bodies.n, device=dev)
+            from . import tune
+
+            cfg = tune.load(lat)
+            if cfg is not None:
+                lat.set_launch(**dict(tune.DEFAULT, **cfg))
+            lat.init()
+            mem, X, F, U = _nodes_setup(lat, ch, dev)
+            mem.offsets = ch.bodies.body_offsets
+            if closure:
+                lat.set_closure(params, norm, c_guard)
+            steps, every = int(round(fine_steps * r)), int(round(fine_every * r))
+            wss, vel, _ = _run(lat, mem, X, F, U, steps, every, (ch.nz, ch.nx))
+            flags = lat.error_flags()
+            rate = _graph_rate(lat, mem, X, F, U)
+            torch.cuda.synchronize()
+            res[name] = {"nx": n, "r": r, "storage": st, "closure": closure, "steps": steps, "tau": ch.tau,
+                         "nodes": ch.bodies.n, "wss": _patch_mean(wss, patches), "vel": vel,
+                         "mlups": ch.cells * rate / 1e6, "fine_eq_mlups": ch.cells * rate / 1e6 / r ** 4,
+                         "flags": flags}
+            del lat
+        ref = res["plain%d" % top]
+        base = float(np.mean(ref["wss"]))
+        for name, v in res.items():
+            v["wss_rel_l2"] = float(np.linalg.norm(v["wss"] - ref["wss"]) / np.linalg.norm(ref["wss"]))
+            v["wss_mean_rel"] = float(abs(np.mean(v["wss"]) - base) / abs(base))
+            v["vel_rel_l2"] = float(np.linalg.norm(v["vel"] - ref["vel"]) / np.linalg.norm(ref["vel"]))
+        for name, v in res.items():
+            v["wss_patches"] = v.pop("wss").tolist()
+            del v["vel"]
+            log("seed %d %-10s nx %3d tau %.4f steps %4d: wss %.4g mean %.4g vel %.4g, %.0f MLUPS, %.0f fine-eq" % (
+                seed, name, v["nx"], v["tau"], v["steps"], v["wss_rel_l2"], v["wss_mean_rel"], v["vel_rel_l2"],
+                v["mlups"], v["fine_eq_mlups"]))
+        per_seed.append({"seed": seed, "runs": res})
+    # seed-averaged errors and rates, and the plain resolution matching each run's error
+    names = list(per_seed[0]["runs"])
+    avg = {}
+    for name in names:
+        rs = [p["runs"][name] for p in per_seed]
+        avg[name] = {k: (float(np.mean([x[k] for x in rs])) if isinstance(rs[0][k], float) else rs[0][k])
+                     for k in rs[0] if k != "wss_patches"}
+    plain = [avg["plain%d" % n] for n in sizes[:-1]]
+    xs = [p["nx"] for p in plain]
+    for name, v in avg.items():
+        if name.startswith("plain"):
+            continue
+        n_eq = _interp_log(xs, [p["wss_rel_l2"] for p in plain], v["wss_rel_l2"])
+        v["plain_nx_at_same_wss_error"] = n_eq
+        if n_eq is not None:
+            feq = _interp_log_value(xs, [p["fine_eq_mlups"] for p in plain], n_eq)
+            v["plain_fine_eq_mlups_at_same_wss_error"] = feq
+            v["speedup_at_same_wss_error"] = v["fine_eq_mlups"] / feq
+        log("%-10s wss %.4g -> plain nx %s; %s" % (name, v["wss_rel_l2"], n_eq,
+                                                   v.get("speedup_at_same_wss_error")))
+    return {"seeds": list(seeds), "sizes": sizes, "fine_steps": fine_steps, "per_seed": per_seed, "mean": avg}
+
+
+def _interp_log_value(xs, ys, x):
+    """Value at x of the piecewise log-log line through (xs, ys)."""
+    lx = np.log(xs)
+    return float(np.exp(np.interp(np.log(x), lx, np.log(ys))))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None)
@@ -245,6 +370,10 @@ def main(argv=None):
                     help="run the --alpha candidates on the validation seeds, keep the one with the lowest "
                          "wall-stress error, and evaluate only that one on the held-out seeds")
     ap.add_argument("--c-guard", type=float, default=1.0)
+    ap.add_argument("--ladder", action="store_true",
+                    help="with --weights and one --alpha: plain float32 at a ladder of resolutions, the learned "
+                         "closure and the 16-bit storage forms, compared at the same wall-stress error")
+    ap.add_argument("--ladder-sizes", type=int, nargs="*", default=[128, 160, 192, 224, 256])
     args = ap.parse_args(argv)
 
     import torch
@@ -261,6 +390,22 @@ def main(argv=None):
     train_seeds = list(range(args.train_seeds))
     val_seeds = list(range(100, 100 + args.val_seeds))
     eval_seeds = list(range(200, 200 + args.eval_seeds))
+    if args.ladder:
+        params = norm = None
+        if args.weights:
+            w = torch.load(args.weights, weights_only=True)
+            params, norm = w["params"].to("cuda:0"), w["norm"].to("cuda:0").clone()
+            norm[32:48] *= args.alpha[0]
+        sizes = args.ladder_sizes
+        if args.quick:
+            sizes = [kw["fine"][0] * k // 8 for k in (4, 6, 8)]
+        rep = ladder(params, norm, eval_seeds, sizes=sizes, c_guard=args.c_guard,
+                     fine_steps=2 * args.coarse_steps, log=log, **kw)
+        rep["alpha"] = args.alpha[0] if args.weights else None
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(rep, f, indent=1)
+        return rep
     if args.weights:
         w = torch.load(args.weights, weights_only=True)
         params, norm = w["params"].to("cuda:0"), w["norm"].to("cuda:0")

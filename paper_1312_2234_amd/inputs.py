@@ -275,6 +275,31 @@ def shear_platelets(seed=0, nx=256, ny=128, nz=128, count=16, nodes=2562, semi_a
     return Channel(nx, ny, nz, tau, u_wall_hi=(u_top, 0.0, 0.0), init="shear", bodies=b)
 
 
+def _suspension_centres(seed, count, fine, semi_axes, y_band):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = fine
+    a = np.asarray(semi_axes, float)
+    y_lo = -0.5 + y_band[0]
+    y_hi = min(-0.5 + y_band[1], ny - 0.5 - a[1] - 2.0)
+    return place_bodies(rng, nx, nz, count, float(a.max()) + 2.0, y_lo, y_hi)
+
+
+def _scaled_channel(cen, r, nodes, fine, tau_f, u_top, semi_axes, k_spring, k_bend):
+    """The suspension with fine-lattice centres `cen` on the lattice r times as fine (acoustic
+    scaling: dx and dt both grow by 1/r, lattice velocities are unchanged).  A fine point x_f
+    sits at x = (x_f + 1/2) r - 1/2, so the wall planes y = -1/2 and y = ny - 1/2 map onto each
+    other; semi-axes scale by r; tau = 1/2 + (tau_f - 1/2) r keeps the physical viscosity;
+    the membrane stiffness k dt^2/(rho dx^3) scales by r and the bending energy
+    k_b dt^2/(rho dx^5) by r^3."""
+    nx, ny, nz = (int(round(d * r)) for d in fine)
+    a = np.asarray(semi_axes, float) * r
+    V = _topology(nodes)[0]
+    X, E, H, O = _concat([(V * a[None, :] + (c * r + (r - 1.0) / 2)[None, :], nodes) for c in cen])
+    b = Bodies(X=X, X_rest=X.copy(), edges=E, hinges=H, anchors=None, k_spring=k_spring * r,
+               k_bend=k_bend * r ** 3, body_offsets=O)
+    return Channel(nx, ny, nz, 0.5 + (tau_f - 0.5) * r, u_wall_hi=(u_top, 0.0, 0.0), init="shear", bodies=b)
+
+
 def coarse_fine_pair(seed=0, u_top=0.05, count=16, fine=(256, 128, 128), tau_f=1.0, nodes_f=2562,
                      nodes_c=1282, semi_axes=(6.0, 2.0, 6.0), k_spring=0.005, k_bend=1e-4, y_band=(8.0, 20.0)):
     """The same platelet suspension on a fine lattice and on the 2x coarser one (acoustic
@@ -284,24 +309,27 @@ def coarse_fine_pair(seed=0, u_top=0.05, count=16, fine=(256, 128, 128), tau_f=1
     both).  Coarse platelets have half the semi-axes and `nodes_c` nodes; their spring and
     bending constants follow the same scaling (membrane stiffness k dt^2/(rho dx^3) halves,
     bending energy k_b dt^2/(rho dx^5) drops by 8).  Returns (fine Channel, coarse Channel)."""
-    rng = np.random.default_rng(seed)
-    nx, ny, nz = fine
-    a = np.asarray(semi_axes, float)
-    y_lo = -0.5 + y_band[0]
-    y_hi = min(-0.5 + y_band[1], ny - 0.5 - a[1] - 2.0)
-    cen = place_bodies(rng, nx, nz, count, float(a.max()) + 2.0, y_lo, y_hi)
-    Vf = _topology(nodes_f)[0]
-    Vc = _topology(nodes_c)[0]
-    Xf, Ef, Hf, Of = _concat([(Vf * a[None, :] + c[None, :], nodes_f) for c in cen])
-    Xc, Ec, Hc, Oc = _concat([(Vc * (a / 2)[None, :] + ((c - 0.5) / 2)[None, :], nodes_c) for c in cen])
-    bf = Bodies(X=Xf, X_rest=Xf.copy(), edges=Ef, hinges=Hf, anchors=None, k_spring=k_spring, k_bend=k_bend,
-                body_offsets=Of)
-    bc = Bodies(X=Xc, X_rest=Xc.copy(), edges=Ec, hinges=Hc, anchors=None, k_spring=k_spring / 2,
-                k_bend=k_bend / 8, body_offsets=Oc)
-    tau_c = 0.5 + (tau_f - 0.5) / 2
-    chf = Channel(nx, ny, nz, tau_f, u_wall_hi=(u_top, 0.0, 0.0), init="shear", bodies=bf)
-    chc = Channel(nx // 2, ny // 2, nz // 2, tau_c, u_wall_hi=(u_top, 0.0, 0.0), init="shear", bodies=bc)
-    return chf, chc
+    cen = _suspension_centres(seed, count, fine, semi_axes, y_band)
+    kw = dict(fine=fine, tau_f=tau_f, u_top=u_top, semi_axes=semi_axes, k_spring=k_spring, k_bend=k_bend)
+    return _scaled_channel(cen, 1.0, nodes_f, **kw), _scaled_channel(cen, 0.5, nodes_c, **kw)
+
+
+def resolution_ladder(seed=0, sizes=(128, 160, 192, 224, 256), u_top=0.05, count=16, fine=(256, 128, 128),
+                      tau_f=1.0, semi_axes=(6.0, 2.0, 6.0), k_spring=0.005, k_bend=1e-4, y_band=(8.0, 20.0)):
+    """The suspension of coarse_fine_pair(seed) at several resolutions (lattice length in x
+    from `sizes`; the other dimensions in proportion), all acoustically scaled from the fine
+    one: returns {nx: (Channel, r)} with r = nx / fine nx.  Platelets of r < 3/4 carry 1282
+    nodes, finer ones 2562 (node spacing below one lattice unit on every rung).  The rungs
+    nx = fine and nx = fine / 2 are exactly the two channels of coarse_fine_pair."""
+    cen = _suspension_centres(seed, count, fine, semi_axes, y_band)
+    kw = dict(fine=fine, tau_f=tau_f, u_top=u_top, semi_axes=semi_axes, k_spring=k_spring, k_bend=k_bend)
+    out = {}
+    for n in sizes:
+        r = n / fine[0]
+        if any(abs(d * r - round(d * r)) > 1e-9 for d in fine):
+            raise ValueError("rung %d does not scale the lattice %s to whole cells" % (n, fine))
+        out[n] = (_scaled_channel(cen, r, 2562 if r >= 0.75 else 1282, **kw), r)
+    return out
 
 
 BATCH_SIZES = [(48, 32, 32), (64, 48, 48), (96, 64, 64), (128, 64, 64)]

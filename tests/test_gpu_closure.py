@@ -389,3 +389,29 @@ def test_closure_in_coupled_step_with_platelet(orc, gpu):
               % (steps, e, spread_ref))
         assert e <= (bound if bound is not None else 3.0 * spread_ref)
         assert np.all(np.isfinite(Xg)) and np.abs(Xg - Xr).max() <= 1.0
+
+
+def test_fixed_error_ladder_small(gpu):
+    """The resolution ladder end to end on a small suspension (fine 64x48x32, two platelets):
+    the finest plain run is its own reference (zero error); a closure whose last layer is zero
+    reproduces the plain coarsest run exactly (bitwise equal steps, so equal wall stress and
+    velocities); 16-bit storage stays within its rounding of the float32 run; every run is
+    flag-free and timed."""
+    from paper_1312_2234_amd import closure
+
+    rng = np.random.default_rng(4)
+    th = theta_bf16(rng, zero_last=True)
+    flat = np.concatenate([np.zeros(16), np.ones(16), np.full(16, 1e-3)])
+    rep = closure.ladder(T(th), T(flat), [200], sizes=(32, 48, 64), storages=("f16",), fine_steps=160,
+                         fine_every=16, fine=(64, 48, 32), count=2, log=lambda m: print(m, flush=True))
+    runs = rep["per_seed"][0]["runs"]
+    assert set(runs) == {"plain32", "plain48", "plain64", "learned32", "f1664"}
+    assert runs["plain64"]["wss_rel_l2"] == 0.0 and runs["plain64"]["vel_rel_l2"] == 0.0
+    assert runs["learned32"]["wss_rel_l2"] == runs["plain32"]["wss_rel_l2"]
+    assert runs["learned32"]["vel_rel_l2"] == runs["plain32"]["vel_rel_l2"]
+    assert runs["f1664"]["wss_rel_l2"] < 1e-2
+    for name, v in runs.items():
+        assert v["flags"] == 0, name
+        assert v["mlups"] > 0 and np.isfinite(v["wss_rel_l2"]) and np.isfinite(v["vel_rel_l2"])
+    assert runs["plain32"]["steps"] == 80 and runs["plain48"]["steps"] == 120
+    assert abs(runs["plain48"]["fine_eq_mlups"] * 0.75 ** 4 - runs["plain48"]["mlups"]) < 1e-6 * runs["plain48"]["mlups"]

@@ -64,3 +64,50 @@ def test_poiseuille_sphere():
     r = np.linalg.norm(b.X_rest - np.array([[16], [10], [16]]), axis=0)
     assert np.allclose(r, 4.0)
     assert 0.08 < np.std(b.X - b.X_rest) < 0.12
+
+
+def test_resolution_ladder_acoustic_scaling():
+    """Each rung is the fine suspension under acoustic scaling: wall planes map onto each other,
+    platelet centroids sit at (x_f + 1/2) r - 1/2, semi-axes scale by r, the viscosity
+    (tau - 1/2) by r, spring stiffness by r and bending by r^3; the finest and half rungs are
+    the two channels of coarse_fine_pair."""
+    lad = inputs.resolution_ladder(seed=5, sizes=(128, 160, 192, 256))
+    fine, coarse = inputs.coarse_fine_pair(seed=5)
+    assert np.array_equal(lad[256][0].bodies.X, fine.bodies.X)
+    assert np.array_equal(lad[128][0].bodies.X, coarse.bodies.X)
+    bf = fine.bodies
+    cen_f = np.array([bf.X[:, a:b].mean(axis=1) for a, b in zip(bf.body_offsets[:-1], bf.body_offsets[1:])])
+    ext_f = np.array([np.ptp(bf.X[:, a:b], axis=1) for a, b in zip(bf.body_offsets[:-1], bf.body_offsets[1:])])
+    for n, (ch, r) in lad.items():
+        assert r == n / 256 and (ch.nx, ch.ny, ch.nz) == (n, n // 2, n // 2)
+        assert abs((ch.tau - 0.5) - 0.5 * r) < 1e-15
+        b = ch.bodies
+        assert abs(b.k_spring - 0.005 * r) < 1e-15 and abs(b.k_bend - 1e-4 * r ** 3) < 1e-18
+        cen = np.array([b.X[:, a:c].mean(axis=1) for a, c in zip(b.body_offsets[:-1], b.body_offsets[1:])])
+        ext = np.array([np.ptp(b.X[:, a:c], axis=1) for a, c in zip(b.body_offsets[:-1], b.body_offsets[1:])])
+        assert np.allclose(cen, (cen_f + 0.5) * r - 0.5, atol=2e-3)  # node means: the 1282-point set is not exactly centred
+        assert np.allclose(ext, ext_f * r, rtol=0.02)        # sphere point sets differ below 3/4
+        # wall planes: y = -1/2 and y = ny - 1/2 are the images of the fine planes
+        assert (-0.5 + 0.5) * r - 0.5 == -0.5 and (127.5 + 0.5) * r - 0.5 == ch.ny - 0.5
+        assert b.n == 16 * (2562 if r >= 0.75 else 1282)
+    try:
+        inputs.resolution_ladder(seed=5, sizes=(99,))
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("a rung that does not scale to whole cells must be rejected")
+
+
+def test_log_log_interpolation():
+    from paper_1312_2234_amd.closure import _interp_log, _interp_log_value, _patch_mean
+
+    xs, ys = [128, 160, 192], [0.02, 0.01, 0.004]
+    assert abs(_interp_log(xs, ys, 0.01) - 160) < 1e-9
+    # on a power law the log-log line is exact
+    x = 150.0
+    p = np.log(0.02 / 0.01) / np.log(160 / 128)
+    assert abs(_interp_log(xs, ys, 0.02 * (x / 128) ** -p) - x) < 1e-9
+    assert _interp_log(xs, ys, 0.03) is None and _interp_log(xs, ys, 0.001) is None
+    assert abs(_interp_log_value(xs, [1e5, 5e4, 2e4], 160) - 5e4) < 1e-6
+    w = np.arange(4 * 6, dtype=float).reshape(4, 6)
+    assert np.array_equal(_patch_mean(w, (2, 3)), np.array([[3.5, 5.5, 7.5], [15.5, 17.5, 19.5]]))
