@@ -80,25 +80,76 @@ constexpr Basis make_basis() {
 
 constexpr Basis kBasis = make_basis();
 
+// Opposite velocities come in 9 pairs (i, opp(i)), plus the rest velocity.  Gram-Schmidt
+// only mixes monomials of equal degree parity (a product of odd and even components sums
+// to zero over the velocity set), so every row of the basis is even (M[k][opp i] = M[k][i])
+// or odd (M[k][opp i] = -M[k][i]): an even moment needs only the pair sums, an odd one only
+// the differences, which halves both transforms.
+constexpr int kPairs = 9;
+constexpr int kPairLo[kPairs] = {0, 2, 4, 6, 7, 8, 9, 14, 15};
+
+constexpr int row_parity(int k) {  // 0 even, 1 odd, -1 neither
+    bool even = true, odd = true;
+    for (int i = 0; i < Q; ++i) {
+        even = even && kBasis.m[k][opp(i)] == kBasis.m[k][i];
+        odd = odd && kBasis.m[k][opp(i)] == -kBasis.m[k][i];
+    }
+    return even ? 0 : (odd ? 1 : -1);
+}
+constexpr bool pairs_ok() {
+    for (int p = 0; p < kPairs; ++p)
+        if (opp(kPairLo[p]) <= kPairLo[p]) return false;
+    for (int k = 0; k < MLP_NNC; ++k) {
+        if (row_parity(k) < 0) return false;
+        if (row_parity(k) == 1 && kBasis.m[k][Q - 1] != 0.0f) return false;
+    }
+    return opp(Q - 1) == Q - 1;
+}
+static_assert(pairs_ok(), "moment basis rows must have a definite parity");
+
 // m_k = sum_i M_nc[k][i] d_i; zero entries of the basis are skipped at compile time.
 __device__ __forceinline__ void to_moments(const float d[Q], float m[MLP_NNC]) {
+    float sp[kPairs], dp[kPairs];
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+        sp[p] = d[kPairLo[p]] + d[opp(kPairLo[p])];
+        dp[p] = d[kPairLo[p]] - d[opp(kPairLo[p])];
+    }
 #pragma unroll
     for (int k = 0; k < MLP_NNC; ++k) {
+        const bool odd = row_parity(k) == 1;
         float s = 0.0f;
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            if (kBasis.m[k][i] != 0.0f) s += kBasis.m[k][i] * d[i];
+        for (int p = 0; p < kPairs; ++p)
+            if (kBasis.m[k][kPairLo[p]] != 0.0f) s += kBasis.m[k][kPairLo[p]] * (odd ? dp[p] : sp[p]);
+        if (!odd && kBasis.m[k][Q - 1] != 0.0f) s += kBasis.m[k][Q - 1] * d[Q - 1];
         m[k] = s;
     }
 }
 
-// d_i = sum_k M_nc[k][i] m_k
-__device__ __forceinline__ float from_moments(const float m[MLP_NNC], int i) {
-    float s = 0.0f;
+// d_i = sum_k M_nc[k][i] m_k for every i: per pair, the even rows' sum E and the odd rows'
+// sum O give d_i = E + O and d_opp(i) = E - O.
+__device__ __forceinline__ void from_moments(const float m[MLP_NNC], float d[Q]) {
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+        const int i = kPairLo[p];
+        float e = 0.0f, o = 0.0f;
+#pragma unroll
+        for (int k = 0; k < MLP_NNC; ++k)
+            if (kBasis.m[k][i] != 0.0f) {
+                if (row_parity(k) == 1)
+                    o += kBasis.m[k][i] * m[k];
+                else
+                    e += kBasis.m[k][i] * m[k];
+            }
+        d[i] = e + o;
+        d[opp(i)] = e - o;
+    }
+    float r = 0.0f;
 #pragma unroll
     for (int k = 0; k < MLP_NNC; ++k)
-        if (kBasis.m[k][i] != 0.0f) s += kBasis.m[k][i] * m[k];
-    return s;
+        if (kBasis.m[k][Q - 1] != 0.0f) r += kBasis.m[k][Q - 1] * m[k];
+    d[Q - 1] = r;
 }
 
 __device__ __forceinline__ short bf16_bits(float f) {
@@ -106,15 +157,26 @@ __device__ __forceinline__ short bf16_bits(float f) {
     return __builtin_bit_cast(short, b);
 }
 
+// Two and four values at once: one packed conversion per pair (the same rounding as
+// bf16_bits, without the repacking of single conversions).
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned bf16_pair(float a, float b) {
+    const f2v v = {a, b};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+}
+__device__ __forceinline__ bf4 bf16_quad(acc4 a) {
+    const u2v p = {bf16_pair(a[0], a[1]), bf16_pair(a[2], a[3])};
+    return __builtin_bit_cast(bf4, p);
+}
+
 // relu, then bfloat16: round first, then clamp the bit patterns as int16 (a negative
 // bfloat16 is a negative int16, -0 included), one packed max per two values; the same
 // result as rounding relu(a) for every finite a
 __device__ __forceinline__ bf4 relu_bf16(acc4 a) {
-    bf4 r;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) r[k] = bf16_bits(a[k]);
     const bf4 z = {0, 0, 0, 0};
-    return __builtin_elementwise_max(r, z);
+    return __builtin_elementwise_max(bf16_quad(a), z);
 }
 
 __device__ __forceinline__ acc4 mfma(bf4 a, bf4 b, acc4 c) {
@@ -214,15 +276,15 @@ struct WaveStage {
 // out[16] per lane.  Every lane of the wavefront must call it (matrix cores use all 64).
 __device__ __forceinline__ void mlp_wave(const FwdW& W, WaveStage& S, const float in[16], float out[16]) {
     const int lane = threadIdx.x & 63, q = lane >> 4, p = lane & 15;
-    typedef short s8 __attribute__((ext_vector_type(8)));
-    s8 lo, hi;
+    typedef unsigned u4v __attribute__((ext_vector_type(4)));
+    u4v lo, hi;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        lo[k] = bf16_bits(in[k]);
-        hi[k] = bf16_bits(in[8 + k]);
+    for (int k = 0; k < 4; ++k) {
+        lo[k] = bf16_pair(in[2 * k], in[2 * k + 1]);
+        hi[k] = bf16_pair(in[8 + 2 * k], in[8 + 2 * k + 1]);
     }
-    *(s8*)&S.x[lane * 16] = lo;
-    *(s8*)&S.x[lane * 16 + 8] = hi;
+    *(u4v*)&S.x[lane * 16] = lo;
+    *(u4v*)&S.x[lane * 16 + 8] = hi;
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -310,10 +372,12 @@ __global__ void __launch_bounds__(256, 3) k_step_cl(LatArgs a, const MlpPacked* 
             const bool ok = dd <= cg * cg * mm;
             T* dst = (T*)a.dst + ch.pop_off;
             const float om = ch.omega, guo = ch.guo;
+            float df[Q];
+            from_moments(dm, df);
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 float gn = bgk_c(i, g[i], cs, om, guo);  // the plain step's value
-                if (ok) gn += from_moments(dm, i);
+                if (ok) gn += df[i];
                 if (NT)
                     St::st_nt(dst + pidx(i, n), gn);
                 else
@@ -429,9 +493,7 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const MlpPacked* __restrict__ P
                 dy[r] = gscale * e;
             }
             gb3 += dy;
-            bf4 dyb;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) dyb[r] = bf16_bits(dy[r]);
+            const bf4 dyb = bf16_quad(dy);
             put_T(L.dyT, 4 * q, cell, dyb);
             // d / d a2 = (W3 dy) * [a2 > 0]
             bf4 d2[4];
@@ -441,8 +503,7 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const MlpPacked* __restrict__ P
 #pragma unroll
                 for (int r = 0; r < 4; ++r) a[r] = h2[o][r] > 0 ? a[r] : 0.0f;  // bf16 > 0 as int16 > 0
                 gb2[o] += a;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) d2[o][r] = bf16_bits(a[r]);
+                d2[o] = bf16_quad(a);
                 put_T(L.d2T, 16 * o + 4 * q, cell, d2[o]);
             }
             // d / d a1 = (W2 d2) * [a1 > 0]
@@ -454,9 +515,7 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const MlpPacked* __restrict__ P
 #pragma unroll
                 for (int r = 0; r < 4; ++r) a[r] = h1[o1][r] > 0 ? a[r] : 0.0f;
                 gb1[o1] += a;
-                bf4 d1;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) d1[r] = bf16_bits(a[r]);
+                const bf4 d1 = bf16_quad(a);
                 put_T(L.d1T, 16 * o1 + 4 * q, cell, d1);
             }
         }

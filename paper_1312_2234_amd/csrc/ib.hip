@@ -415,7 +415,10 @@ __global__ void __launch_bounds__(SP_THREADS) k_ib_spread(IbArgs a) {
         if (end > a.list_cap) end = a.list_cap;
         for (int k = tid; k < 3 * TILE_CELLS; k += SP_THREADS) acc[k] = 0ull;
         const int T = a.set.flag_list[slot];
+        // the channel's fields in registers: read through the descriptor, the node loop below
+        // would load them again from memory after every LDS atomic
         const Chan& ch = a.chan[a.set.flag_ch[slot]];
+        const int cnx = ch.nx, cny = ch.ny, cnz = ch.nz;
         const int t = (int)(T - ch.tile_off);
         const int tx0 = (t % ch.tnx) * TILE;
         const int ty0 = ((t / ch.tnx) % ch.tny) * TILE;
@@ -438,13 +441,13 @@ __global__ void __launch_bounds__(SP_THREADS) k_ib_spread(IbArgs a) {
             for (int q = wave; q < nb; q += SP_THREADS / 64) {
                 const int4 bq = base[q];
                 int cx = bq.x + ix, cy = bq.y + iy, cz = bq.z + iz;
-                if (cx >= ch.nx) cx -= ch.nx;
-                if (cz >= ch.nz) cz -= ch.nz;
+                if (cx >= cnx) cx -= cnx;
+                if (cz >= cnz) cz -= cnz;
                 bool ok = true;
                 if (wrap_y) {
-                    if (cy >= ch.ny) cy -= ch.ny;
+                    if (cy >= cny) cy -= cny;
                 } else {
-                    ok = cy >= 0 && cy < ch.ny;
+                    ok = cy >= 0 && cy < cny;
                 }
                 const int lx = cx - tx0, ly = cy - ty0, lz = cz - tz0;
                 if (ok && (unsigned)lx < (unsigned)TILE && (unsigned)ly < (unsigned)TILE && (unsigned)lz < (unsigned)TILE) {
