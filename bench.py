@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--workload", default="shear")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--kernel", default="cos", choices=["cos", "peskin4"])
-    ap.add_argument("--cpu-steps", type=int, default=48)
+    ap.add_argument("--cpu-steps", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lbm-only-steps", type=int, default=200)
     ap.add_argument("--tune", action="store_true", help="re-time the lattice kernel's launch shapes")

@@ -175,6 +175,45 @@ def test_spread_is_deterministic_and_empty_ok(gpu):
     assert float(N(v).__abs__().max()) == 0.0
 
 
+def tile_pairs(X, dims, walls):
+    """Node-tile pairs of the 8^3 tiles the 4^3 stencils touch (rows inside a wall dropped)."""
+    tot = np.ones(X.shape[1], np.int64)
+    for d, n in enumerate(dims):
+        cells = np.floor(X[d]).astype(np.int64)[:, None] - 1 + np.arange(4)[None, :]
+        if d == 1 and walls:
+            cells = np.where((cells >= 0) & (cells < n), cells, -1)
+            t = np.where(cells >= 0, cells // 8, -1)
+            first = np.max(np.where(t >= 0, t, -1), axis=1)
+            lo = np.min(np.where(t >= 0, t, 1 << 30), axis=1)
+            tot *= np.where(first < 0, 0, first - lo + 1)
+        else:
+            t = (cells % n) // 8
+            tot *= 1 + (t[:, 3] != t[:, 0])
+    return int(tot.sum())
+
+
+def test_spread_partial_capacity_exhausted(orc, gpu):
+    """More 256-entry chunks than partial force blocks (16384): the tiles beyond the capacity are
+    spread by a single work item over their whole list.  Both kinds must agree with the oracle."""
+    rng = np.random.default_rng(15)
+    dims = (64, 48, 64)
+    ch = inputs.Channel(*dims, 0.8)
+    n = 2_000_000
+    X = np.stack([rng.uniform(0, 64, n), rng.uniform(-0.5, 47.5, n), rng.uniform(0, 64, n)])
+    pairs = tile_pairs(X, dims, True)
+    assert pairs / 256 > 1.1 * 16384, pairs      # the capacity is exceeded
+    F32 = (1e-3 * rng.standard_normal((3, n))).astype(np.float32)
+    o, g = pair(orc, gpu, ch, max_nodes=n)
+    o.spread(X, F32.astype(np.float64))
+    g.set_nodes(n)
+    g.spread(T(X), T(F32))
+    _, v_g = gpu_fields(g)
+    e = emax(2 * v_g, o.g)
+    print("%d nodes, %d node-tile pairs: e_max %.3e" % (n, pairs, e))
+    assert e <= 2e-6
+    assert g.error_flags() == 0
+
+
 def test_error_flags(gpu):
     ch = inputs.Channel(16, 16, 16, 0.8)
     g = gpu.Lattice([ch], max_nodes=2, device=DEV)
