@@ -713,17 +713,20 @@ __device__ void hinge(const double x[4][3], double grad[4][3], bool want_grad, d
     sub(x[2], x[1], e);
     const double AA = dt3(nA, nA), BB = dt3(nB, nB), L = sqrt(dt3(e, e));
     const double iab = 1.0 / sqrt(AA * BB);
+    // one reciprocal each instead of a division per use (FP64 division is a long sequence)
+    const double iL = 1.0 / L;
     crs(nA, nB, cr);
     cth = dt3(nA, nB) * iab;
-    sth = dt3(cr, e) * iab / L;
+    sth = dt3(cr, e) * iab * iL;
     if (want_grad) {
         double t0[3], t3[3];
         sub(x[0], x[2], t0); sub(x[3], x[2], t3);
-        const double c1A = -dt3(t0, e) / L, c1B = -dt3(t3, e) / L;
+        const double c1A = -dt3(t0, e) * iL, c1B = -dt3(t3, e) * iL;
         sub(x[0], x[1], t0); sub(x[3], x[1], t3);
-        const double c2A = dt3(t0, e) / L, c2B = dt3(t3, e) / L;
+        const double c2A = dt3(t0, e) * iL, c2B = dt3(t3, e) * iL;
+        const double iA = 1.0 / AA, iB = 1.0 / BB;
         for (int d = 0; d < 3; ++d) {
-            const double qA = nA[d] / AA, qB = nB[d] / BB;
+            const double qA = nA[d] * iA, qB = nB[d] * iB;
             grad[0][d] = -L * qA;
             grad[3][d] = -L * qB;
             grad[1][d] = c1A * qA + c1B * qB;
