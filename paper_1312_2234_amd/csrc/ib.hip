@@ -344,8 +344,9 @@ __global__ void __launch_bounds__(1024) k_ib_scan(IbArgs a) {
             int L = 1;
             while ((1ll << L) < a.n) ++L;
             // one contribution |w_x w_y w_z F| <= max|F|/8 < 2^(e-3) stays below 2^31 after
-            // scaling (so it converts exactly through int32), and a sum of <= n of them stays
-            // below 2^62; the quantum is 2^-34 max|F| or finer
+            // scaling, hence below 2^23 at the spread's per-batch scale 2^(s-8) (so it converts
+            // exactly through int32), and a sum of <= n of them stays below 2^62; the quantum
+            // of a contribution is 2^-26 max|F| or finer
             s = 34 - e;
             if (s > 65 - e - L) s = 65 - e - L;
         }
@@ -383,20 +384,28 @@ __global__ void __launch_bounds__(256) k_ib_scatter(IbArgs a) {
 constexpr int SP_THREADS = 512;   // 8 wavefronts per work item (four work items per CU)
 constexpr int SP_BATCH = 256;     // node records staged at a time (>= SP_CHUNK)
 
-__device__ __forceinline__ unsigned long long fixed_round(float c, float scale) {
+__device__ __forceinline__ unsigned fixed_round(float c, float scale) {
     // round-to-nearest-even of c * scale (a power of two: the product is exact) for
-    // |c * scale| < 2^31, sign-extended to 64 bits
-    return (unsigned long long)(long long)(int)__builtin_rintf(c * scale);
+    // |c * scale| < 2^23, as a two's-complement 32-bit word
+    return (unsigned)(int)__builtin_rintf(c * scale);
 }
+
+// Contributions are summed per staged batch in 32-bit LDS words (cheaper atomics than 64-bit
+// ones), at 2^-8 of the tile accumulator's scale: each is below 2^23 there and a batch adds
+// at most SP_BATCH of them to a cell, so a batch sum stays below 2^31 and is exact.  After
+// each batch the words are added, scaled by 2^8, to the tile's 64-bit accumulator.
+constexpr int SP_BATCH_SHIFT = 8;
+static_assert(SP_BATCH <= (1 << SP_BATCH_SHIFT), "a batch sum must stay below 2^31");
 
 __global__ void __launch_bounds__(SP_THREADS) k_ib_spread(IbArgs a) {
     __shared__ unsigned long long acc[3 * TILE_CELLS];
+    __shared__ unsigned acc32[3 * TILE_CELLS];
     __shared__ int4 base[SP_BATCH];         // stencil base x, y, z of each staged node
     __shared__ float4 wrec[SP_BATCH][4];    // w_x[4], w_y[4], w_z[4], (F, pad)
     const int nwork = a.set.hdr->nchunk;
     const int sexp = a.set.hdr->scale_exp;
     const bool nonfinite = a.set.hdr->nonfinite != 0;
-    const float scale = ldexpf(1.0f, sexp);
+    const float scale = ldexpf(1.0f, sexp - SP_BATCH_SHIFT);
     const double inv = ldexp(1.0, -sexp);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ix = lane & 3, iy = (lane >> 2) & 3, iz = lane >> 4;
@@ -413,7 +422,10 @@ __global__ void __launch_bounds__(SP_THREADS) k_ib_spread(IbArgs a) {
             if (end > beg + SP_CHUNK) end = beg + SP_CHUNK;
         }
         if (end > a.list_cap) end = a.list_cap;
-        for (int k = tid; k < 3 * TILE_CELLS; k += SP_THREADS) acc[k] = 0ull;
+        for (int k = tid; k < 3 * TILE_CELLS; k += SP_THREADS) {
+            acc[k] = 0ull;
+            acc32[k] = 0u;
+        }
         const int T = a.set.flag_list[slot];
         // the channel's fields in registers: read through the descriptor, the node loop below
         // would load them again from memory after every LDS atomic
@@ -454,10 +466,15 @@ __global__ void __launch_bounds__(SP_THREADS) k_ib_spread(IbArgs a) {
                     const float* w = (const float*)wrec[q];
                     const float ww = w[ix] * (w[4 + iy] * w[8 + iz]);
                     const int loc = (lz << 6) | (ly << 3) | lx;
-                    atomicAdd(&acc[loc], fixed_round(ww * w[12], scale));
-                    atomicAdd(&acc[TILE_CELLS + loc], fixed_round(ww * w[13], scale));
-                    atomicAdd(&acc[2 * TILE_CELLS + loc], fixed_round(ww * w[14], scale));
+                    atomicAdd(&acc32[loc], fixed_round(ww * w[12], scale));
+                    atomicAdd(&acc32[TILE_CELLS + loc], fixed_round(ww * w[13], scale));
+                    atomicAdd(&acc32[2 * TILE_CELLS + loc], fixed_round(ww * w[14], scale));
                 }
+            }
+            __syncthreads();
+            for (int k = tid; k < 3 * TILE_CELLS; k += SP_THREADS) {
+                acc[k] += (unsigned long long)((long long)(int)acc32[k] * (1ll << SP_BATCH_SHIFT));
+                acc32[k] = 0u;
             }
         }
         __syncthreads();
