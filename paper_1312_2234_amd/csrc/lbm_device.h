@@ -98,13 +98,10 @@ struct StBF16 {
     using T = uint16_t;
     static __device__ __forceinline__ float dec(T v) { return __uint_as_float((uint32_t)v << 16); }
     static __device__ __forceinline__ float ld(const T* p) { return dec(*p); }
-    // round to nearest, ties to even; NaN stays a quiet NaN
-    static __device__ __forceinline__ uint16_t enc(float v) {
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return (uint16_t)(u >> 16);
-    }
+    // round to nearest, ties to even, NaN stays NaN: the hardware conversion (one
+    // v_cvt_pk_bf16_f32), equal on every float32 input to the integer rounding
+    // u + 0x7fff + (u >> 16 & 1) taken >> 16
+    static __device__ __forceinline__ uint16_t enc(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
     static __device__ __forceinline__ void st(T* p, float v) { *p = enc(v); }
     static __device__ __forceinline__ void st_nt(T* p, float v) { __builtin_nontemporal_store(enc(v), p); }
 };

@@ -426,6 +426,53 @@ def test_launch_shapes_agree(gpu, launch, dims):
 
 
 # ----------------------------------------------------------------------------- 16-bit storage
+def bf16_rne32(x):
+    """float32 -> nearest bfloat16 (ties to even), as float32: the integer rounding rule."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_half_storage_rounding_is_nearest_even(gpu, storage):
+    """The stored 16-bit value of a population is g = f - w_i rounded to nearest, ties to
+    even (float32 arithmetic, then one conversion).  Exact ties, their neighbours and random
+    values go in through lbm_set_populations (periodic box: the state round-trips through
+    streaming exactly) and must come back as w_i + round(f - w_i), bit for bit."""
+    rng = np.random.default_rng(21)
+    ch = inputs.Channel(16, 8, 8, 0.8, walls=False)
+    w = np.array([1 / 18] * 6 + [1 / 36] * 12 + [1 / 3], np.float32)
+    n = ch.cells
+    mag = rng.uniform(1e-4, 1e-2, (19, n)) * rng.choice([-1.0, 1.0], (19, n))
+    g = mag.astype(np.float32)
+    u = g.view(np.uint32).copy()
+    if storage == "bf16":
+        half = n // 3   # exact ties of bfloat16, and one float32 step either side
+        u[:, :half] = (u[:, :half] & 0xFFFF0000) | 0x8000
+        u[:, half:2 * half] = (u[:, half:2 * half] & 0xFFFF0000) | 0x8000
+        u[:, half:2 * half] += rng.choice([-1, 1], (19, half)).astype(np.uint32)
+    else:
+        half = n // 3   # exact ties of float16 (13 dropped bits: tie at bit 12)
+        u[:, :half] = (u[:, :half] & 0xFFFFE000) | 0x1000
+        u[:, half:2 * half] = (u[:, half:2 * half] & 0xFFFFE000) | 0x1000
+        u[:, half:2 * half] += rng.choice([-1, 1], (19, half)).astype(np.uint32)
+    g = u.view(np.float32)
+    f = (w[:, None] + g).astype(np.float32)
+    gg = (f - w[:, None]).astype(np.float32)            # what the device rounds
+    if storage == "bf16":
+        stored = bf16_rne32(gg)
+    else:
+        stored = gg.astype(np.float16).astype(np.float32)
+    expect = (w[:, None] + stored).astype(np.float32)
+    lat = gpu.Lattice([ch], storage=storage, device=DEV)
+    lat.set_populations(T(f.reshape(-1)))
+    got = lat.populations().cpu().numpy().reshape(19, n)
+    assert np.array_equal(got.view(np.uint32), expect.view(np.uint32))
+    # the ties really were ties: some of them rounded down, some up
+    tie = gg[:, :half]
+    assert np.any(stored[:, :half] > tie) and np.any(stored[:, :half] < tie)
+
+
 @pytest.mark.parametrize("storage,bound", [("f16", 2e-3), ("bf16", 2e-2)])
 def test_half_storage_error_bounded(orc, gpu, storage, bound):
     """Weight-shifted 16-bit storage, float32 arithmetic: error against the FP64 oracle on a
