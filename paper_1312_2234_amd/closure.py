@@ -352,6 +352,24 @@ def _interp_log_value(xs, ys, x):
     return float(np.exp(np.interp(np.log(x), lx, np.log(ys))))
 
 
+def train_throughput(steps, snapshots=8, cells=524288, batch=65536, dev="cuda:0"):
+    """Training rate on seeded synthetic data of the production shape (no fine runs): features
+    ~ N(0, 1e-4^2), targets ~ N(0, 1e-6^2), `snapshots` x `cells` samples, one validation
+    batch.  Prints one JSON line."""
+    import torch
+
+    g = torch.Generator(device=dev).manual_seed(0)
+    feat = torch.randn(snapshots, cells, 16, device=dev, generator=g) * 1e-4
+    tgt = torch.randn(snapshots, cells, 16, device=dev, generator=g) * 1e-6
+    vf, vt = feat[:1, :batch].clone(), tgt[:1, :batch].clone()
+    torch.cuda.synchronize()
+    _, _, _, secs = train(feat, tgt, vf, vt, steps=steps, batch=batch, log_every=10 ** 9, log=lambda m: None)
+    rep = {"adam_steps": steps, "batch": batch, "seconds": round(secs, 4),
+           "samples_per_s": round(steps * batch / secs, 1), "us_per_step": round(secs / steps * 1e6, 2)}
+    print(json.dumps(rep), flush=True)
+    return rep
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None)
@@ -374,6 +392,9 @@ def main(argv=None):
                     help="with --weights and one --alpha: plain float32 at a ladder of resolutions, the learned "
                          "closure and the 16-bit storage forms, compared at the same wall-stress error")
     ap.add_argument("--ladder-sizes", type=int, nargs="*", default=[128, 160, 192, 224, 256])
+    ap.add_argument("--train-throughput", type=int, default=0, metavar="STEPS",
+                    help="time STEPS Adam steps on seeded synthetic data (8 snapshots of 524,288 cells) and "
+                         "print the training rate")
     args = ap.parse_args(argv)
 
     import torch
@@ -381,6 +402,8 @@ def main(argv=None):
     def log(msg):
         print(msg, flush=True)
 
+    if args.train_throughput:
+        return train_throughput(args.train_throughput)
     kw = {}
     if args.quick:
         kw = dict(fine=(64, 48, 32), count=2)

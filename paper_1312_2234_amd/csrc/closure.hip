@@ -598,17 +598,40 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const MlpPacked* __restrict__ P
     }
 }
 
-// Sum the per-workgroup partials in workgroup order (double accumulation).
-__global__ void k_grad_reduce(const float* __restrict__ partial, int nblk, float* __restrict__ grad,
-                              float* __restrict__ loss) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j > MLP_PARAMS) return;
+// Sum the per-workgroup partials in a fixed order (double accumulation): slice k of
+// RD_SLICES holds consecutive workgroups, summed in workgroup order by one thread, and the
+// slices are then added in slice order, so the result does not depend on scheduling.  A
+// workgroup covers RD_P parameters (coalesced rows) with all slices in parallel.
+constexpr int RD_P = 64, RD_SLICES = 16;
+__global__ void __launch_bounds__(RD_P * RD_SLICES) k_grad_reduce(const float* __restrict__ partial, int nblk,
+                                                               float* __restrict__ grad, float* __restrict__ loss) {
+    __shared__ double part[RD_SLICES][RD_P];
+    const int p = threadIdx.x % RD_P, sl = threadIdx.x / RD_P;
+    const int j = blockIdx.x * RD_P + p;
+    const int per = (nblk + RD_SLICES - 1) / RD_SLICES;
+    const int b0 = sl * per, b1 = b0 + per < nblk ? b0 + per : nblk;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * (MLP_PARAMS + 1) + j];
-    if (j < MLP_PARAMS)
-        grad[j] = (float)s;
-    else if (loss)
-        *loss = (float)s;
+    if (j <= MLP_PARAMS) {
+        int b = b0;
+        for (; b + 8 <= b1; b += 8) {
+            float t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = partial[(int64_t)(b + u) * (MLP_PARAMS + 1) + j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += t[u];
+        }
+        for (; b < b1; ++b) s += partial[(int64_t)b * (MLP_PARAMS + 1) + j];
+    }
+    part[sl][p] = s;
+    __syncthreads();
+    if (sl == 0 && j <= MLP_PARAMS) {
+        double tot = 0.0;
+        for (int k = 0; k < RD_SLICES; ++k) tot += part[k][p];
+        if (j < MLP_PARAMS)
+            grad[j] = (float)tot;
+        else if (loss)
+            *loss = (float)tot;
+    }
 }
 
 // Adam (Kingma & Ba 2015) with bias correction; step counts from 1.
@@ -807,7 +830,8 @@ hipError_t launch_mlp_grad(hipStream_t s, const MlpPacked* P, const float* raw, 
     k_mlp_grad<<<dim3((unsigned)nblk), dim3(64), 0, s>>>(P, raw, tgt, B, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_grad_reduce<<<dim3((MLP_PARAMS + 1 + 255) / 256), dim3(256), 0, s>>>(partial, (int)nblk, grad, loss);
+    k_grad_reduce<<<dim3((MLP_PARAMS + 1 + RD_P - 1) / RD_P), dim3(RD_P * RD_SLICES), 0, s>>>(partial, (int)nblk, grad,
+                                                                                          loss);
     return hipGetLastError();
 }
 
