@@ -101,7 +101,7 @@ def closure_weights(torch, dev):
     return (torch.from_numpy(th.astype(np.float32)).to(dev), torch.from_numpy(norm.astype(np.float32)).to(dev))
 
 
-def cpu_baseline(channels, kernel, steps):
+def cpu_baseline(channels, kernel, steps, single_steps=4):
     """The FP64 oracle (as it stands) on `steps` coupled steps of the first channel."""
     import numpy as np
 
@@ -116,14 +116,35 @@ def cpu_baseline(channels, kernel, steps):
                           anchors=b.anchors, k_tether=b.k_tether)
     X = b.X.copy()
     oracle.coupled_step(o, mem, X)  # first touch of the arrays, not timed
+    cores = oracle.threads()
     t0 = time.perf_counter()
     for _ in range(steps):
         oracle.coupled_step(o, mem, X)
     dt = time.perf_counter() - t0
-    return {"value": round(ch.cells * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": "%d coupled steps (forces, spread, LBM, interpolation, move) of the full %dx%dx%d "
-                      "workload, FP64, %.1f s" % (steps, ch.nx, ch.ny, ch.nz, dt)}
+    out = {"value": round(ch.cells * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": "%d coupled steps (forces, spread, LBM, interpolation, move) of the full %dx%dx%d "
+                     "workload, FP64, %.1f s" % (steps, ch.nx, ch.ny, ch.nz, dt),
+           "host": {"cpu": cpu_model(), "nproc": os.cpu_count()}}
+    if single_steps > 0:
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        for _ in range(single_steps):
+            oracle.coupled_step(o, mem, X)
+        d1 = time.perf_counter() - t0
+        oracle.set_threads(cores)
+        out["single_core"] = {"value": round(ch.cells * single_steps / d1 / 1e6, 4), "unit": "MLUPS", "cores": 1,
+                              "sample": "%d coupled steps, %.1f s" % (single_steps, d1)}
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
@@ -135,6 +156,7 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--kernel", default="cos", choices=["cos", "peskin4"])
     ap.add_argument("--cpu-steps", type=int, default=64)
+    ap.add_argument("--cpu-single-steps", type=int, default=4, help="steps of the one-thread oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lbm-only-steps", type=int, default=200)
     ap.add_argument("--tune", action="store_true", help="re-time the lattice kernel's launch shapes")
@@ -255,7 +277,7 @@ def main():
         del src, dst
     if not args.no_cpu_baseline and args.cpu_steps > 0 and len(channels) == 1:
         del lat
-        out["cpu_baseline"] = cpu_baseline(channels, args.kernel, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(channels, args.kernel, args.cpu_steps, args.cpu_single_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -93,6 +93,15 @@ int32_t orc_threads(void) {
 #endif
 }
 
+/* set the threads later OpenMP regions use (for timing only; results do not depend on it) */
+void orc_set_threads(int32_t n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* accessors so that tests can check the tables against the paper */
 void orc_tables(int32_t* c, double* w, int32_t* opp) {
     for (int i = 0; i < Q; ++i) {

@@ -53,6 +53,7 @@ def lib():
         L.orc_phi.restype = C.c_double
         L.orc_tables.argtypes = [ip, dp, ip]
         L.orc_threads.restype = C.c_int32
+        L.orc_set_threads.argtypes = [C.c_int32]
         L.orc_init.argtypes = [pp, dp, dp, dp]
         L.orc_moments.argtypes = [pp, dp, dp, dp, dp]
         L.orc_step.argtypes = [pp, dp, dp, dp]
@@ -96,6 +97,11 @@ def _f64(a):
 def threads():
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().orc_threads())
+
+
+def set_threads(n):
+    """Threads for later parallel loops (timing only)."""
+    lib().orc_set_threads(int(n))
 
 
 def tables():
