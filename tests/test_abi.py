@@ -80,3 +80,17 @@ def test_oracle_builds_and_is_separate():
     csrc = os.path.join(ROOT, "paper_1312_2234_amd", "csrc")
     for f in os.listdir(csrc):
         assert "oracle" not in open(os.path.join(csrc, f)).read()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asked for more it says so and exits non-zero, before
+    touching a device."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
