@@ -81,7 +81,7 @@ Layout layout_of(const lbm_params* p, int32_t nch, lbm_storage st, int64_t max_n
         L.rec = take(sizeof(float) * 20 * max_nodes);
         L.rank = take(sizeof(int32_t) * 27 * max_nodes);
         L.blkbase = take(sizeof(int32_t) * HS * ((max_nodes + 255) / 256));
-        L.blkmax = take(sizeof(uint32_t) * ((max_nodes + 255) / 256));
+        L.blkmax = take(sizeof(uint32_t) * ((8 * max_nodes + 255) / 256));  // bin blocks or force workgroups
         L.nbase = take(sizeof(int4) * max_nodes);
         for (int k = 0; k < 2; ++k) {
             L.sets[k][0] = take(sizeof(int32_t) * sz.tiles);           // cnt
@@ -155,6 +155,7 @@ IbArgs ib_args(lbm_ctx* c, int set) {
     a.part_cap = c->part_cap;
     a.item_slot = c->d_item_slot;
     a.blkmax = c->d_blkmax;
+    a.blkmax_n = (c->n_nodes + 255) / 256;
     a.max_items = c->max_items;
     return a;
 }
@@ -527,15 +528,18 @@ static lbm_status coupled(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, doub
     const bool ov = c->launch.overlap && c->side && !c->closure && nsteps > 0;
     if (ov && far_update(c) != hipSuccess) return LBM_ERR_HIP;
     for (int s = 0; s < nsteps; ++s) {
-        if (m) {
-            hipError_t e = launch_membrane_forces(m, X, F, c->stream);
-            if (e != hipSuccess) return LBM_ERR_HIP;
-        }
         c->ibset ^= 1;
         IbArgs a = ib_args(c, c->ibset);
         a.X = X;
         a.F = F;
-        if (launch_ib_spread(c, a) != hipSuccess) return LBM_ERR_HIP;
+        if (m) {
+            // the binning needs only X: it runs beside the hinge forces, and the force kernel
+            // after them fills in what it needs of F
+            if (launch_forces_and_bin(c, m, X, F, a) != hipSuccess) return LBM_ERR_HIP;
+            if (launch_ib_spread_binned(c, a) != hipSuccess) return LBM_ERR_HIP;
+        } else if (launch_ib_spread(c, a) != hipSuccess) {
+            return LBM_ERR_HIP;
+        }
         LatArgs la = lat_args(c);
         hipError_t e;
         if (ov) {

@@ -137,7 +137,10 @@ __device__ __forceinline__ void for_tiles(const Chan& ch, int bx, int by, int bz
                 f(q++, ch.tile_off + tx[i] + (int64_t)ch.tnx * (ty[j] + (int64_t)ch.tny * tz[k]));
 }
 
-__global__ void __launch_bounds__(256) k_ib_bin(IbArgs a) {
+// One block of the binning (256 nodes; `blk` is its index among the bin blocks).  With
+// `with_f` it also copies F into the node records and reduces max |F| for the scan; without,
+// the membrane-force kernel that runs after it does both (the coupled step).
+__device__ __forceinline__ void bin_block(const IbArgs& a, int64_t blk, bool with_f) {
     __shared__ int hkey[HS];
     __shared__ int hcnt[HS];
     __shared__ float wmax[4];
@@ -146,7 +149,7 @@ __global__ void __launch_bounds__(256) k_ib_bin(IbArgs a) {
         hcnt[e] = 0;
     }
     __syncthreads();
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t m = blk * blockDim.x + threadIdx.x;
     float fm = 0.0f;
     if (m < a.n) {
         const int c = a.node_ch[m];
@@ -184,12 +187,13 @@ __global__ void __launch_bounds__(256) k_ib_bin(IbArgs a) {
             r[8 + k] = w[1][k];
             r[12 + k] = w[2][k];
         }
-        for (int d = 0; d < 3; ++d) {
-            const float F = a.F[d * a.n + m];
-            r[16 + d] = F;
-            fm = fmaxf(fm, fabsf(F));
-            if (!isfinite(F)) fm = __uint_as_float(0x7f800000u);
-        }
+        if (with_f)
+            for (int d = 0; d < 3; ++d) {
+                const float F = a.F[d * a.n + m];
+                r[16 + d] = F;
+                fm = fmaxf(fm, fabsf(F));
+                if (!isfinite(F)) fm = __uint_as_float(0x7f800000u);
+            }
         int32_t* rk = a.rank + m * MAXT;
         for_tiles(ch, b[0], b[1], b[2], [&](int q, int64_t T) {
             int h = (int)(((uint32_t)T * 2654435761u) >> (32 - HS_BITS)) & (HS - 1);
@@ -219,7 +223,7 @@ __global__ void __launch_bounds__(256) k_ib_bin(IbArgs a) {
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = __uint_as_float(ub);
     __syncthreads();
     // only the entries in use are read back (by the scatter)
-    int32_t* bb = a.blkbase + (int64_t)blockIdx.x * HS;
+    int32_t* bb = a.blkbase + blk * HS;
     for (int e = threadIdx.x; e < HS; e += blockDim.x) {
         const int T = hkey[e];
         if (T >= 0) {
@@ -228,15 +232,17 @@ __global__ void __launch_bounds__(256) k_ib_bin(IbArgs a) {
             bb[e] = base;
         }
     }
-    if (threadIdx.x == 0) {
+    if (with_f && threadIdx.x == 0) {
         uint32_t mx = 0;
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
             const uint32_t v = __float_as_uint(wmax[k]);
             mx = v > mx ? v : mx;
         }
-        a.blkmax[blockIdx.x] = mx;  // reduced by the scan
+        a.blkmax[blk] = mx;  // reduced by the scan
     }
 }
+
+__global__ void __launch_bounds__(256) k_ib_bin(IbArgs a) { bin_block(a, blockIdx.x, true); }
 
 // ---------------------------------------------------------------- scan (one workgroup)
 __device__ __forceinline__ int wave_incl_scan(int v) {
@@ -305,7 +311,7 @@ __global__ void __launch_bounds__(1024) k_ib_scan(IbArgs a) {
     // max |F| over the bin blocks' maxima (float bits order like the values; NaN/Inf above all)
     __shared__ uint32_t fmx[16];
     {
-        const int nbk = (int)((a.n + 255) / 256);
+        const int nbk = (int)a.blkmax_n;
         uint32_t mx = 0;
         for (int k = tid; k < nbk; k += blockDim.x) {
             const uint32_t v = a.blkmax[k];
@@ -520,6 +526,12 @@ __global__ void __launch_bounds__(MG_THREADS) k_ib_merge(IbArgs a) {
 hipError_t launch_ib_spread(lbm_ctx* c, const IbArgs& a) {
     const unsigned nb = (unsigned)((a.n + 255) / 256);
     if (a.n > 0) k_ib_bin<<<dim3(nb), dim3(256), 0, c->stream>>>(a);
+    return launch_ib_spread_binned(c, a);
+}
+
+// The spread after the binning: scan, scatter, fixed-point spread, merge.
+hipError_t launch_ib_spread_binned(lbm_ctx* c, const IbArgs& a) {
+    const unsigned nb = (unsigned)((a.n + 255) / 256);
     k_ib_scan<<<dim3(1), dim3(1024), 0, c->stream>>>(a);
     if (a.n > 0) k_ib_scatter<<<dim3(nb), dim3(256), 0, c->stream>>>(a);
     // the number of work items is only known on the device: a grid of a few workgroups per
@@ -772,10 +784,8 @@ __global__ void k_mem_rest(ib_membrane m, const double* X) {
     }
 }
 
-// Bending forces of every hinge on its four vertices: -k_b sin(theta - theta0) grad(theta).
-__global__ void __launch_bounds__(256) k_mem_hinges(ib_membrane m, const double* X) {
-    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= m.nh) return;
+// Bending forces of hinge h on its four vertices: -k_b sin(theta - theta0) grad(theta).
+__device__ __forceinline__ void hinge_one(const ib_membrane& m, const double* X, int64_t h) {
     double x[4][3], gr[4][3];
     for (int k = 0; k < 4; ++k) ld3(X, m.n, m.hinges[4 * h + k], x[k]);
     double c, sn;
@@ -787,6 +797,11 @@ __global__ void __launch_bounds__(256) k_mem_hinges(ib_membrane m, const double*
     }
 }
 
+__global__ void __launch_bounds__(256) k_mem_hinges(ib_membrane m, const double* X) {
+    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h < m.nh) hinge_one(m, X, h);
+}
+
 // Inverse of the node -> hinge incidence CSR: position of (hinge, role) in hinge_inc.
 __global__ void k_mem_hinge_slots(ib_membrane m, int64_t nnz) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -794,8 +809,11 @@ __global__ void k_mem_hinge_slots(ib_membrane m, int64_t nnz) {
 }
 
 // Per node (8 lanes each, partial sums combined by a fixed butterfly): springs (CSR), the
-// hinge forces of its incidences, tether.
-__global__ void __launch_bounds__(256) k_mem_forces(ib_membrane m, const double* X, float* Fout) {
+// hinge forces of its incidences, tether.  In the coupled step (rec != NULL) it also puts F
+// into the node records and the workgroup's max |F| into bmax[workgroup], the two parts of
+// the binning that need F.
+__global__ void __launch_bounds__(256) k_mem_forces(ib_membrane m, const double* X, float* Fout, float* rec,
+                                                    uint32_t* bmax) {
     const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
     const int sl = threadIdx.x & 7;
     const bool valid = i < m.n;
@@ -822,10 +840,47 @@ __global__ void __launch_bounds__(256) k_mem_forces(ib_membrane m, const double*
         F[1] += __shfl_xor(F[1], d, 64);
         F[2] += __shfl_xor(F[2], d, 64);
     }
+    if (valid && m.anchors)
+        for (int d = 0; d < 3; ++d) F[d] -= m.k_tether * (xi[d] - m.anchors[d * m.n + i]);
+    float Ff[3] = {(float)F[0], (float)F[1], (float)F[2]};
     if (valid && sl == 0) {
-        if (m.anchors)
-            for (int d = 0; d < 3; ++d) F[d] -= m.k_tether * (xi[d] - m.anchors[d * m.n + i]);
-        for (int d = 0; d < 3; ++d) Fout[d * m.n + i] = (float)F[d];
+        for (int d = 0; d < 3; ++d) Fout[d * m.n + i] = Ff[d];
+        if (rec)
+            for (int d = 0; d < 3; ++d) rec[i * REC + 16 + d] = Ff[d];
+    }
+    if (bmax) {
+        // workgroup max |F| as float bits (NaN/Inf above every finite value), as the binning does
+        float fm = 0.0f;
+        if (valid)
+            for (int d = 0; d < 3; ++d) {
+                fm = fmaxf(fm, fabsf(Ff[d]));
+                if (!isfinite(Ff[d])) fm = __uint_as_float(0x7f800000u);
+            }
+        uint32_t ub = __float_as_uint(fm);
+        for (int d = 32; d >= 1; d >>= 1) {
+            const uint32_t o = __shfl_xor(ub, d, 64);
+            ub = o > ub ? o : ub;
+        }
+        __shared__ uint32_t wm[4];
+        if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = ub;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t mx = 0;
+            for (int k = 0; k < (int)(blockDim.x >> 6); ++k) mx = wm[k] > mx ? wm[k] : mx;
+            bmax[blockIdx.x] = mx;
+        }
+    }
+}
+
+// The coupled step's first launch: the binning of the nodes by position (workgroups
+// [0, nbb), dispatched first: theirs is the longer dependent chain) and the hinge forces (the
+// rest), which it does not depend on.
+__global__ void __launch_bounds__(256) k_hinges_bin(ib_membrane m, const double* X, IbArgs a, int64_t nbb) {
+    if ((int64_t)blockIdx.x < nbb) {
+        bin_block(a, blockIdx.x, false);
+    } else {
+        const int64_t h = ((int64_t)blockIdx.x - nbb) * blockDim.x + threadIdx.x;
+        if (h < m.nh) hinge_one(m, X, h);
     }
 }
 
@@ -844,7 +899,19 @@ hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* 
     if (m->n <= 0) return hipSuccess;
     if (m->hinge_ptr && m->k_bend != 0.0 && m->nh > 0)
         k_mem_hinges<<<dim3((unsigned)((m->nh + 255) / 256)), dim3(256), 0, s>>>(*m, X);
-    k_mem_forces<<<dim3((unsigned)((8 * m->n + 255) / 256)), dim3(256), 0, s>>>(*m, X, F);
+    k_mem_forces<<<dim3((unsigned)((8 * m->n + 255) / 256)), dim3(256), 0, s>>>(*m, X, F, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_forces_and_bin(lbm_ctx* c, const ib_membrane* m, const double* X, float* F, IbArgs& a) {
+    const bool hinges = m->hinge_ptr && m->k_bend != 0.0 && m->nh > 0;
+    const int64_t nbh = hinges ? (m->nh + 255) / 256 : 0;
+    const int64_t nbb = (a.n + 255) / 256;
+    if (nbh + nbb > 0) k_hinges_bin<<<dim3((unsigned)(nbh + nbb)), dim3(256), 0, c->stream>>>(*m, X, a, nbb);
+    const int64_t nbf = (8 * m->n + 255) / 256;
+    if (m->n > 0)
+        k_mem_forces<<<dim3((unsigned)nbf), dim3(256), 0, c->stream>>>(*m, X, F, a.rec, a.blkmax);
+    a.blkmax_n = m->n > 0 ? nbf : 0;
     return hipGetLastError();
 }
 
