@@ -533,10 +533,9 @@ static lbm_status coupled(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, doub
         a.X = X;
         a.F = F;
         if (m) {
-            // the binning needs only X: it runs beside the hinge forces, and the force kernel
-            // after them fills in what it needs of F
-            if (launch_forces_and_bin(c, m, X, F, a) != hipSuccess) return LBM_ERR_HIP;
-            if (launch_ib_spread_binned(c, a) != hipSuccess) return LBM_ERR_HIP;
+            // the binning and the scan need only X: they run beside the hinge and node forces,
+            // and the force kernel fills in what the spread needs of F
+            if (launch_forces_spread(c, m, X, F, a) != hipSuccess) return LBM_ERR_HIP;
         } else if (launch_ib_spread(c, a) != hipSuccess) {
             return LBM_ERR_HIP;
         }

@@ -255,7 +255,56 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
-__global__ void __launch_bounds__(1024) k_ib_scan(IbArgs a) {
+// max |F| over the per-workgroup maxima in blkmax and the spread's fixed-point scale from it
+// (set.hdr: fmax_bits, nonfinite, scale_exp).  Every thread of one workgroup calls it.
+__device__ __forceinline__ void spread_scale(const IbArgs& a) {
+    __shared__ uint32_t fmx[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    {
+        const int nbk = (int)a.blkmax_n;
+        uint32_t mx = 0;
+        for (int k = tid; k < nbk; k += blockDim.x) {
+            const uint32_t v = a.blkmax[k];
+            mx = v > mx ? v : mx;
+        }
+        for (int d = 32; d >= 1; d >>= 1) {
+            const uint32_t o = __shfl_xor(mx, d, 64);
+            mx = o > mx ? o : mx;
+        }
+        if (lane == 0) fmx[wave] = mx;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        uint32_t mxall = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mxall = fmx[w] > mxall ? fmx[w] : mxall;
+        a.set.hdr->fmax_bits = mxall;
+        // fixed-point scale: |contribution| <= max|F|/8 and at most n contributions per
+        // cell, so |sum| < n * 2^e / 8 with max|F| < 2^e; keep sums below 2^62.
+        const float fm = __uint_as_float(mxall);
+        int s = 0;
+        if (!isfinite(fm)) {
+            a.set.hdr->nonfinite = 1;
+            atomicOr(a.flags, LBM_FLAG_FORCE_NONFINITE);
+        } else if (fm > 0.0f) {
+            int e;
+            frexpf(fm, &e);  // fm < 2^e
+            int L = 1;
+            while ((1ll << L) < a.n) ++L;
+            // one contribution |w_x w_y w_z F| <= max|F|/8 < 2^(e-3) stays below 2^31 after
+            // scaling, hence below 2^23 at the spread's per-batch scale 2^(s-8) (so it converts
+            // exactly through int32), and a sum of <= n of them stays below 2^62; the quantum
+            // of a contribution is 2^-26 max|F| or finer
+            s = 34 - e;
+            if (s > 65 - e - L) s = 65 - e - L;
+        }
+        a.set.hdr->scale_exp = s;
+    }
+}
+
+// One workgroup: list offsets, work items and partial-block offsets of the flagged tiles;
+// with_scale: also the spread's scale (else the scatter's first workgroup computes it, once
+// the membrane forces are in).
+__device__ __forceinline__ void scan_block(const IbArgs& a, bool with_scale) {
     __shared__ int wsum[3][16];
     __shared__ int carry[3];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -308,26 +357,8 @@ __global__ void __launch_bounds__(1024) k_ib_scan(IbArgs a) {
             for (int j = 0; j < 3; ++j) carry[j] = excl[j] + val[j];
         __syncthreads();
     }
-    // max |F| over the bin blocks' maxima (float bits order like the values; NaN/Inf above all)
-    __shared__ uint32_t fmx[16];
-    {
-        const int nbk = (int)a.blkmax_n;
-        uint32_t mx = 0;
-        for (int k = tid; k < nbk; k += blockDim.x) {
-            const uint32_t v = a.blkmax[k];
-            mx = v > mx ? v : mx;
-        }
-        for (int d = 32; d >= 1; d >>= 1) {
-            const uint32_t o = __shfl_xor(mx, d, 64);
-            mx = o > mx ? o : mx;
-        }
-        if (lane == 0) fmx[wave] = mx;
-        __syncthreads();
-    }
+    if (with_scale) spread_scale(a);
     if (tid == 0) {
-        uint32_t mxall = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mxall = fmx[w] > mxall ? fmx[w] : mxall;
-        a.set.hdr->fmax_bits = mxall;
         const int total = carry[0];
         a.set.slot_off[nf] = total;
         a.set.chunk_off[nf] = carry[1];
@@ -337,32 +368,15 @@ __global__ void __launch_bounds__(1024) k_ib_scan(IbArgs a) {
         a.other.hdr->fmax_bits = 0;
         a.other.hdr->nonfinite = 0;
         a.other.hdr->scale_exp = 0;
-        // fixed-point scale: |contribution| <= max|F|/8 and at most n contributions per
-        // cell, so |sum| < n * 2^e / 8 with max|F| < 2^e; keep sums below 2^62.
-        const float fm = __uint_as_float(a.set.hdr->fmax_bits);
-        int s = 0;
-        if (!isfinite(fm)) {
-            a.set.hdr->nonfinite = 1;
-            atomicOr(a.flags, LBM_FLAG_FORCE_NONFINITE);
-        } else if (fm > 0.0f) {
-            int e;
-            frexpf(fm, &e);  // fm < 2^e
-            int L = 1;
-            while ((1ll << L) < a.n) ++L;
-            // one contribution |w_x w_y w_z F| <= max|F|/8 < 2^(e-3) stays below 2^31 after
-            // scaling, hence below 2^23 at the spread's per-batch scale 2^(s-8) (so it converts
-            // exactly through int32), and a sum of <= n of them stays below 2^62; the quantum
-            // of a contribution is 2^-26 max|F| or finer
-            s = 34 - e;
-            if (s > 65 - e - L) s = 65 - e - L;
-        }
-        a.set.hdr->scale_exp = s;
         if (total > a.list_cap) atomicOr(a.flags, LBM_FLAG_LIST_OVERFLOW);
     }
 }
 
+__global__ void __launch_bounds__(1024) k_ib_scan(IbArgs a) { scan_block(a, true); }
+
 // ---------------------------------------------------------------- scatter (no atomics)
 __global__ void __launch_bounds__(256) k_ib_scatter(IbArgs a) {
+    if (a.scale_in_scatter && blockIdx.x == 0) spread_scale(a);
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= a.n) return;
     const float* r = a.rec + m * REC;
@@ -534,6 +548,11 @@ hipError_t launch_ib_spread_binned(lbm_ctx* c, const IbArgs& a) {
     const unsigned nb = (unsigned)((a.n + 255) / 256);
     k_ib_scan<<<dim3(1), dim3(1024), 0, c->stream>>>(a);
     if (a.n > 0) k_ib_scatter<<<dim3(nb), dim3(256), 0, c->stream>>>(a);
+    return launch_ib_spread_items(c, a);
+}
+
+// Fixed-point spread of the listed nodes and the merge of split tiles.
+hipError_t launch_ib_spread_items(lbm_ctx* c, const IbArgs& a) {
     // the number of work items is only known on the device: a grid of a few workgroups per
     // CU walks them (launching one workgroup per possible item costs more in empty waves
     // than the work itself)
@@ -812,9 +831,9 @@ __global__ void k_mem_hinge_slots(ib_membrane m, int64_t nnz) {
 // hinge forces of its incidences, tether.  In the coupled step (rec != NULL) it also puts F
 // into the node records and the workgroup's max |F| into bmax[workgroup], the two parts of
 // the binning that need F.
-__global__ void __launch_bounds__(256) k_mem_forces(ib_membrane m, const double* X, float* Fout, float* rec,
-                                                    uint32_t* bmax) {
-    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+__device__ __forceinline__ void forces_block(const ib_membrane& m, const double* X, float* Fout, float* rec,
+                                             uint32_t* bmax, int64_t blk) {
+    const int64_t i = (blk * blockDim.x + threadIdx.x) >> 3;
     const int sl = threadIdx.x & 7;
     const bool valid = i < m.n;
     double xi[3] = {0.0, 0.0, 0.0}, xj[3], r[3], F[3] = {0.0, 0.0, 0.0};
@@ -861,15 +880,30 @@ __global__ void __launch_bounds__(256) k_mem_forces(ib_membrane m, const double*
             const uint32_t o = __shfl_xor(ub, d, 64);
             ub = o > ub ? o : ub;
         }
-        __shared__ uint32_t wm[4];
+        __shared__ uint32_t wm[16];
         if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = ub;
         __syncthreads();
         if (threadIdx.x == 0) {
             uint32_t mx = 0;
             for (int k = 0; k < (int)(blockDim.x >> 6); ++k) mx = wm[k] > mx ? wm[k] : mx;
-            bmax[blockIdx.x] = mx;
+            bmax[blk] = mx;
         }
     }
+}
+
+__global__ void __launch_bounds__(256) k_mem_forces(ib_membrane m, const double* X, float* Fout) {
+    forces_block(m, X, Fout, nullptr, nullptr, blockIdx.x);
+}
+
+// The coupled step's second launch: the scan of the tile lists (workgroup 0; it needs only
+// the binning) and the membrane forces (the rest, 128 nodes each), which also fill in the
+// records' F and max |F| per workgroup.
+constexpr int FS_THREADS = 1024;
+__global__ void __launch_bounds__(FS_THREADS) k_forces_scan(ib_membrane m, const double* X, float* F, IbArgs a) {
+    if (blockIdx.x == 0)
+        scan_block(a, false);
+    else
+        forces_block(m, X, F, a.rec, a.blkmax, (int64_t)blockIdx.x - 1);
 }
 
 // The coupled step's first launch: the binning of the nodes by position (workgroups
@@ -899,20 +933,24 @@ hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* 
     if (m->n <= 0) return hipSuccess;
     if (m->hinge_ptr && m->k_bend != 0.0 && m->nh > 0)
         k_mem_hinges<<<dim3((unsigned)((m->nh + 255) / 256)), dim3(256), 0, s>>>(*m, X);
-    k_mem_forces<<<dim3((unsigned)((8 * m->n + 255) / 256)), dim3(256), 0, s>>>(*m, X, F, nullptr, nullptr);
+    k_mem_forces<<<dim3((unsigned)((8 * m->n + 255) / 256)), dim3(256), 0, s>>>(*m, X, F);
     return hipGetLastError();
 }
 
-hipError_t launch_forces_and_bin(lbm_ctx* c, const ib_membrane* m, const double* X, float* F, IbArgs& a) {
+// Coupled step, forces to spread: [binning | hinges] -> [scan | membrane forces] -> scatter
+// (whose first workgroup sets the spread's scale from the forces) -> spread -> merge.
+hipError_t launch_forces_spread(lbm_ctx* c, const ib_membrane* m, const double* X, float* F, IbArgs& a) {
     const bool hinges = m->hinge_ptr && m->k_bend != 0.0 && m->nh > 0;
     const int64_t nbh = hinges ? (m->nh + 255) / 256 : 0;
     const int64_t nbb = (a.n + 255) / 256;
     if (nbh + nbb > 0) k_hinges_bin<<<dim3((unsigned)(nbh + nbb)), dim3(256), 0, c->stream>>>(*m, X, a, nbb);
-    const int64_t nbf = (8 * m->n + 255) / 256;
-    if (m->n > 0)
-        k_mem_forces<<<dim3((unsigned)nbf), dim3(256), 0, c->stream>>>(*m, X, F, a.rec, a.blkmax);
-    a.blkmax_n = m->n > 0 ? nbf : 0;
-    return hipGetLastError();
+    const int64_t nbf = (8 * m->n + FS_THREADS - 1) / FS_THREADS;
+    a.blkmax_n = nbf;
+    a.scale_in_scatter = 1;
+    k_forces_scan<<<dim3((unsigned)(1 + nbf)), dim3(FS_THREADS), 0, c->stream>>>(*m, X, F, a);
+    const int64_t nbs = nbb > 0 ? nbb : 1;  // the first workgroup sets the scale, also with no nodes
+    k_ib_scatter<<<dim3((unsigned)nbs), dim3(256), 0, c->stream>>>(a);
+    return launch_ib_spread_items(c, a);
 }
 
 }  // namespace lbmib

@@ -95,7 +95,8 @@ struct IbArgs {
     unsigned long long* part;  // [part_cap][3][512] fixed-point partial sums of split tiles' chunks
     int64_t part_cap;
     uint32_t* blkmax;       // max |F| (float bits) per bin block, or per membrane-force workgroup
-    int64_t blkmax_n;       // entries of blkmax the scan reduces
+    int64_t blkmax_n;       // entries of blkmax reduced for the spread's scale
+    int32_t scale_in_scatter;  // the scatter's first workgroup sets the scale (not the scan)
     int32_t* item_slot;     // [max_items] slot of each spread work item
     int64_t max_items;
 };
@@ -219,11 +220,12 @@ hipError_t launch_copy16(hipStream_t s, const void* src, void* dst, int64_t byte
 // ib.hip
 hipError_t launch_ib_spread(lbm_ctx* c, const IbArgs& a);
 hipError_t launch_ib_spread_binned(lbm_ctx* c, const IbArgs& a);
+hipError_t launch_ib_spread_items(lbm_ctx* c, const IbArgs& a);
 hipError_t launch_ib_interp(lbm_ctx* c, const IbArgs& a);
 hipError_t launch_ib_advance(hipStream_t s, int64_t n, double* X, const float* U);
 hipError_t launch_membrane_rest(const ib_membrane* m, const double* X_rest, hipStream_t s);
 hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* F, hipStream_t s);
-hipError_t launch_forces_and_bin(lbm_ctx* c, const ib_membrane* m, const double* X, float* F, IbArgs& a);
+hipError_t launch_forces_spread(lbm_ctx* c, const ib_membrane* m, const double* X, float* F, IbArgs& a);
 
 // closure.hip
 hipError_t launch_mlp_pack(hipStream_t s, const float* params, const float* norm, float c_guard, MlpPacked* P);
