@@ -297,6 +297,14 @@ typedef struct {
                             the learned closure is enabled.  Default 0: on MI355X the
                             bandwidth-bound update occupies every CU and the latency-bound IB
                             kernels beside it slow down more than the overlap gains. */
+    int32_t split;       /* coupled steps without the closure or overlap: 1 = the lattice update with
+                            the body force alone runs in the same launch as the spread, then the
+                            flagged tiles' cells are updated with their force (merging split
+                            tiles' partial sums on the way); 0 = spread, merge, one fused update;
+                            -1 (default) = 1 for a single channel, 0 for several.  Bitwise the
+                            same results.  It pays when the flagged tiles are a few percent of the
+                            lattice (one channel with 16 platelets: 2.7%, 195 -> 190 us per step)
+                            and loses when they are many (the 64-channel batch: 10%). */
 } lbm_launch;
 
 lbm_status lbm_set_launch(lbm_ctx* ctx, const lbm_launch* cfg /*host*/);

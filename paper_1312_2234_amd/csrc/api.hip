@@ -128,6 +128,10 @@ LatArgs lat_args(lbm_ctx* c) {
         a.flag_list = c->set[c->ibset].flag_list;
         a.flag_ch = c->set[c->ibset].flag_ch;
         a.hdr = c->set[c->ibset].hdr;
+        a.big = c->set[c->ibset].big;
+        a.chunk_off = c->set[c->ibset].chunk_off;
+        a.part = c->d_part;
+        a.force_w = c->d_force;
     }
     return a;
 }
@@ -532,16 +536,26 @@ static lbm_status coupled(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, doub
         IbArgs a = ib_args(c, c->ibset);
         a.X = X;
         a.F = F;
+        // Without the closure or the second stream, the lattice update away from the IB tiles
+        // (body force only) runs in the spread's launch, and the flagged tiles' cells are then
+        // updated with their force (merging split tiles' partial sums on the way): bitwise the
+        // fused update.
+        const bool split_update =
+            m && !ov && !c->closure && (c->launch.split == 1 || (c->launch.split == -1 && c->nch == 1));
         if (m) {
             // the binning and the scan need only X: they run beside the hinge and node forces,
             // and the force kernel fills in what the spread needs of F
-            if (launch_forces_spread(c, m, X, F, a) != hipSuccess) return LBM_ERR_HIP;
+            if (launch_forces_scatter(c, m, X, F, a) != hipSuccess) return LBM_ERR_HIP;
+            if (!split_update && launch_ib_spread_items(c, a) != hipSuccess) return LBM_ERR_HIP;
         } else if (launch_ib_spread(c, a) != hipSuccess) {
             return LBM_ERR_HIP;
         }
         LatArgs la = lat_args(c);
         hipError_t e;
-        if (ov) {
+        if (split_update) {
+            e = launch_spread_far(c, a, la);
+            if (e == hipSuccess) e = launch_step_tiles(c, la, true);
+        } else if (ov) {
             e = hipStreamWaitEvent(c->stream, c->ev_far, 0);
             if (e == hipSuccess) e = launch_step_tiles(c, la);
         } else {
@@ -614,7 +628,7 @@ lbm_status lbm_set_launch(lbm_ctx* c, const lbm_launch* cfg) {
     if (b != 64 && b != 128 && b != 256 && b != 512 && b != 1024) return LBM_ERR_ARG;
     if (cfg->persistent < 0 || (cfg->xcd_remap != 0 && cfg->xcd_remap != 1) ||
         (cfg->nontemporal != 0 && cfg->nontemporal != 1) || cfg->vec < 0 || cfg->vec > 4 || cfg->vec == 3 ||
-        (cfg->overlap != 0 && cfg->overlap != 1))
+        (cfg->overlap != 0 && cfg->overlap != 1) || cfg->split < -1 || cfg->split > 1)
         return LBM_ERR_ARG;
     c->launch = *cfg;
     return LBM_OK;

@@ -417,7 +417,8 @@ __device__ __forceinline__ unsigned fixed_round(float c, float scale) {
 constexpr int SP_BATCH_SHIFT = 8;
 static_assert(SP_BATCH <= (1 << SP_BATCH_SHIFT), "a batch sum must stay below 2^31");
 
-__global__ void __launch_bounds__(SP_THREADS) k_ib_spread(IbArgs a) {
+// The spread's work items first, first + stride, ... (one workgroup of SP_THREADS threads).
+__device__ __forceinline__ void spread_items(const IbArgs& a, int64_t first, int64_t stride) {
     __shared__ unsigned long long acc[3 * TILE_CELLS];
     __shared__ unsigned acc32[3 * TILE_CELLS];
     __shared__ int4 base[SP_BATCH];         // stencil base x, y, z of each staged node
@@ -429,7 +430,7 @@ __global__ void __launch_bounds__(SP_THREADS) k_ib_spread(IbArgs a) {
     const double inv = ldexp(1.0, -sexp);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ix = lane & 3, iy = (lane >> 2) & 3, iz = lane >> 4;
-    for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
+    for (int64_t wi = first; wi < nwork; wi += stride) {
         const int slot = a.item_slot[wi];
         const int c = wi - a.set.chunk_off[slot];
         const int nch = a.set.chunk_off[slot + 1] - a.set.chunk_off[slot];
@@ -509,6 +510,68 @@ __global__ void __launch_bounds__(SP_THREADS) k_ib_spread(IbArgs a) {
         }
         __syncthreads();
     }
+}
+
+__global__ void __launch_bounds__(SP_THREADS) k_ib_spread(IbArgs a) { spread_items(a, blockIdx.x, gridDim.x); }
+
+// The spread's work items (workgroups [0, gs)) beside the lattice update of every cell with
+// the body force alone (the rest, SP_THREADS/64 segments of 64 cells each), which does not
+// depend on the spread; the flagged tiles' cells are updated again afterwards with their
+// force (k_step_tiles).  Same helpers and roundings as the fused step.
+template <class St, bool NT>
+__global__ void __launch_bounds__(SP_THREADS) k_spread_far(IbArgs a, LatArgs la, int64_t gs) {
+    using T = typename St::T;
+    if ((int64_t)blockIdx.x < gs) {
+        spread_items(a, blockIdx.x, gs);
+        return;
+    }
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t seg = ((int64_t)blockIdx.x - gs) * (SP_THREADS / 64) + wave;
+    if (seg >= la.nseg) return;
+    const Chan& ch = la.chan[la.seg_ch[seg]];
+    const int64_t n64 = (seg - ch.seg_off) * 64 + lane;
+    if (n64 >= ch.ncell) return;
+    const int32_t n = (int32_t)n64;
+    int x, y, z;
+    cell_xyz(ch, (uint32_t)n, x, y, z);
+    const T* src = (const T*)la.src + ch.pop_off;
+    T* dst = (T*)la.dst + ch.pop_off;
+    float g[Q];
+    pull<St>(src, ch, ch.ncell, n, x, y, z, g);
+    float drho, jx, jy, jz;
+    moments(g, drho, jx, jy, jz);
+    const CellState cs = cell_state(drho, jx, jy, jz, ch.body[0], ch.body[1], ch.body[2]);
+    const float om = ch.omega, guo = ch.guo;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const float gn = bgk_c(i, g[i], cs, om, guo);
+        if (NT)
+            St::st_nt(dst + pidx(i, n), gn);
+        else
+            St::st(dst + pidx(i, n), gn);
+    }
+}
+
+template <class St>
+static void launch_spread_far_typed(lbm_ctx* c, const IbArgs& a, const LatArgs& la, int64_t gs, int64_t gl) {
+    const dim3 grid((unsigned)(gs + gl)), block(SP_THREADS);
+    if (c->launch.nontemporal)
+        k_spread_far<St, true><<<grid, block, 0, c->stream>>>(a, la, gs);
+    else
+        k_spread_far<St, false><<<grid, block, 0, c->stream>>>(a, la, gs);
+}
+
+hipError_t launch_spread_far(lbm_ctx* c, const IbArgs& a, const LatArgs& la) {
+    int64_t gs = c->max_items < c->ib_grid ? c->max_items : c->ib_grid;
+    if (gs < 1) gs = 1;
+    const int64_t gl = (la.nseg + SP_THREADS / 64 - 1) / (SP_THREADS / 64);
+    switch (c->storage) {
+        case LBM_STORE_F32: launch_spread_far_typed<StF32>(c, a, la, gs, gl); break;
+        case LBM_STORE_F16: launch_spread_far_typed<StF16>(c, a, la, gs, gl); break;
+        case LBM_STORE_BF16: launch_spread_far_typed<StBF16>(c, a, la, gs, gl); break;
+    }
+    return hipGetLastError();
 }
 
 // Force blocks of split tiles: the sum of their chunks' partial blocks (chunk order).
@@ -937,9 +1000,9 @@ hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* 
     return hipGetLastError();
 }
 
-// Coupled step, forces to spread: [binning | hinges] -> [scan | membrane forces] -> scatter
-// (whose first workgroup sets the spread's scale from the forces) -> spread -> merge.
-hipError_t launch_forces_spread(lbm_ctx* c, const ib_membrane* m, const double* X, float* F, IbArgs& a) {
+// Coupled step, forces to node lists: [binning | hinges] -> [scan | membrane forces] ->
+// scatter (whose first workgroup sets the spread's scale from the forces).
+hipError_t launch_forces_scatter(lbm_ctx* c, const ib_membrane* m, const double* X, float* F, IbArgs& a) {
     const bool hinges = m->hinge_ptr && m->k_bend != 0.0 && m->nh > 0;
     const int64_t nbh = hinges ? (m->nh + 255) / 256 : 0;
     const int64_t nbb = (a.n + 255) / 256;
@@ -950,7 +1013,8 @@ hipError_t launch_forces_spread(lbm_ctx* c, const ib_membrane* m, const double* 
     k_forces_scan<<<dim3((unsigned)(1 + nbf)), dim3(FS_THREADS), 0, c->stream>>>(*m, X, F, a);
     const int64_t nbs = nbb > 0 ? nbb : 1;  // the first workgroup sets the scale, also with no nodes
     k_ib_scatter<<<dim3((unsigned)nbs), dim3(256), 0, c->stream>>>(a);
-    return launch_ib_spread_items(c, a);
+    return hipGetLastError();
 }
+
 
 }  // namespace lbmib

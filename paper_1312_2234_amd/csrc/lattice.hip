@@ -48,13 +48,37 @@ __global__ void __launch_bounds__(1024) k_step(LatArgs a) {
 // The same update for the cells of the flagged IB tiles only (one workgroup of 512 threads
 // per tile, one cell per thread), with their force.  Used after a full update with the body
 // force alone: it overwrites exactly the cells whose IB force may be nonzero, with the
-// values the fused update produces.
-template <class St>
+// values the fused update produces.  MERGE: a tile spread in several work items has only
+// partial fixed-point blocks yet; this cell's sums are added here (as the merge kernel adds
+// them) and the tile's force block is written for the later readers.
+template <class St, bool MERGE>
 __global__ void __launch_bounds__(TILE_CELLS) k_step_tiles(LatArgs a) {
     using T = typename St::T;
     const int nf = a.hdr->nflag;
     const int l = threadIdx.x;
     for (int slot = blockIdx.x; slot < nf; slot += gridDim.x) {
+        float f3[3];
+        const int bigid = MERGE ? a.big[slot] : -1;
+        if (MERGE && bigid >= 0) {
+            const int nch = a.chunk_off[slot + 1] - a.chunk_off[slot];
+            const unsigned long long* pb = a.part + (int64_t)bigid * (3 * TILE_CELLS) + l;
+            unsigned long long v[3] = {0ull, 0ull, 0ull};
+            for (int j = 0; j < nch; ++j)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) v[k] += pb[(int64_t)j * (3 * TILE_CELLS) + k * TILE_CELLS];
+            const bool nonfinite = a.hdr->nonfinite != 0;
+            const double inv = ldexp(1.0, -a.hdr->scale_exp);
+            float* fw = a.force_w + (int64_t)slot * (3 * TILE_CELLS) + l;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                f3[k] = nonfinite ? __builtin_nanf("") : (float)((double)(long long)v[k] * inv);
+                fw[k * TILE_CELLS] = f3[k];
+            }
+        } else {
+            const float* fb = a.force + (int64_t)slot * (3 * TILE_CELLS) + l;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) f3[k] = fb[k * TILE_CELLS];
+        }
         const Chan& ch = a.chan[a.flag_ch[slot]];
         const int t = (int)(a.flag_list[slot] - ch.tile_off);
         const int x = (t % ch.tnx) * TILE + (l & 7);
@@ -68,7 +92,13 @@ __global__ void __launch_bounds__(TILE_CELLS) k_step_tiles(LatArgs a) {
         pull<St>(s, ch, ch.ncell, n, x, y, z, g);
         float drho, jx, jy, jz, Fx, Fy, Fz;
         moments(g, drho, jx, jy, jz);
-        ib_force(a, ch, x, y, z, Fx, Fy, Fz);
+        // the body force plus this tile's IB force, as ib_force adds them
+        Fx = ch.body[0];
+        Fy = ch.body[1];
+        Fz = ch.body[2];
+        Fx += f3[0];
+        Fy += f3[1];
+        Fz += f3[2];
         const CellState cs = cell_state(drho, jx, jy, jz, Fx, Fy, Fz);
         const float om = ch.omega, guo = ch.guo;
 #pragma unroll
@@ -440,14 +470,22 @@ hipError_t launch_lattice(lbm_ctx* c, int which, const LatArgs& a) {
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_step_tiles(lbm_ctx* c, const LatArgs& a) {
+template <class St>
+static void launch_tiles_typed(lbm_ctx* c, const LatArgs& a, bool merge, dim3 grid, dim3 block) {
+    if (merge)
+        k_step_tiles<St, true><<<grid, block, 0, c->stream>>>(a);
+    else
+        k_step_tiles<St, false><<<grid, block, 0, c->stream>>>(a);
+}
+
+hipError_t launch_step_tiles(lbm_ctx* c, const LatArgs& a, bool merge) {
     int64_t g = c->max_slots < c->ib_grid ? c->max_slots : c->ib_grid;
     if (g < 1) g = 1;
     const dim3 grid((unsigned)g), block(TILE_CELLS);
     switch (c->storage) {
-        case LBM_STORE_F32: k_step_tiles<StF32><<<grid, block, 0, c->stream>>>(a); break;
-        case LBM_STORE_F16: k_step_tiles<StF16><<<grid, block, 0, c->stream>>>(a); break;
-        case LBM_STORE_BF16: k_step_tiles<StBF16><<<grid, block, 0, c->stream>>>(a); break;
+        case LBM_STORE_F32: launch_tiles_typed<StF32>(c, a, merge, grid, block); break;
+        case LBM_STORE_F16: launch_tiles_typed<StF16>(c, a, merge, grid, block); break;
+        case LBM_STORE_BF16: launch_tiles_typed<StBF16>(c, a, merge, grid, block); break;
     }
     return hipGetLastError();
 }

@@ -56,6 +56,10 @@ struct LatArgs {
     const int32_t* flag_list;  // flagged tiles of the current force field (tile update)
     const int32_t* flag_ch;
     const IbHdr* hdr;
+    const int32_t* big;        // first partial block of each split slot, -1 otherwise
+    const int32_t* chunk_off;  // [slots+1] work items of each slot
+    const unsigned long long* part;  // fixed-point partial blocks of split slots
+    float* force_w;            // force blocks, written by the merging tile update
     int32_t remap;          // XCD-aware block order
     int32_t persistent;     // loop over blocks
     // auxiliary inputs / outputs of the non-step kernels
@@ -198,7 +202,7 @@ struct lbm_ctx {
     int64_t ib_grid = 1024;  // workgroups of the grid-stride IB kernels (set from the CU count)
     float* d_force = nullptr;
     float* d_vel = nullptr;
-    lbm_launch launch{256, 1, 0, 1, 0, 0};
+    lbm_launch launch{256, 1, 0, 1, 0, 0, -1};
     hipStream_t side = nullptr;         // second stream of the overlapped coupled step
     hipEvent_t ev_state = nullptr, ev_far = nullptr;
     lbmib::MlpPacked* d_mlp = nullptr;
@@ -211,7 +215,7 @@ namespace lbmib {
 
 // lattice.hip
 hipError_t launch_lattice(lbm_ctx* c, int which, const LatArgs& a);
-hipError_t launch_step_tiles(lbm_ctx* c, const LatArgs& a);
+hipError_t launch_step_tiles(lbm_ctx* c, const LatArgs& a, bool merge = false);
 enum { LK_STEP = 0, LK_INIT, LK_MOMENTS, LK_GETF, LK_SETF, LK_WSS };
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
 hipError_t launch_wss(lbm_ctx* c, const LatArgs& a, int64_t total);
@@ -225,7 +229,8 @@ hipError_t launch_ib_interp(lbm_ctx* c, const IbArgs& a);
 hipError_t launch_ib_advance(hipStream_t s, int64_t n, double* X, const float* U);
 hipError_t launch_membrane_rest(const ib_membrane* m, const double* X_rest, hipStream_t s);
 hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* F, hipStream_t s);
-hipError_t launch_forces_spread(lbm_ctx* c, const ib_membrane* m, const double* X, float* F, IbArgs& a);
+hipError_t launch_forces_scatter(lbm_ctx* c, const ib_membrane* m, const double* X, float* F, IbArgs& a);
+hipError_t launch_spread_far(lbm_ctx* c, const IbArgs& a, const LatArgs& la);
 
 // closure.hip
 hipError_t launch_mlp_pack(hipStream_t s, const float* params, const float* norm, float c_guard, MlpPacked* P);

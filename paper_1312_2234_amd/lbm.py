@@ -43,7 +43,7 @@ class LbmParams(C.Structure):
 
 class LbmLaunch(C.Structure):
     _fields_ = [("block", C.c_int32), ("xcd_remap", C.c_int32), ("persistent", C.c_int32),
-                ("nontemporal", C.c_int32), ("vec", C.c_int32), ("overlap", C.c_int32)]
+                ("nontemporal", C.c_int32), ("vec", C.c_int32), ("overlap", C.c_int32), ("split", C.c_int32)]
 
 
 class IbMembrane(C.Structure):
@@ -335,15 +335,15 @@ class Lattice:
             _check(lib().lbm_restrict(self.h, float(tau_coarse), _ptr(g), _ptr(F)), "lbm_restrict")
         return g, F
 
-    def set_launch(self, block=256, xcd_remap=1, persistent=0, nontemporal=0, vec=0, overlap=0):
-        cfg = LbmLaunch(block, xcd_remap, persistent, nontemporal, vec, overlap)
+    def set_launch(self, block=256, xcd_remap=1, persistent=0, nontemporal=0, vec=0, overlap=0, split=-1):
+        cfg = LbmLaunch(block, xcd_remap, persistent, nontemporal, vec, overlap, split)
         _check(lib().lbm_set_launch(self.h, C.byref(cfg)), "lbm_set_launch")
 
     def get_launch(self):
         cfg = LbmLaunch()
         _check(lib().lbm_get_launch(self.h, C.byref(cfg)), "lbm_get_launch")
         return dict(block=cfg.block, xcd_remap=cfg.xcd_remap, persistent=cfg.persistent,
-                    nontemporal=cfg.nontemporal, vec=cfg.vec, overlap=cfg.overlap)
+                    nontemporal=cfg.nontemporal, vec=cfg.vec, overlap=cfg.overlap, split=cfg.split)
 
 
 def stream_copy(src, dst, variant=0, grid=0):

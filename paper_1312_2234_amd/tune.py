@@ -15,7 +15,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(_HERE, "tuned_launch.json")
 
-DEFAULT = dict(block=256, xcd_remap=1, persistent=0, nontemporal=1, vec=0, overlap=0)
+DEFAULT = dict(block=256, xcd_remap=1, persistent=0, nontemporal=1, vec=0, overlap=0, split=-1)
 
 
 def candidates(n_cu=256):

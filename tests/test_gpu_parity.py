@@ -518,17 +518,20 @@ def test_storage_precision_report_with_platelet(orc, gpu):
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_overlapped_schedule_is_bitwise_sequential(gpu, storage):
-    """The overlapped coupled step (body-force-only update on a second stream, then the
-    flagged IB tiles updated again with their force) gives the same bits as the fused
-    update, eagerly and replayed from a graph."""
+    """The split coupled steps give the same bits as the fused update, eagerly and replayed
+    from a graph:
+    - overlap: the body-force-only update on a second stream, then the flagged IB tiles
+      updated again with their force;
+    - split: the body-force-only update in the spread's launch, then the flagged tiles
+      updated with their force, merging split tiles' partial sums on the way."""
     import torch
 
     ch = inputs.shear_platelets(seed=2, nx=96, ny=48, nz=64, count=3)
     b = ch.bodies
     out = []
-    for overlap in (1, 0):
+    for overlap, split in ((1, 0), (0, 1), (0, 0)):
         g = gpu.Lattice([ch], storage=storage, max_nodes=b.n, device=DEV)
-        g.set_launch(block=128, xcd_remap=0, nontemporal=1, overlap=overlap)
+        g.set_launch(block=128, xcd_remap=0, nontemporal=1, overlap=overlap, split=split)
         g.init()
         g.set_nodes(b.n)
         mem = gpu.Membrane(b, device=DEV)
@@ -541,6 +544,35 @@ def test_overlapped_schedule_is_bitwise_sequential(gpu, storage):
         g.coupled_steps(mem, 1, X, F, U)
         torch.cuda.synchronize()
         out.append((N(g.get_state()), N(X), g.error_flags()))
-    assert out[0][2] == 0 and out[1][2] == 0
-    assert np.array_equal(out[0][0], out[1][0])
-    assert np.array_equal(out[0][1], out[1][1])
+    assert all(o[2] == 0 for o in out)
+    for o in out[:2]:
+        assert np.array_equal(o[0], out[2][0])
+        assert np.array_equal(o[1], out[2][1])
+
+
+def test_split_update_multichannel_is_bitwise_fused(gpu):
+    """Several channels (uneven sizes and platelet counts): the split coupled step, forced on,
+    gives the fused update's bits; the default for several channels is the fused update."""
+    import torch
+
+    chans = inputs.batched_channels(seed=3, nch=5)
+    b, offs = inputs.concat_bodies(chans)
+    out = []
+    for split in (1, 0, -1):
+        g = gpu.Lattice(chans, max_nodes=b.n, device=DEV)
+        g.set_launch(block=256, xcd_remap=0, nontemporal=1, split=split)
+        g.init()
+        g.set_nodes(b.n, offs)
+        mem = gpu.Membrane(b, device=DEV)
+        X = T(b.X)
+        F = torch.zeros((3, b.n), dtype=torch.float32, device=DEV)
+        U = torch.zeros_like(F)
+        g.coupled_steps(mem, 5, X, F, U)
+        g.graph_capture(mem, 2, X, F, U)
+        g.graph_launch(2)
+        torch.cuda.synchronize()
+        out.append((N(g.get_state()), N(X), g.error_flags(), g.get_launch()["split"]))
+    assert all(o[2] == 0 for o in out)
+    assert out[2][3] == -1
+    for o in out[:2]:
+        assert np.array_equal(o[0], out[2][0]) and np.array_equal(o[1], out[2][1])
