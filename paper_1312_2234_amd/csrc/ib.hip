@@ -718,6 +718,25 @@ __global__ void __launch_bounds__(256) k_ib_gather(IbArgs a) {
         else if (y >= ch.ny) y -= ch.ny;
         int z = b[2] + cq;
         if (z >= ch.nz) z -= ch.nz;
+        // the row's four x cells lie in at most two tiles (the first and the last cell's; a
+        // middle cell in neither happens only when nx < 8): two slot lookups, not four
+        int xs4[4], sl4[4];
+        if (yok) {
+#pragma unroll
+            for (int ax = 0; ax < 4; ++ax) {
+                int x = b[0] + ax;
+                if (x >= ch.nx) x -= ch.nx;
+                xs4[ax] = x;
+            }
+            const int sa = a.set.tile_slot[tile_of(ch, xs4[0], y, z)];
+            const int sb = a.set.tile_slot[tile_of(ch, xs4[3], y, z)];
+#pragma unroll
+            for (int ax = 0; ax < 4; ++ax) {
+                const int tx = xs4[ax] >> 3;
+                sl4[ax] = tx == (xs4[0] >> 3) ? sa
+                                              : (tx == (xs4[3] >> 3) ? sb : a.set.tile_slot[tile_of(ch, xs4[ax], y, z)]);
+            }
+        }
 #pragma unroll
         for (int ax = 0; ax < 4; ++ax) {
             const float ww = w[0][ax] * wyz;
@@ -726,9 +745,8 @@ __global__ void __launch_bounds__(256) k_ib_gather(IbArgs a) {
                 const float* uw = y < 0 ? ch.uw_lo : ch.uw_hi;
                 v0 = uw[0]; v1 = uw[1]; v2 = uw[2];
             } else {
-                int x = b[0] + ax;
-                if (x >= ch.nx) x -= ch.nx;
-                const int slot = a.set.tile_slot[tile_of(ch, x, y, z)];
+                const int x = xs4[ax];
+                const int slot = sl4[ax];
                 if (slot >= 0) {
                     const float4 vb = ((const float4*)(a.vel + (int64_t)slot * (4 * TILE_CELLS)))[tile_local(x, y, z)];
                     v0 = vb.x; v1 = vb.y; v2 = vb.z;
