@@ -27,10 +27,15 @@
  *       scheme creates mass.
  *   R2  Both the equilibrium and the source use the shifted velocity v.
  *   R3  Eq. (36) prints the zero branch of phi as "|x| <= 2"; read as |x| >= 2.
- *   R4  Walls: halfway bounce-back with the moving-wall term 6 w_i rho_w c_i.u_w
- *       (rho_w = 1) on planes y = -1/2 and y = ny - 1/2 (wall normal along y);
- *       x and z are periodic.  (The paper's own on-site wall of Eq. (23)-(30) is
- *       a later extension.)
+ *   R4  Walls (walls = 1): halfway bounce-back with the moving-wall term
+ *       6 w_i rho_w c_i.u_w (rho_w = 1) on planes y = -1/2 and y = ny - 1/2 (wall
+ *       normal along y); x and z are periodic.
+ *   R22 On-site walls (walls = 2): the velocity boundary of Eq. (23)-(30) on the
+ *       rows y = 0 and y = ny - 1 themselves, turned from the paper's z-normal wall
+ *       to a y-normal one.  With the Guo force the fluid velocity is
+ *       (sum c f + F/2) / rho, so the momentum the rule imposes is rho v_w - F/2
+ *       (the printed rule, which has no force, is the case F = 0); the wall node
+ *       then moves exactly with the wall.
  *   R5  The interpolated velocity is v^{n+1} = (sum c f^{n+1} + (F_body + g^n)/2)
  *       / rho^{n+1}, the field after the LBM step (Fig. 1), taken at X^n; stencil
  *       rows inside a wall take that wall's velocity; spreading drops them.
@@ -77,11 +82,12 @@ static const double CS2 = 1.0 / 3.0; /* c_s^2, text under Eq. (20) */
 
 typedef struct {
     int32_t nx, ny, nz;
-    int32_t walls;   /* 1: bounce-back walls normal to y; 0: periodic in y too */
+    int32_t walls;   /* 1: bounce-back walls normal to y; 2: on-site walls on rows 0 and
+                        ny-1 (R22); 0: periodic in y too */
     double tau;
     double body[3];  /* constant body force, added to the IB force field */
-    double uw_lo[3]; /* velocity of the wall at y = -1/2 */
-    double uw_hi[3]; /* velocity of the wall at y = ny - 1/2 */
+    double uw_lo[3]; /* velocity of the lower wall (y = -1/2, or row 0 on-site) */
+    double uw_hi[3]; /* velocity of the upper wall (y = ny - 1/2, or row ny-1 on-site) */
 } orc_params;
 
 /* threads an OpenMP region of the oracle uses (1 without OpenMP) */
@@ -171,16 +177,77 @@ void orc_init(const orc_params* p, double* f, const double* rho, const double* u
     }
 }
 
+/* The 19 populations of node n (row y) as the step sees them.  With on-site walls
+ * (walls = 2, reading R22) the populations entering the fluid at a wall row have no
+ * source node; Hecht and Harting's rule, Eq. (23)-(30), sets them from the others.
+ * The paper writes it for the wall z = 0; here the wall normal is y, the inward
+ * normal is n = +e_y on row 0 and -e_y on row ny-1, and x, z are the transverse
+ * directions t.  With F the force at the node and J = rho v_w - F/2 (R22):
+ *   Eq. (23)       rho (1 - n.v_w) = sum_{c.n=0} f + 2 sum_{c.n=-1} f - n.F/2
+ *   Eq. (29)-(30)  N_t = 1/2 sum_{c.n=0} c_t f - J_t / 3
+ *   Eq. (24)       f_i = f_opp(i) + n.J / 3                       (c_i = n)
+ *   Eq. (25)-(28)  f_i = f_opp(i) + (n.J + c_it J_t) / 6 - c_it N_t  (c_i = n + c_it e_t)
+ * Every other node, and every population with c.n <= 0, is returned as stored. */
+static void node_populations(const orc_params* p, const double* f, const double* g, int64_t n, int64_t y,
+                             double fn[Q]) {
+    int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    for (int i = 0; i < Q; ++i) fn[i] = f[i * N + n];
+    if (p->walls != 2 || (y != 0 && y != p->ny - 1)) return;
+    int s = y == 0 ? 1 : -1; /* n = s e_y */
+    const double* vw = y == 0 ? p->uw_lo : p->uw_hi;
+    double F[3];
+    for (int d = 0; d < 3; ++d) F[d] = p->body[d] + (g ? g[d * N + n] : 0.0);
+    double par = 0.0, out = 0.0;
+    for (int i = 0; i < Q; ++i) {
+        int cn = s * CV[i][1];
+        if (cn == 0) par += fn[i];
+        if (cn == -1) out += fn[i];
+    }
+    double rho = (par + 2.0 * out - 0.5 * s * F[1]) / (1.0 - s * vw[1]); /* Eq. (23) */
+    double J[3];
+    for (int d = 0; d < 3; ++d) J[d] = rho * vw[d] - 0.5 * F[d];
+    double Nt[3] = {0.0, 0.0, 0.0}; /* Eq. (29)-(30); Nt[1] unused */
+    for (int t = 0; t < 3; t += 2) {
+        double m = 0.0;
+        for (int i = 0; i < Q; ++i)
+            if (CV[i][1] == 0) m += CV[i][t] * fn[i];
+        Nt[t] = 0.5 * m - J[t] / 3.0;
+    }
+    double nJ = s * J[1];
+    for (int i = 0; i < Q; ++i) {
+        if (s * CV[i][1] != 1) continue;
+        int o = opposite(i);
+        int t = CV[i][0] != 0 ? 0 : (CV[i][2] != 0 ? 2 : -1);
+        if (t < 0)
+            fn[i] = fn[o] + nJ / 3.0;                                            /* Eq. (24) */
+        else
+            fn[i] = fn[o] + (nJ + CV[i][t] * J[t]) / 6.0 - CV[i][t] * Nt[t];     /* Eq. (25)-(28) */
+    }
+}
+
+/* The populations of every node as the next step sees them (node_populations):
+ * a copy of f, with the on-site wall rule applied at the wall rows when walls = 2. */
+void orc_complete(const orc_params* p, const double* f, const double* g, double* fc) {
+    int64_t nx = p->nx, ny = p->ny, nz = p->nz, N = nx * ny * nz;
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        double fn[Q];
+        node_populations(p, f, g, n, (n / nx) % ny, fn);
+        for (int i = 0; i < Q; ++i) fc[i * N + n] = fn[i];
+    }
+}
+
 /* Eq. (17)-(18) and the shift under Eq. (19):
  * rho = sum f, v = (sum c f + F/2) / rho with F = F_body + g(x). */
 void orc_moments(const orc_params* p, const double* f, const double* g, double* rho, double* v) {
     int64_t N = (int64_t)p->nx * p->ny * p->nz;
 #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; ++n) {
-        double r = 0.0, j[3] = {0, 0, 0};
+        double r = 0.0, j[3] = {0, 0, 0}, fn[Q];
+        node_populations(p, f, g, n, (n / p->nx) % p->ny, fn);
         for (int i = 0; i < Q; ++i) {
-            r += f[i * N + n];
-            for (int d = 0; d < 3; ++d) j[d] += CV[i][d] * f[i * N + n];
+            r += fn[i];
+            for (int d = 0; d < 3; ++d) j[d] += CV[i][d] * fn[i];
         }
         rho[n] = r;
         for (int d = 0; d < 3; ++d) {
@@ -196,10 +263,11 @@ void orc_collide(const orc_params* p, const double* f, const double* g, double* 
     int64_t N = (int64_t)p->nx * p->ny * p->nz;
 #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; ++n) {
-        double r = 0.0, j[3] = {0, 0, 0}, F[3], v[3], feq[Q], S[Q];
+        double r = 0.0, j[3] = {0, 0, 0}, F[3], v[3], feq[Q], S[Q], fn[Q];
+        node_populations(p, f, g, n, (n / p->nx) % p->ny, fn);
         for (int i = 0; i < Q; ++i) {
-            r += f[i * N + n];
-            for (int d = 0; d < 3; ++d) j[d] += CV[i][d] * f[i * N + n];
+            r += fn[i];
+            for (int d = 0; d < 3; ++d) j[d] += CV[i][d] * fn[i];
         }
         for (int d = 0; d < 3; ++d) {
             F[d] = p->body[d] + (g ? g[d * N + n] : 0.0);
@@ -208,12 +276,14 @@ void orc_collide(const orc_params* p, const double* f, const double* g, double* 
         orc_feq(r, v, feq);
         orc_source(p->tau, v, F, S);
         for (int i = 0; i < Q; ++i)
-            fs[i * N + n] = f[i * N + n] - (f[i * N + n] - feq[i]) / p->tau + S[i];
+            fs[i * N + n] = fn[i] - (fn[i] - feq[i]) / p->tau + S[i];
     }
 }
 
 /* Streaming of one LBM time step (reading R4 at walls):
- * f_i(x, t+1) = f*_i(x - c_i); across a wall f_i(x, t+1) = f*_{opp(i)}(x) + 6 w_i rho_w c_i.u_w. */
+ * f_i(x, t+1) = f*_i(x - c_i); across a wall f_i(x, t+1) = f*_{opp(i)}(x) + 6 w_i rho_w c_i.u_w.
+ * On-site walls (R22): a population entering through the wall has no source and is
+ * stored as 0; node_populations sets it when the state is read. */
 void orc_stream(const orc_params* p, const double* fs, double* fout) {
     int64_t nx = p->nx, ny = p->ny, nz = p->nz, N = nx * ny * nz;
 #pragma omp parallel for schedule(static)
@@ -223,7 +293,9 @@ void orc_stream(const orc_params* p, const double* fs, double* fout) {
                 int64_t n = x + nx * (y + ny * z);
                 for (int i = 0; i < Q; ++i) {
                     int64_t ys = y - CV[i][1];
-                    if (p->walls && (ys < 0 || ys >= ny)) {
+                    if (p->walls == 2 && (ys < 0 || ys >= ny)) {
+                        fout[i * N + n] = 0.0;
+                    } else if (p->walls && (ys < 0 || ys >= ny)) {
                         const double* uw = ys < 0 ? p->uw_lo : p->uw_hi;
                         double cu = CV[i][0] * uw[0] + CV[i][1] * uw[1] + CV[i][2] * uw[2];
                         fout[i * N + n] = fs[opposite(i) * N + n] + 6.0 * WT[i] * 1.0 * cu;
@@ -249,7 +321,9 @@ void orc_unstream(const orc_params* p, const double* f, double* fs) {
                 int64_t n = x + nx * (y + ny * z);
                 for (int i = 0; i < Q; ++i) {
                     int64_t ys = y - CV[i][1];
-                    if (p->walls && (ys < 0 || ys >= ny)) {
+                    if (p->walls == 2 && (ys < 0 || ys >= ny)) {
+                        fs[opposite(i) * N + n] = 0.0; /* leaves through the wall: not used */
+                    } else if (p->walls && (ys < 0 || ys >= ny)) {
                         const double* uw = ys < 0 ? p->uw_lo : p->uw_hi;
                         double cu = CV[i][0] * uw[0] + CV[i][1] * uw[1] + CV[i][2] * uw[2];
                         fs[opposite(i) * N + n] = f[i * N + n] - 6.0 * WT[i] * 1.0 * cu;
@@ -344,10 +418,11 @@ void orc_wall_stress(const orc_params* p, const double* f, const double* g, doub
         for (int64_t z = 0; z < nz; ++z)
             for (int64_t x = 0; x < nx; ++x) {
                 int64_t n = x + nx * (y + ny * z);
-                double r = 0.0, j[3] = {0, 0, 0}, F[3], v[3], feq[Q];
+                double r = 0.0, j[3] = {0, 0, 0}, F[3], v[3], feq[Q], fn[Q];
+                node_populations(p, f, g, n, y, fn);
                 for (int i = 0; i < Q; ++i) {
-                    r += f[i * N + n];
-                    for (int d = 0; d < 3; ++d) j[d] += CV[i][d] * f[i * N + n];
+                    r += fn[i];
+                    for (int d = 0; d < 3; ++d) j[d] += CV[i][d] * fn[i];
                 }
                 for (int d = 0; d < 3; ++d) {
                     F[d] = p->body[d] + (g ? g[d * N + n] : 0.0);
@@ -358,7 +433,7 @@ void orc_wall_stress(const orc_params* p, const double* f, const double* g, doub
                 for (int q = 0; q < 2; ++q) {
                     int a = comps[q], b = 1;
                     double s = 0.0;
-                    for (int i = 0; i < Q; ++i) s += (double)CV[i][a] * CV[i][b] * (f[i * N + n] - feq[i]);
+                    for (int i = 0; i < Q; ++i) s += (double)CV[i][a] * CV[i][b] * (fn[i] - feq[i]);
                     out[q * nz * nx + z * nx + x] = -k * s - k * 0.5 * (F[a] * v[b] + F[b] * v[a]);
                 }
             }

@@ -56,6 +56,7 @@ def lib():
         L.orc_set_threads.argtypes = [C.c_int32]
         L.orc_init.argtypes = [pp, dp, dp, dp]
         L.orc_moments.argtypes = [pp, dp, dp, dp, dp]
+        L.orc_complete.argtypes = [pp, dp, dp, dp]
         L.orc_step.argtypes = [pp, dp, dp, dp]
         L.orc_collide.argtypes = [pp, dp, dp, dp]
         L.orc_stream.argtypes = [pp, dp, dp]
@@ -139,15 +140,30 @@ def lattice_timestep(tau, h, mu, rho):
 
 
 # ----------------------------------------------------------------- lattice object
+def wall_mode(walls) -> int:
+    """0 = periodic in y, 1 = halfway bounce-back walls (R4), 2 = on-site walls on the
+    rows y = 0 and ny-1 (Eq. 23-30, R22).  True means 1; "onsite" means 2."""
+    if walls == "onsite":
+        return 2
+    if walls is True or walls is False:
+        return int(walls)
+    if walls in (0, 1, 2):
+        return int(walls)
+    raise ValueError(f"walls must be False, True, 'onsite' or 0/1/2, not {walls!r}")
+
+
 class Lattice:
     """One channel: populations f[19][nz][ny][nx] (paper order) and the IB force field
-    g[3][nz][ny][nx], both FP64.  Methods follow the per-step order of Fig. 1."""
+    g[3][nz][ny][nx], both FP64.  Methods follow the per-step order of Fig. 1.  With
+    on-site walls the populations entering at a wall row are not stored (they read as 0
+    in ``f``); ``populations()`` gives the state with them set by Eq. (23)-(30)."""
 
     def __init__(self, nx, ny, nz, tau, walls=True, body=(0, 0, 0), u_wall_lo=(0, 0, 0),
                  u_wall_hi=(0, 0, 0), kernel="cos"):
         self.shape = (nz, ny, nx)
         self.N = nx * ny * nz
-        self.p = _Params(nx, ny, nz, 1 if walls else 0, float(tau), (C.c_double * 3)(*body),
+        self.walls = wall_mode(walls)
+        self.p = _Params(nx, ny, nz, self.walls, float(tau), (C.c_double * 3)(*body),
                          (C.c_double * 3)(*u_wall_lo), (C.c_double * 3)(*u_wall_hi))
         self.kernel = KERNELS[kernel]
         self.f = np.zeros((19, nz, ny, nx))
@@ -161,9 +177,10 @@ class Lattice:
         lib().orc_init(C.byref(self.p), _d(self.f), _d(_f64(rho)), _d(_f64(u)))
 
     def shear_profile(self):
-        """Linear profile between the two walls (planes y=-1/2 and y=ny-1/2)."""
+        """Linear profile between the two walls (planes y=-1/2 and y=ny-1/2; rows 0 and
+        ny-1 with on-site walls)."""
         nz, ny, nx = self.shape
-        s = (np.arange(ny) + 0.5) / ny
+        s = np.arange(ny) / (ny - 1) if self.walls == 2 else (np.arange(ny) + 0.5) / ny
         lo, hi = np.array(self.p.uw_lo[:]), np.array(self.p.uw_hi[:])
         u = lo[:, None] + (hi - lo)[:, None] * s[None, :]
         return np.ascontiguousarray(np.broadcast_to(u[:, None, :, None], (3, nz, ny, nx)))
@@ -191,6 +208,13 @@ class Lattice:
         fs = np.empty_like(f)
         lib().orc_unstream(C.byref(self.p), _d(f), _d(fs))
         return fs
+
+    def populations(self):
+        """The pre-collision populations the next step reads: ``f`` with the on-site wall
+        rule applied at the wall rows (a copy of ``f`` otherwise)."""
+        fc = np.empty_like(self.f)
+        lib().orc_complete(C.byref(self.p), _d(self.f), _d(self.g), _d(fc))
+        return fc
 
     def moments(self):
         rho = np.empty(self.shape)

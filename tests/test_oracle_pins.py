@@ -148,6 +148,84 @@ def test_poiseuille_steady_state_exact(orc):
         assert np.abs(v[0, 0, :, 0] - ex).max() < 1e-12 * ex.max() * 1e3
 
 
+def test_onsite_couette_steady_state_exact(orc):
+    """On-site walls (Eq. 23-30) on rows 0 and ny-1, both walls moving (x and z):
+    u(y) = u_lo + (u_hi - u_lo) y / (ny - 1) exactly, rho = 1."""
+    for tau in (0.8, 1.3):
+        ny, lo, hi = 9, np.array([-0.01, 0, 0.0]), np.array([0.05, 0, 0.02])
+        L = orc.Lattice(2, ny, 2, tau, walls="onsite", u_wall_lo=tuple(lo), u_wall_hi=tuple(hi))
+        L.init()
+        L.step(int(40 * ny * ny / ((tau - 0.5) / 3)))
+        rho, v = L.moments()
+        y = np.arange(ny)
+        for d in (0, 2):
+            assert np.abs(v[d, 0, :, 0] - (lo[d] + (hi[d] - lo[d]) * y / (ny - 1))).max() < 1e-14
+        assert np.abs(v[1]).max() < 1e-14
+        assert np.abs(rho - 1).max() < 1e-12
+        # sigma_xy = rho nu du/dy at both wall rows
+        wlo, whi = L.wall_stress()
+        nu = (tau - 0.5) / 3
+        sxy = nu * (hi[0] - lo[0]) / (ny - 1)
+        assert np.abs(wlo[0] - sxy).max() < 1e-12 and np.abs(whi[0] - sxy).max() < 1e-12
+
+
+def test_onsite_poiseuille_steady_state_exact(orc):
+    """Body-force channel with on-site walls: u_x = g/(2 nu) y (H - y), H = ny - 1, with no
+    slip term at any tau.  Reading R22 (the imposed momentum is rho v_w - F/2) is what
+    makes the wall node move with the wall; the printed rule without it slips by g/2."""
+    for tau in (0.6, 0.8, 1.2):
+        ny, g = 12, 1e-5
+        L = orc.Lattice(1, ny, 1, tau, walls="onsite", body=(g, 0, 0))
+        L.init()
+        nu = (tau - 0.5) / 3
+        L.step(int(60 * ny * ny / nu))
+        _, v = L.moments()
+        y = np.arange(ny)
+        ex = g / (2 * nu) * y * (ny - 1 - y)
+        assert np.abs(v[0, 0, :, 0] - ex).max() < 2e-11 * ex.max()
+
+
+def test_onsite_wall_node_moves_with_the_wall(orc):
+    """Any state, any force: after the rule of Eq. (23)-(30) the velocity (sum c f + F/2)/rho
+    of every wall-row node equals that wall's velocity, including a normal component;
+    the populations leaving through the wall and those parallel to it are untouched."""
+    rng = np.random.default_rng(11)
+    nx, ny, nz = 5, 7, 4
+    lo, hi = (0.02, 0.01, -0.03), (-0.04, -0.015, 0.05)
+    L = orc.Lattice(nx, ny, nz, 0.9, walls="onsite", body=(1e-4, -2e-5, 3e-5), u_wall_lo=lo, u_wall_hi=hi)
+    L.init(u=0.02 * rng.standard_normal((3, nz, ny, nx)), rho=1 + 0.01 * rng.standard_normal((nz, ny, nx)))
+    L.f *= 1 + 0.05 * rng.standard_normal(L.f.shape)  # off equilibrium
+    L.g = 1e-3 * rng.standard_normal(L.g.shape)
+    _, v = L.moments()
+    assert np.abs(v[:, :, 0, :] - np.array(lo)[:, None, None]).max() < 1e-15
+    assert np.abs(v[:, :, ny - 1, :] - np.array(hi)[:, None, None]).max() < 1e-15
+    fc = L.populations()
+    c, _, _ = orc.tables()
+    enter_lo = c[:, 1] == 1
+    enter_hi = c[:, 1] == -1
+    assert np.array_equal(fc[~enter_lo][:, :, 0, :], L.f[~enter_lo][:, :, 0, :])
+    assert np.array_equal(fc[~enter_hi][:, :, ny - 1, :], L.f[~enter_hi][:, :, ny - 1, :])
+    assert np.array_equal(fc[:, :, 1:ny - 1, :], L.f[:, :, 1:ny - 1, :])
+
+
+def test_onsite_rule_keeps_a_wall_equilibrium(orc):
+    """With no force, a wall row at equilibrium f^eq(rho, v_w) (Eq. 20) is a fixed point of
+    the rule: the unknowns it produces are the equilibrium values, for any rho."""
+    rng = np.random.default_rng(12)
+    nx, ny, nz = 4, 5, 3
+    lo, hi = (0.03, 0.02, -0.01), (-0.02, -0.01, 0.04)
+    L = orc.Lattice(nx, ny, nz, 0.8, walls="onsite", u_wall_lo=lo, u_wall_hi=hi)
+    u = np.zeros((3, nz, ny, nx))
+    u[:, :, 0, :] = np.array(lo)[:, None, None]
+    u[:, :, ny - 1, :] = np.array(hi)[:, None, None]
+    L.init(u=u, rho=1 + 0.05 * rng.standard_normal((nz, ny, nx)))
+    f0 = L.f.copy()
+    c, _, _ = orc.tables()
+    L.f[np.ix_(c[:, 1] == 1, range(nz), [0], range(nx))] = 0.0
+    L.f[np.ix_(c[:, 1] == -1, range(nz), [ny - 1], range(nx))] = 0.0
+    assert np.abs(L.populations() - f0).max() < 1e-15
+
+
 def test_shear_wave_decay(orc):
     """Periodic box, u_x = A sin(2 pi y / L): decays as exp(-nu k^2 t), nu = (tau - 1/2)/3."""
     Ly, tau, A = 64, 0.8, 1e-4
