@@ -10,7 +10,9 @@
  * Conventions shared by every call
  *   Units        lattice units: h = dt = rho_0 = 1.
  *   Geometry     x and z periodic; y bounded by two walls (halfway bounce-back) at the
- *                planes y = -1/2 and y = ny - 1/2 when `walls` = 1, periodic when 0.
+ *                planes y = -1/2 and y = ny - 1/2 when `walls` = 1; by the on-site
+ *                velocity walls of Eq. (23)-(30) on the rows y = 0 and y = ny - 1 when
+ *                `walls` = 2; periodic when 0.
  *   Numbering    D3Q19 directions in the paper's order i = 1..19 (stored 0..18), the
  *                order fixed by the on-site wall equations Eq. (23)-(30).
  *   Layout       SoA, x fastest: cell n = x + nx*(y + ny*z).  Per-cell fields of all
@@ -65,7 +67,8 @@ typedef enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2 } lbm_st
 typedef enum { IB_PHI_COS4 = 0, IB_PHI_PESKIN4 = 1 } ib_kernel;
 
 /* Error bits reported by lbm_error_flags(). */
-#define LBM_FLAG_NODE_OUTSIDE 0x1u  /* an IB node's y fell outside [-1, ny) (or was not finite) */
+#define LBM_FLAG_NODE_OUTSIDE 0x1u  /* an IB node's y fell outside [-1, ny) ([0, ny-1] with on-site
+                                       walls), or was not finite */
 #define LBM_FLAG_LIST_OVERFLOW 0x2u /* IB tile lists exceeded their capacity (contributions lost) */
 #define LBM_FLAG_FORCE_NONFINITE 0x4u /* a Lagrangian force was Inf/NaN (force field set to NaN) */
 #define LBM_FLAG_CLOSURE_FALLBACK 0x8u /* the learned closure fell back to plain BGK at some node */
@@ -75,11 +78,16 @@ typedef enum { IB_PHI_COS4 = 0, IB_PHI_PESKIN4 = 1 } ib_kernel;
  * force in Eq. (19), wall velocities of the two y-walls. */
 typedef struct {
     int32_t nx, ny, nz; /* >= 1 each; the IB calls need nx, nz >= 4 */
-    int32_t walls;      /* 1 = bounce-back walls normal to y, 0 = periodic in y */
+    int32_t walls;      /* 1 = bounce-back walls normal to y (planes y = -1/2, ny - 1/2);
+                           2 = on-site velocity walls on rows 0 and ny-1 (Eq. (23)-(30), turned
+                           to a y-normal wall; ny >= 3): the populations entering a wall row
+                           are set so that its velocity (sum c f + F/2)/rho equals the wall's,
+                           i.e. the imposed momentum is rho u_w - F/2; 0 = periodic in y.
+                           lbm_restrict and closure_targets reject 2 (LBM_ERR_UNSUPPORTED). */
     float tau;          /* > 0.5 */
     float body_force[3];
-    float u_wall_lo[3]; /* velocity of the wall at y = -1/2; y component must be 0 */
-    float u_wall_hi[3]; /* velocity of the wall at y = ny - 1/2; y component must be 0 */
+    float u_wall_lo[3]; /* velocity of the lower wall (y = -1/2; row 0 on-site); y component 0 */
+    float u_wall_hi[3]; /* velocity of the upper wall (y = ny - 1/2; row ny-1 on-site); y component 0 */
 } lbm_params;
 
 /* Bytes of device workspace for `nch` channels with the given storage and room for up to
@@ -99,13 +107,15 @@ lbm_status lbm_destroy(lbm_ctx* ctx);
 
 /* f(x, 0) = f^eq(rho, u) of Eq. (20) at every cell.  rho: [cells] or NULL (rho = 1);
  * u: [3][cells] per channel or NULL, meaning the steady wall-driven profile
- * u(y) = u_lo + (u_hi - u_lo) (y + 1/2) / ny with walls (zero without walls). */
+ * u(y) = u_lo + (u_hi - u_lo) (y + 1/2) / ny with walls, u_lo + (u_hi - u_lo) y / (ny - 1)
+ * with on-site walls (zero without walls). */
 lbm_status lbm_init(lbm_ctx* ctx, const float* rho, const float* u);
 
 /* `nsteps` lattice-Boltzmann steps (section 3.3): collide with BGK (Eq. (16)) and the Guo
  * force term (Eq. (19), with the sign of the c_s^2 I term read as minus) using the force
  * F = body_force + g, g the field of the last ib_spread (zero if none), then stream with
- * halfway bounce-back (moving-wall term 6 w_i c_i.u_w) at the y-walls. */
+ * halfway bounce-back (moving-wall term 6 w_i c_i.u_w) at the y-walls, or with the on-site
+ * rule of Eq. (23)-(30) at the wall rows (walls = 2). */
 lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps);
 
 /* Declare the Lagrangian nodes: n in total (<= max_nodes), node_offsets = host array of
@@ -134,7 +144,9 @@ lbm_status ib_advance(lbm_ctx* ctx, int64_t n, double* X, const float* U);
 lbm_status lbm_moments(lbm_ctx* ctx, float* drho, float* v);
 
 /* Current pre-collision populations f_i (not shifted), paper order, [19][cells] per
- * channel, float32.  lbm_set_populations takes the same layout and replaces the state. */
+ * channel, float32.  lbm_set_populations takes the same layout and replaces the state.
+ * With on-site walls the populations entering a wall row are those of the wall rule (with
+ * the current force); lbm_set_populations ignores them there. */
 lbm_status lbm_get_populations(lbm_ctx* ctx, float* f);
 lbm_status lbm_set_populations(lbm_ctx* ctx, const float* f);
 

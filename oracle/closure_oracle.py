@@ -192,10 +192,12 @@ def correction(f, g, body, theta, norm, c_guard=1.0, bf16=False):
 
 def closure_step(lat, theta, norm, c_guard=1.0, bf16=False):
     """One step of the coarse lattice with the learned closure: collide (Eq. 16, 19, 20),
-    add the guarded correction, stream.  Returns the number of guarded nodes."""
+    add the guarded correction, stream.  Returns the number of guarded nodes.  The
+    features are those of the populations the step reads (with on-site walls, the wall
+    rows' entering populations set by Eq. (23)-(30))."""
     fs = lat.collide()
     body = np.array(lat.p.body[:])
-    dF, nrej = correction(lat.f, lat.g, body, theta, norm, c_guard, bf16)
+    dF, nrej = correction(lat.populations(), lat.g, body, theta, norm, c_guard, bf16)
     lat.stream_from(fs + dF.reshape(fs.shape))
     return nrej
 

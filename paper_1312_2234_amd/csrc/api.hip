@@ -24,7 +24,8 @@ bool valid_params(const lbm_params* p, int32_t nch) {
         if (q.nx < 1 || q.ny < 1 || q.nz < 1) return false;
         if ((int64_t)q.nx * q.ny * q.nz >= (int64_t(1) << 31)) return false;
         if (!(q.tau > 0.5f) || !(q.tau < 1e6f)) return false;
-        if (q.walls != 0 && q.walls != 1) return false;
+        if (q.walls < 0 || q.walls > 2) return false;
+        if (q.walls == 2 && q.ny < 3) return false;  // two wall rows and at least one fluid row
         if (q.u_wall_lo[1] != 0.0f || q.u_wall_hi[1] != 0.0f) return false;
     }
     return true;
@@ -727,6 +728,7 @@ lbm_status lbm_restrict(lbm_ctx* c, float tau_coarse, float* g_c, float* F_c) {
     if (c->nch != 1) return LBM_ERR_UNSUPPORTED;
     const lbm_params& p = c->params[0];
     if ((p.nx & 1) || (p.ny & 1) || (p.nz & 1)) return LBM_ERR_UNSUPPORTED;
+    if (p.walls == 2) return LBM_ERR_UNSUPPORTED;  // 2x2x2 blocks align with halfway walls only
     LatArgs a = lat_args(c);
     return hip_ok(launch_restrict(c, a, 2.0f * tau_coarse / p.tau, g_c, F_c));
 }
@@ -734,6 +736,7 @@ lbm_status lbm_restrict(lbm_ctx* c, float tau_coarse, float* g_c, float* F_c) {
 lbm_status closure_targets(const lbm_params* coarse, const float* g0, const float* F, const float* g1, float* feat,
                            float* target, void* stream) {
     if (!valid_params(coarse, 1) || !g0 || !F || !g1 || !feat || !target) return LBM_ERR_ARG;
+    if (coarse->walls == 2) return LBM_ERR_UNSUPPORTED;  // coarse-graining assumes halfway walls
     Chan ch;
     memset(&ch, 0, sizeof(ch));
     ch.nx = coarse->nx;

@@ -340,8 +340,9 @@ __global__ void __launch_bounds__(256, 3) k_step_cl(LatArgs a, const MlpPacked* 
             cell_xyz(ch, (uint32_t)n, x, y, z);
             pull<St>((const T*)a.src + ch.pop_off, ch, ch.ncell, n, x, y, z, g);
             float drho, jx, jy, jz, Fx, Fy, Fz;
-            moments(g, drho, jx, jy, jz);
             ib_force(a, ch, x, y, z, Fx, Fy, Fz);
+            onsite_wall(ch, y, g, Fx, Fy, Fz);
+            moments(g, drho, jx, jy, jz);
             cs = cell_state(drho, jx, jy, jz, Fx, Fy, Fz);
             float d[Q], m[MLP_NNC];
 #pragma unroll

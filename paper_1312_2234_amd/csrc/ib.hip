@@ -168,7 +168,8 @@ __device__ __forceinline__ void bin_block(const IbArgs& a, int64_t blk, bool wit
                 w[d][0] = w[d][1] = w[d][2] = w[d][3] = 0.0f;
             }
             if (d == 1 && ch.walls) {
-                if (base < -2 || base > ch.ny - 2) bad = true;  // node outside y in [-1, ny)
+                // node outside the channel: y outside [-1, ny), or [0, ny-1] with on-site walls
+                if (ch.walls == 2 ? (X < 0.0 || X > ch.ny - 1.0) : (base < -2 || base > ch.ny - 2)) bad = true;
                 if (base < -4) base = -4;
                 if (base > ch.ny) base = ch.ny;
                 b[d] = (int)base;
@@ -539,6 +540,7 @@ __global__ void __launch_bounds__(SP_THREADS) k_spread_far(IbArgs a, LatArgs la,
     T* dst = (T*)la.dst + ch.pop_off;
     float g[Q];
     pull<St>(src, ch, ch.ncell, n, x, y, z, g);
+    onsite_wall(ch, y, g, ch.body[0], ch.body[1], ch.body[2]);
     float drho, jx, jy, jz;
     moments(g, drho, jx, jy, jz);
     const CellState cs = cell_state(drho, jx, jy, jz, ch.body[0], ch.body[1], ch.body[2]);
@@ -647,12 +649,13 @@ __global__ void __launch_bounds__(512) k_ib_vel(IbArgs a) {
             const int32_t n = x + ch.nx * (y + ch.ny * z);
             float g[Q];
             pull<St>((const T*)a.pop + ch.pop_off, ch, ch.ncell, n, x, y, z, g);
+            const float Fx = ch.body[0] + fb[l], Fy = ch.body[1] + fb[TILE_CELLS + l],
+                        Fz = ch.body[2] + fb[2 * TILE_CELLS + l];
+            onsite_wall(ch, y, g, Fx, Fy, Fz);
             float drho, jx, jy, jz;
             moments(g, drho, jx, jy, jz);
             const float ir = 1.0f / (1.0f + drho);
-            vb[l] = make_float4((jx + 0.5f * (ch.body[0] + fb[l])) * ir,
-                                (jy + 0.5f * (ch.body[1] + fb[TILE_CELLS + l])) * ir,
-                                (jz + 0.5f * (ch.body[2] + fb[2 * TILE_CELLS + l])) * ir, 0.0f);
+            vb[l] = make_float4((jx + 0.5f * Fx) * ir, (jy + 0.5f * Fy) * ir, (jz + 0.5f * Fz) * ir, 0.0f);
         }
     }
 }
@@ -754,6 +757,7 @@ __global__ void __launch_bounds__(256) k_ib_gather(IbArgs a) {
                     const int32_t n = x + ch.nx * (y + ch.ny * z);
                     float g[Q];
                     pull<St>((const T*)a.pop + ch.pop_off, ch, ch.ncell, n, x, y, z, g);
+                    onsite_wall(ch, y, g, ch.body[0], ch.body[1], ch.body[2]);
                     float drho, jx, jy, jz;
                     moments(g, drho, jx, jy, jz);
                     const float ir = 1.0f / (1.0f + drho);

@@ -30,8 +30,9 @@ __global__ void __launch_bounds__(1024) k_step(LatArgs a) {
         float g[Q];
         pull<St>(s, ch, N, n, x, y, z, g);
         float drho, jx, jy, jz, Fx, Fy, Fz;
-        moments(g, drho, jx, jy, jz);
         ib_force(a, ch, x, y, z, Fx, Fy, Fz);
+        onsite_wall(ch, y, g, Fx, Fy, Fz);
+        moments(g, drho, jx, jy, jz);
         const CellState cs = cell_state(drho, jx, jy, jz, Fx, Fy, Fz);
         const float om = ch.omega, guo = ch.guo;
 #pragma unroll
@@ -91,7 +92,6 @@ __global__ void __launch_bounds__(TILE_CELLS) k_step_tiles(LatArgs a) {
         float g[Q];
         pull<St>(s, ch, ch.ncell, n, x, y, z, g);
         float drho, jx, jy, jz, Fx, Fy, Fz;
-        moments(g, drho, jx, jy, jz);
         // the body force plus this tile's IB force, as ib_force adds them
         Fx = ch.body[0];
         Fy = ch.body[1];
@@ -99,6 +99,8 @@ __global__ void __launch_bounds__(TILE_CELLS) k_step_tiles(LatArgs a) {
         Fx += f3[0];
         Fy += f3[1];
         Fz += f3[2];
+        onsite_wall(ch, y, g, Fx, Fy, Fz);
+        moments(g, drho, jx, jy, jz);
         const CellState cs = cell_state(drho, jx, jy, jz, Fx, Fy, Fz);
         const float om = ch.omega, guo = ch.guo;
 #pragma unroll
@@ -195,6 +197,11 @@ __global__ void __launch_bounds__(256) k_step_v(LatArgs a) {
             float gk[Q];
 #pragma unroll
             for (int i = 0; i < Q; ++i) gk[i] = g[i][k];
+            if (ch.walls == 2 && (y == 0 || y == ny - 1)) {
+                onsite_wall(ch, y, gk, Fx[k], Fy[k], Fz[k]);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) g[i][k] = gk[i];
+            }
             float drho, jx, jy, jz;
             moments(gk, drho, jx, jy, jz);
             cs[k] = cell_state(drho, jx, jy, jz, Fx[k], Fy[k], Fz[k]);
@@ -249,8 +256,10 @@ __global__ void __launch_bounds__(1024) k_init(LatArgs a) {
                 uy = u[N + m];
                 uz = u[2 * N + m];
             } else if (ch.walls) {
+                // steady wall-driven profile: walls at y = -1/2 and ny - 1/2, or on the rows
+                // 0 and ny-1 (on-site walls)
                 const int ym = (int)((m / ch.nx) % ch.ny);
-                const float s = ((float)ym + 0.5f) / (float)ch.ny;
+                const float s = ch.walls == 2 ? (float)ym / (float)(ch.ny - 1) : ((float)ym + 0.5f) / (float)ch.ny;
                 ux = ch.uw_lo[0] + (ch.uw_hi[0] - ch.uw_lo[0]) * s;
                 uy = 0.0f;
                 uz = ch.uw_lo[2] + (ch.uw_hi[2] - ch.uw_lo[2]) * s;
@@ -288,8 +297,9 @@ __global__ void __launch_bounds__(1024) k_moments(LatArgs a) {
         float g[Q];
         pull<St>((const T*)a.src + ch.pop_off, ch, N, n, x, y, z, g);
         float drho, jx, jy, jz, Fx, Fy, Fz;
-        moments(g, drho, jx, jy, jz);
         ib_force(a, ch, x, y, z, Fx, Fy, Fz);
+        onsite_wall(ch, y, g, Fx, Fy, Fz);
+        moments(g, drho, jx, jy, jz);
         const float ir = 1.0f / (1.0f + drho);
         if (a.out_rho) a.out_rho[ch.cell_off + n] = drho;
         if (a.out_v) {
@@ -310,6 +320,11 @@ __global__ void __launch_bounds__(1024) k_getf(LatArgs a) {
         const int64_t N = ch.ncell;
         float g[Q];
         pull<St>((const T*)a.src + ch.pop_off, ch, N, n, x, y, z, g);
+        if (ch.walls == 2) {
+            float Fx, Fy, Fz;
+            ib_force(a, ch, x, y, z, Fx, Fy, Fz);
+            onsite_wall(ch, y, g, Fx, Fy, Fz);
+        }
         float* f = a.out_f + (int64_t)Q * ch.cell_off;
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[(int64_t)i * N + n] = g[i] + wgt(i);
@@ -337,8 +352,9 @@ __global__ void __launch_bounds__(256) k_wss(LatArgs a, int nch, int64_t total) 
     float g[Q];
     pull<St>((const T*)a.src + ch.pop_off, ch, N, n, x, y, z, g);
     float drho, jx, jy, jz, Fx, Fy, Fz;
-    moments(g, drho, jx, jy, jz);
     ib_force(a, ch, x, y, z, Fx, Fy, Fz);
+    onsite_wall(ch, y, g, Fx, Fy, Fz);
+    moments(g, drho, jx, jy, jz);
     const float rho = 1.0f + drho, ir = 1.0f / rho;
     const float vx = (jx + 0.5f * Fx) * ir, vy = (jy + 0.5f * Fy) * ir, vz = (jz + 0.5f * Fz) * ir;
     float sxy = 0.f, szy = 0.f;

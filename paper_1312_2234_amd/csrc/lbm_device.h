@@ -132,7 +132,9 @@ __device__ __forceinline__ void stv(typename St::T* p, const float in[V]) {
 // Populations arriving at cell n = (x, y, z) of the current step: f_i(x) = f*_i(x - c_i)
 // with x, z periodic; when x - c_i lies beyond a y-wall the halfway bounce-back gives
 // f_i(x) = f*_opp(i)(x) + 6 w_i c_i.u_w.  In the shifted variables the same relation
-// holds for g = f - w because w_i = w_opp(i).  `s` points at the channel's block.
+// holds for g = f - w because w_i = w_opp(i).  `s` points at the channel's block.  With
+// on-site walls the entering populations of a wall row are loaded the same way and then
+// replaced by onsite_wall().
 template <class St>
 __device__ __forceinline__ void pull(const typename St::T* __restrict__ s, const Chan& ch, int64_t N,
                                      int32_t n, int x, int y, int z, float g[Q]) {
@@ -161,6 +163,51 @@ __device__ __forceinline__ void pull(const typename St::T* __restrict__ s, const
         }
         g[i] = v;
     }
+}
+
+// On-site velocity walls (Chan::walls == 2; Eq. (23)-(30), turned to a y-normal wall).  The
+// walls lie on the rows y = 0 and y = ny-1; there the populations entering the fluid
+// (c.n = +1 for the inward normal n = +y on row 0, -y on row ny-1) have no source cell and
+// are set from the others so that the cell's velocity (sum c f + F/2)/rho is the wall's.
+// With J = rho u_w - F/2 (F the cell's force):
+//   rho (1 - n.u_w) = sum_{c.n=0} f + 2 sum_{c.n=-1} f - n.F/2
+//   N_t = sum_{c.n=0} c_t f / 2 - J_t / 3          (t = x, z)
+//   f_i = f_opp(i) + 6 w_i c_i.J - sum_t c_it N_t   (c_i.n = +1)
+// In the shifted variables g = f - w the weights drop out: those of c.n = 0 plus twice those
+// of c.n = -1 sum to 1, the c.n = 0 ones are symmetric in c_t, and w_i = w_opp(i); so
+// rho - 1 = (S_0 + 2 S_- - n.F/2 + n.u_w) / (1 - n.u_w) over the shifted sums S.
+template <int S>
+__device__ __forceinline__ void onsite_rows(const float* u, float g[Q], float Fx, float Fy, float Fz) {
+    float s0 = 0.f, sm = 0.f, px = 0.f, pz = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (cy(i) == 0) {
+            s0 += g[i];
+            if (cx(i)) px += cx(i) * g[i];
+            if (cz(i)) pz += cz(i) * g[i];
+        } else if (cy(i) == -S) {
+            sm += g[i];
+        }
+    }
+    const float un = S * u[1];
+    const float drho = (s0 + 2.0f * sm - 0.5f * S * Fy + un) / (1.0f - un);
+    const float rho = 1.0f + drho;
+    const float Jx = rho * u[0] - 0.5f * Fx, Jy = rho * u[1] - 0.5f * Fy, Jz = rho * u[2] - 0.5f * Fz;
+    const float Nx = 0.5f * px - Jx * (1.0f / 3.0f), Nz = 0.5f * pz - Jz * (1.0f / 3.0f);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        if (cy(i) == S)
+            g[i] = g[opp(i)] + 6.0f * wgt(i) * (cx(i) * Jx + cy(i) * Jy + cz(i) * Jz) - (cx(i) * Nx + cz(i) * Nz);
+}
+
+// Applies the on-site rule to a pulled cell of row y (no-op for other rows and wall kinds).
+// Every kernel that reads the state calls it between the pull and the moments.
+__device__ __forceinline__ void onsite_wall(const Chan& ch, int y, float g[Q], float Fx, float Fy, float Fz) {
+    if (ch.walls != 2) return;
+    if (y == 0)
+        onsite_rows<1>(ch.uw_lo, g, Fx, Fy, Fz);
+    else if (y == ch.ny - 1)
+        onsite_rows<-1>(ch.uw_hi, g, Fx, Fy, Fz);
 }
 
 // Zeroth and first moments of the shifted populations: drho = sum g, j = sum c g

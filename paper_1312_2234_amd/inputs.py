@@ -247,7 +247,7 @@ class Channel:
     body: tuple = (0.0, 0.0, 0.0)
     u_wall_lo: tuple = (0.0, 0.0, 0.0)
     u_wall_hi: tuple = (0.0, 0.0, 0.0)
-    walls: bool = True
+    walls: bool | str = True      # False, True (halfway bounce-back) or "onsite" (Eq. 23-30)
     init: str = "rest"            # "rest" (u = 0) or "shear" (linear wall-driven profile)
     bodies: Bodies | None = None
 

@@ -135,9 +135,18 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def wall_code(walls) -> int:
+    """lbm_params.walls: False/0 periodic, True/1 halfway bounce-back, "onsite"/2 on-site walls."""
+    if walls == "onsite":
+        return 2
+    if walls is True or walls is False or walls in (0, 1, 2):
+        return int(walls)
+    raise ValueError(f"walls must be False, True, 'onsite' or 0/1/2, not {walls!r}")
+
+
 def params_of(ch) -> LbmParams:
     """lbm_params from an inputs.Channel (or any object with the same fields)."""
-    return LbmParams(ch.nx, ch.ny, ch.nz, 1 if ch.walls else 0, float(ch.tau), (C.c_float * 3)(*ch.body),
+    return LbmParams(ch.nx, ch.ny, ch.nz, wall_code(ch.walls), float(ch.tau), (C.c_float * 3)(*ch.body),
                      (C.c_float * 3)(*ch.u_wall_lo), (C.c_float * 3)(*ch.u_wall_hi))
 
 
