@@ -39,6 +39,14 @@ def make_workload(name):
         desc = ("shear channel 256x128x128, top wall u=0.05, tau=1.0, 16 oblate platelets "
                 "(6,2,6) x 2562 IB nodes, spring k=0.005 + bending 1e-4")
         return [ch], desc
+    if name == "shear_onsite":
+        import dataclasses
+
+        ch = dataclasses.replace(inputs.shear_platelets(seed=0), walls="onsite")
+        desc = ("shear channel 256x128x128 with on-site velocity walls (Eq. 23-30) on rows 0 and 127, "
+                "top wall u=0.05, tau=1.0, 16 oblate platelets (6,2,6) x 2562 IB nodes, spring k=0.005 + "
+                "bending 1e-4")
+        return [ch], desc
     if name == "batched":
         chans = inputs.batched_channels(seed=0)
         desc = ("64 independent shear channels, sizes uniform over {48x32x32, 64x48x48, 96x64x64, 128x64x64}, "

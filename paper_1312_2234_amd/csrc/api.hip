@@ -222,6 +222,7 @@ lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib
     c->max_nodes = max_nodes;
     c->stream = (hipStream_t)stream;
     c->params.assign(ch, ch + nch);
+    for (int q = 0; q < nch; ++q) c->onsite = c->onsite || ch[q].walls == 2;
     c->total_cells = sz.cells;
     c->total_segs = sz.segs;
     c->total_tiles = sz.tiles;

@@ -340,9 +340,12 @@ __global__ void __launch_bounds__(256, 3) k_step_cl(LatArgs a, const MlpPacked* 
             cell_xyz(ch, (uint32_t)n, x, y, z);
             pull<St>((const T*)a.src + ch.pop_off, ch, ch.ncell, n, x, y, z, g);
             float drho, jx, jy, jz, Fx, Fy, Fz;
-            ib_force(a, ch, x, y, z, Fx, Fy, Fz);
-            onsite_wall(ch, y, g, Fx, Fy, Fz);
             moments(g, drho, jx, jy, jz);
+            ib_force(a, ch, x, y, z, Fx, Fy, Fz);
+            if (St::onsite && onsite_row(ch, y)) {
+                onsite_wall(ch, y, g, Fx, Fy, Fz);
+                moments(g, drho, jx, jy, jz);
+            }
             cs = cell_state(drho, jx, jy, jz, Fx, Fy, Fz);
             float d[Q], m[MLP_NNC];
 #pragma unroll
@@ -804,12 +807,7 @@ static hipError_t step_cl_typed(lbm_ctx* c, const LatArgs& a) {
 }
 
 hipError_t launch_step_closure(lbm_ctx* c, const LatArgs& a) {
-    switch (c->storage) {
-        case LBM_STORE_F32: return step_cl_typed<StF32>(c, a);
-        case LBM_STORE_F16: return step_cl_typed<StF16>(c, a);
-        case LBM_STORE_BF16: return step_cl_typed<StBF16>(c, a);
-    }
-    return hipErrorInvalidValue;
+    return with_storage(c, [&](auto st) { return step_cl_typed<decltype(st)>(c, a); });
 }
 
 hipError_t launch_mlp_forward(hipStream_t s, const MlpPacked* P, const float* raw, int64_t B, float* dm,

@@ -540,7 +540,7 @@ __global__ void __launch_bounds__(SP_THREADS) k_spread_far(IbArgs a, LatArgs la,
     T* dst = (T*)la.dst + ch.pop_off;
     float g[Q];
     pull<St>(src, ch, ch.ncell, n, x, y, z, g);
-    onsite_wall(ch, y, g, ch.body[0], ch.body[1], ch.body[2]);
+    if (St::onsite && onsite_row(ch, y)) onsite_wall(ch, y, g, ch.body[0], ch.body[1], ch.body[2]);
     float drho, jx, jy, jz;
     moments(g, drho, jx, jy, jz);
     const CellState cs = cell_state(drho, jx, jy, jz, ch.body[0], ch.body[1], ch.body[2]);
@@ -568,11 +568,7 @@ hipError_t launch_spread_far(lbm_ctx* c, const IbArgs& a, const LatArgs& la) {
     int64_t gs = c->max_items < c->ib_grid ? c->max_items : c->ib_grid;
     if (gs < 1) gs = 1;
     const int64_t gl = (la.nseg + SP_THREADS / 64 - 1) / (SP_THREADS / 64);
-    switch (c->storage) {
-        case LBM_STORE_F32: launch_spread_far_typed<StF32>(c, a, la, gs, gl); break;
-        case LBM_STORE_F16: launch_spread_far_typed<StF16>(c, a, la, gs, gl); break;
-        case LBM_STORE_BF16: launch_spread_far_typed<StBF16>(c, a, la, gs, gl); break;
-    }
+    with_storage(c, [&](auto st) { launch_spread_far_typed<decltype(st)>(c, a, la, gs, gl); });
     return hipGetLastError();
 }
 
@@ -651,7 +647,7 @@ __global__ void __launch_bounds__(512) k_ib_vel(IbArgs a) {
             pull<St>((const T*)a.pop + ch.pop_off, ch, ch.ncell, n, x, y, z, g);
             const float Fx = ch.body[0] + fb[l], Fy = ch.body[1] + fb[TILE_CELLS + l],
                         Fz = ch.body[2] + fb[2 * TILE_CELLS + l];
-            onsite_wall(ch, y, g, Fx, Fy, Fz);
+            if (St::onsite && onsite_row(ch, y)) onsite_wall(ch, y, g, Fx, Fy, Fz);
             float drho, jx, jy, jz;
             moments(g, drho, jx, jy, jz);
             const float ir = 1.0f / (1.0f + drho);
@@ -757,7 +753,7 @@ __global__ void __launch_bounds__(256) k_ib_gather(IbArgs a) {
                     const int32_t n = x + ch.nx * (y + ch.ny * z);
                     float g[Q];
                     pull<St>((const T*)a.pop + ch.pop_off, ch, ch.ncell, n, x, y, z, g);
-                    onsite_wall(ch, y, g, ch.body[0], ch.body[1], ch.body[2]);
+                    if (St::onsite && onsite_row(ch, y)) onsite_wall(ch, y, g, ch.body[0], ch.body[1], ch.body[2]);
                     float drho, jx, jy, jz;
                     moments(g, drho, jx, jy, jz);
                     const float ir = 1.0f / (1.0f + drho);
@@ -794,11 +790,7 @@ static void launch_interp_typed(lbm_ctx* c, const IbArgs& a) {
 }
 
 hipError_t launch_ib_interp(lbm_ctx* c, const IbArgs& a) {
-    switch (c->storage) {
-        case LBM_STORE_F32: launch_interp_typed<StF32>(c, a); break;
-        case LBM_STORE_F16: launch_interp_typed<StF16>(c, a); break;
-        case LBM_STORE_BF16: launch_interp_typed<StBF16>(c, a); break;
-    }
+    with_storage(c, [&](auto st) { launch_interp_typed<decltype(st)>(c, a); });
     return hipGetLastError();
 }
 

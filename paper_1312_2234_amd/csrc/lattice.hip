@@ -30,9 +30,12 @@ __global__ void __launch_bounds__(1024) k_step(LatArgs a) {
         float g[Q];
         pull<St>(s, ch, N, n, x, y, z, g);
         float drho, jx, jy, jz, Fx, Fy, Fz;
-        ib_force(a, ch, x, y, z, Fx, Fy, Fz);
-        onsite_wall(ch, y, g, Fx, Fy, Fz);
         moments(g, drho, jx, jy, jz);
+        ib_force(a, ch, x, y, z, Fx, Fy, Fz);
+        if (St::onsite && onsite_row(ch, y)) {
+            onsite_wall(ch, y, g, Fx, Fy, Fz);
+            moments(g, drho, jx, jy, jz);
+        }
         const CellState cs = cell_state(drho, jx, jy, jz, Fx, Fy, Fz);
         const float om = ch.omega, guo = ch.guo;
 #pragma unroll
@@ -92,6 +95,7 @@ __global__ void __launch_bounds__(TILE_CELLS) k_step_tiles(LatArgs a) {
         float g[Q];
         pull<St>(s, ch, ch.ncell, n, x, y, z, g);
         float drho, jx, jy, jz, Fx, Fy, Fz;
+        moments(g, drho, jx, jy, jz);
         // the body force plus this tile's IB force, as ib_force adds them
         Fx = ch.body[0];
         Fy = ch.body[1];
@@ -99,8 +103,10 @@ __global__ void __launch_bounds__(TILE_CELLS) k_step_tiles(LatArgs a) {
         Fx += f3[0];
         Fy += f3[1];
         Fz += f3[2];
-        onsite_wall(ch, y, g, Fx, Fy, Fz);
-        moments(g, drho, jx, jy, jz);
+        if (St::onsite && onsite_row(ch, y)) {
+            onsite_wall(ch, y, g, Fx, Fy, Fz);
+            moments(g, drho, jx, jy, jz);
+        }
         const CellState cs = cell_state(drho, jx, jy, jz, Fx, Fy, Fz);
         const float om = ch.omega, guo = ch.guo;
 #pragma unroll
@@ -197,7 +203,7 @@ __global__ void __launch_bounds__(256) k_step_v(LatArgs a) {
             float gk[Q];
 #pragma unroll
             for (int i = 0; i < Q; ++i) gk[i] = g[i][k];
-            if (ch.walls == 2 && (y == 0 || y == ny - 1)) {
+            if (St::onsite && onsite_row(ch, y)) {
                 onsite_wall(ch, y, gk, Fx[k], Fy[k], Fz[k]);
 #pragma unroll
                 for (int i = 0; i < Q; ++i) g[i][k] = gk[i];
@@ -298,7 +304,7 @@ __global__ void __launch_bounds__(1024) k_moments(LatArgs a) {
         pull<St>((const T*)a.src + ch.pop_off, ch, N, n, x, y, z, g);
         float drho, jx, jy, jz, Fx, Fy, Fz;
         ib_force(a, ch, x, y, z, Fx, Fy, Fz);
-        onsite_wall(ch, y, g, Fx, Fy, Fz);
+        if (St::onsite && onsite_row(ch, y)) onsite_wall(ch, y, g, Fx, Fy, Fz);
         moments(g, drho, jx, jy, jz);
         const float ir = 1.0f / (1.0f + drho);
         if (a.out_rho) a.out_rho[ch.cell_off + n] = drho;
@@ -320,7 +326,7 @@ __global__ void __launch_bounds__(1024) k_getf(LatArgs a) {
         const int64_t N = ch.ncell;
         float g[Q];
         pull<St>((const T*)a.src + ch.pop_off, ch, N, n, x, y, z, g);
-        if (ch.walls == 2) {
+        if (St::onsite && onsite_row(ch, y)) {
             float Fx, Fy, Fz;
             ib_force(a, ch, x, y, z, Fx, Fy, Fz);
             onsite_wall(ch, y, g, Fx, Fy, Fz);
@@ -353,7 +359,7 @@ __global__ void __launch_bounds__(256) k_wss(LatArgs a, int nch, int64_t total) 
     pull<St>((const T*)a.src + ch.pop_off, ch, N, n, x, y, z, g);
     float drho, jx, jy, jz, Fx, Fy, Fz;
     ib_force(a, ch, x, y, z, Fx, Fy, Fz);
-    onsite_wall(ch, y, g, Fx, Fy, Fz);
+    if (St::onsite && onsite_row(ch, y)) onsite_wall(ch, y, g, Fx, Fy, Fz);
     moments(g, drho, jx, jy, jz);
     const float rho = 1.0f + drho, ir = 1.0f / rho;
     const float vx = (jx + 0.5f * Fx) * ir, vy = (jy + 0.5f * Fy) * ir, vz = (jz + 0.5f * Fz) * ir;
@@ -478,12 +484,7 @@ static hipError_t launch_wss_typed(lbm_ctx* c, const LatArgs& a, int64_t total) 
 }
 
 hipError_t launch_lattice(lbm_ctx* c, int which, const LatArgs& a) {
-    switch (c->storage) {
-        case LBM_STORE_F32: return launch_typed<StF32>(c, which, a);
-        case LBM_STORE_F16: return launch_typed<StF16>(c, which, a);
-        case LBM_STORE_BF16: return launch_typed<StBF16>(c, which, a);
-    }
-    return hipErrorInvalidValue;
+    return with_storage(c, [&](auto st) { return launch_typed<decltype(st)>(c, which, a); });
 }
 
 template <class St>
@@ -498,21 +499,12 @@ hipError_t launch_step_tiles(lbm_ctx* c, const LatArgs& a, bool merge) {
     int64_t g = c->max_slots < c->ib_grid ? c->max_slots : c->ib_grid;
     if (g < 1) g = 1;
     const dim3 grid((unsigned)g), block(TILE_CELLS);
-    switch (c->storage) {
-        case LBM_STORE_F32: launch_tiles_typed<StF32>(c, a, merge, grid, block); break;
-        case LBM_STORE_F16: launch_tiles_typed<StF16>(c, a, merge, grid, block); break;
-        case LBM_STORE_BF16: launch_tiles_typed<StBF16>(c, a, merge, grid, block); break;
-    }
+    with_storage(c, [&](auto st) { launch_tiles_typed<decltype(st)>(c, a, merge, grid, block); });
     return hipGetLastError();
 }
 
 hipError_t launch_wss(lbm_ctx* c, const LatArgs& a, int64_t total) {
-    switch (c->storage) {
-        case LBM_STORE_F32: return launch_wss_typed<StF32>(c, a, total);
-        case LBM_STORE_F16: return launch_wss_typed<StF16>(c, a, total);
-        case LBM_STORE_BF16: return launch_wss_typed<StBF16>(c, a, total);
-    }
-    return hipErrorInvalidValue;
+    return with_storage(c, [&](auto st) { return launch_wss_typed<decltype(st)>(c, a, total); });
 }
 
 }  // namespace lbmib

@@ -79,6 +79,7 @@ __device__ __forceinline__ void cell_xyz(const Chan& ch, uint32_t n, int& x, int
 
 // ---------------------------------------------------------------- storage codecs
 struct StF32 {
+    static constexpr bool onsite = false;  // no channel with on-site walls
     using T = float;
     static __device__ __forceinline__ float dec(T v) { return v; }
     static __device__ __forceinline__ T enc(float v) { return v; }
@@ -87,6 +88,7 @@ struct StF32 {
     static __device__ __forceinline__ void st_nt(T* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 struct StF16 {
+    static constexpr bool onsite = false;  // no channel with on-site walls
     using T = uint16_t;
     static __device__ __forceinline__ float dec(T v) { return __half2float(__ushort_as_half(v)); }
     static __device__ __forceinline__ float ld(const T* p) { return dec(*p); }
@@ -95,6 +97,7 @@ struct StF16 {
     static __device__ __forceinline__ void st_nt(T* p, float v) { __builtin_nontemporal_store(enc(v), p); }
 };
 struct StBF16 {
+    static constexpr bool onsite = false;  // no channel with on-site walls
     using T = uint16_t;
     static __device__ __forceinline__ float dec(T v) { return __uint_as_float((uint32_t)v << 16); }
     static __device__ __forceinline__ float ld(const T* p) { return dec(*p); }
@@ -104,6 +107,13 @@ struct StBF16 {
     static __device__ __forceinline__ uint16_t enc(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
     static __device__ __forceinline__ void st(T* p, float v) { *p = enc(v); }
     static __device__ __forceinline__ void st_nt(T* p, float v) { __builtin_nontemporal_store(enc(v), p); }
+};
+
+// The same storage form for a context with at least one on-site-wall channel: the kernels
+// compile their wall-row branch only for these, so the others keep the plain code.
+template <class Base>
+struct OnSite : Base {
+    static constexpr bool onsite = true;
 };
 
 // V consecutive stored elements (address aligned to V elements) <-> floats.
@@ -176,8 +186,26 @@ __device__ __forceinline__ void pull(const typename St::T* __restrict__ s, const
 // In the shifted variables g = f - w the weights drop out: those of c.n = 0 plus twice those
 // of c.n = -1 sum to 1, the c.n = 0 ones are symmetric in c_t, and w_i = w_opp(i); so
 // rho - 1 = (S_0 + 2 S_- - n.F/2 + n.u_w) / (1 - n.u_w) over the shifted sums S.
-template <int S>
-__device__ __forceinline__ void onsite_rows(const float* u, float g[Q], float Fx, float Fy, float Fz) {
+//
+// The kernels compile the wall-row branch only for the OnSite<> storage forms (contexts
+// with an on-site-wall channel), take the moments of the pull first, so that the loads of
+// the cell's force overlap them, and on a wall row apply the rule and take the moments again.
+
+// True on the wall rows of a channel with on-site walls.
+__device__ __forceinline__ bool onsite_row(const Chan& ch, int y) {
+    return ch.walls == 2 && (y == 0 || y == ch.ny - 1);
+}
+
+// Applies the on-site rule to a pulled cell of a wall row (onsite_row true).  One body serves both walls:
+// every array index is a compile-time constant and the wall only selects values (two
+// inlined copies chosen at run time get merged by the compiler into stores at a selected
+// index, which moves the array to scratch memory).
+__device__ __forceinline__ void onsite_wall(const Chan& ch, int y, float g[Q], float Fx, float Fy, float Fz) {
+    const bool lo = y == 0;  // inward normal +y on row 0, -y on row ny-1
+    const float sn = lo ? 1.0f : -1.0f;
+    const float ux = lo ? ch.uw_lo[0] : ch.uw_hi[0];
+    const float uy = lo ? ch.uw_lo[1] : ch.uw_hi[1];
+    const float uz = lo ? ch.uw_lo[2] : ch.uw_hi[2];
     float s0 = 0.f, sm = 0.f, px = 0.f, pz = 0.f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -185,29 +213,21 @@ __device__ __forceinline__ void onsite_rows(const float* u, float g[Q], float Fx
             s0 += g[i];
             if (cx(i)) px += cx(i) * g[i];
             if (cz(i)) pz += cz(i) * g[i];
-        } else if (cy(i) == -S) {
-            sm += g[i];
+        } else {
+            sm += ((cy(i) == 1) != lo) ? g[i] : 0.0f;  // leaving through the wall: c.n = -1
         }
     }
-    const float un = S * u[1];
-    const float drho = (s0 + 2.0f * sm - 0.5f * S * Fy + un) / (1.0f - un);
+    const float un = sn * uy;
+    const float drho = (s0 + 2.0f * sm - 0.5f * sn * Fy + un) / (1.0f - un);
     const float rho = 1.0f + drho;
-    const float Jx = rho * u[0] - 0.5f * Fx, Jy = rho * u[1] - 0.5f * Fy, Jz = rho * u[2] - 0.5f * Fz;
+    const float Jx = rho * ux - 0.5f * Fx, Jy = rho * uy - 0.5f * Fy, Jz = rho * uz - 0.5f * Fz;
     const float Nx = 0.5f * px - Jx * (1.0f / 3.0f), Nz = 0.5f * pz - Jz * (1.0f / 3.0f);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        if (cy(i) == S)
-            g[i] = g[opp(i)] + 6.0f * wgt(i) * (cx(i) * Jx + cy(i) * Jy + cz(i) * Jz) - (cx(i) * Nx + cz(i) * Nz);
-}
-
-// Applies the on-site rule to a pulled cell of row y (no-op for other rows and wall kinds).
-// Every kernel that reads the state calls it between the pull and the moments.
-__device__ __forceinline__ void onsite_wall(const Chan& ch, int y, float g[Q], float Fx, float Fy, float Fz) {
-    if (ch.walls != 2) return;
-    if (y == 0)
-        onsite_rows<1>(ch.uw_lo, g, Fx, Fy, Fz);
-    else if (y == ch.ny - 1)
-        onsite_rows<-1>(ch.uw_hi, g, Fx, Fy, Fz);
+        if (cy(i) != 0) {
+            const float v = g[opp(i)] + 6.0f * wgt(i) * (cx(i) * Jx + cy(i) * Jy + cz(i) * Jz) - (cx(i) * Nx + cz(i) * Nz);
+            g[i] = ((cy(i) == 1) == lo) ? v : g[i];  // entering the fluid: c.n = +1
+        }
 }
 
 // Zeroth and first moments of the shifted populations: drho = sum g, j = sum c g

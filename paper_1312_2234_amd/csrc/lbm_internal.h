@@ -169,6 +169,7 @@ struct Layout {
 struct lbm_ctx {
     int nch = 0;
     lbm_storage storage = LBM_STORE_F32;
+    bool onsite = false;  // some channel has on-site walls (walls = 2)
     ib_kernel kernel = IB_PHI_COS4;
     int64_t max_nodes = 0;
     hipStream_t stream = nullptr;
@@ -247,5 +248,24 @@ hipError_t launch_norm(hipStream_t s, const float* raw, const float* tgt, int64_
 hipError_t launch_restrict(lbm_ctx* c, const LatArgs& a, float resc, float* gc, float* Fc);
 hipError_t launch_targets(hipStream_t s, const Chan& ch, const float* g0, const float* F, const float* g1,
                           float* feat, float* target);
+
+// Calls f(St{}) with the storage form of the context: StF32 / StF16 / StBF16, wrapped in
+// OnSite<> when a channel has on-site walls, so that only such contexts run kernels with the
+// wall-row branch compiled in.  Every branch of f must return the same type.
+template <class F>
+auto with_storage(const lbm_ctx* c, F&& f) {
+    if (c->onsite) {
+        switch (c->storage) {
+            case LBM_STORE_F16: return f(OnSite<StF16>{});
+            case LBM_STORE_BF16: return f(OnSite<StBF16>{});
+            default: return f(OnSite<StF32>{});
+        }
+    }
+    switch (c->storage) {
+        case LBM_STORE_F16: return f(StF16{});
+        case LBM_STORE_BF16: return f(StBF16{});
+        default: return f(StF32{});
+    }
+}
 
 }  // namespace lbmib
