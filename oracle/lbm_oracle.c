@@ -46,6 +46,9 @@
  *       gradient of the energy.
  *   R8  Bending stand-in for the finite-element bending of Eq. (6)-(10): the
  *       dihedral energy E = k_b sum_hinges (1 - cos(theta - theta_0)).
+ *   R23 Area and volume constraints, Eq. (4)-(5): Eq. (11) prints the force as
+ *       +dH/dx; as for R7 the oracle takes F = -grad H.  Volumes by the divergence
+ *       theorem over outward-oriented triangles; rest values from the rest shape.
  *
  * Units: lattice units, h = dt = rho_0 = 1.  Arrays are SoA, x fastest:
  * node index n = x + nx*(y + ny*z); populations f[i*N + n] in paper order
@@ -556,4 +559,106 @@ void orc_membrane_forces(int64_t nn, const double* X, int64_t ne, const int32_t*
     if (anchors)
         for (int64_t i = 0; i < nn; ++i)
             for (int d = 0; d < 3; ++d) F[d * nn + i] -= k_tether * (X[d * nn + i] - anchors[d * nn + i]);
+}
+
+/* ---------------------------------------------------------------- area and volume constraints
+ * Eq. (4)-(5) (reading R23: the force is -grad H, as for the springs under R7).  Triangles
+ * (a, b, c) with the outward normal n = (b - a) x (c - a) (right-hand rule); a body's
+ * triangles are contiguous, body_tri[b] .. body_tri[b+1].
+ *   triangle area   S_t = |n| / 2
+ *   body area       S^total = sum over the body's triangles of S_t
+ *   body volume     V = sum over the body's triangles of a.(b x c) / 6   (divergence theorem)
+ *   H = sum_bodies [ k_s (S^total - S_0^total)^2 / (2 S_0^total) + k_v (V - V_0)^2 / (2 V_0) ]
+ *       + sum_triangles k_t (S_t - S_0,t)^2 / (2 S_0,t)
+ * with the rest values measured on the rest shape (orc_triangle_rest). */
+static double tri_area(const double* a, const double* b, const double* c, double n[3]) {
+    double u[3], v[3];
+    sub3(b, a, u); sub3(c, a, v); cross3(u, v, n);
+    return 0.5 * sqrt(dot3(n, n));
+}
+
+static double tri_volume6(const double* a, const double* b, const double* c) {
+    double bc[3];
+    cross3(b, c, bc);
+    return dot3(a, bc);
+}
+
+/* body[2b] = S^total, body[2b+1] = V of each body for the shape X; area[t] = S_t (may be NULL) */
+static void body_measures(int64_t nn, const double* X, const int32_t* tri, int64_t nb, const int32_t* body_tri,
+                          double* area, double* body) {
+    for (int64_t b = 0; b < nb; ++b) {
+        double S = 0.0, V6 = 0.0;
+        for (int64_t t = body_tri[b]; t < body_tri[b + 1]; ++t) {
+            double p[3][3], n[3];
+            for (int k = 0; k < 3; ++k) getp(X, nn, tri[3 * t + k], p[k]);
+            double s = tri_area(p[0], p[1], p[2], n);
+            if (area) area[t] = s;
+            S += s;
+            V6 += tri_volume6(p[0], p[1], p[2]);
+        }
+        body[2 * b] = S;
+        body[2 * b + 1] = V6 / 6.0;
+    }
+}
+
+/* Rest values of Eq. (4)-(5) on the rest shape: S_0 per triangle, (S_0^total, V_0) per body. */
+void orc_triangle_rest(int64_t nn, const double* X_rest, const int32_t* tri, int64_t nb, const int32_t* body_tri,
+                       double* area0, double* body0) {
+    body_measures(nn, X_rest, tri, nb, body_tri, area0, body0);
+}
+
+double orc_constraint_energy(int64_t nn, const double* X, const int32_t* tri, int64_t nb, const int32_t* body_tri,
+                             const double* area0, const double* body0, double k_s, double k_t, double k_v) {
+    int64_t nt = body_tri[nb];
+    double* area = (double*)malloc(sizeof(double) * (nt > 0 ? nt : 1));
+    double* body = (double*)malloc(sizeof(double) * 2 * (nb > 0 ? nb : 1));
+    body_measures(nn, X, tri, nb, body_tri, area, body);
+    double H = 0.0;
+    for (int64_t b = 0; b < nb; ++b) {
+        double dS = body[2 * b] - body0[2 * b], dV = body[2 * b + 1] - body0[2 * b + 1];
+        H += k_s * dS * dS / (2.0 * body0[2 * b]) + k_v * dV * dV / (2.0 * body0[2 * b + 1]);
+    }
+    for (int64_t t = 0; t < nt; ++t) {
+        double d = area[t] - area0[t];
+        H += k_t * d * d / (2.0 * area0[t]);
+    }
+    free(area);
+    free(body);
+    return H;
+}
+
+/* F = -grad H of orc_constraint_energy, [3][nn] (overwritten).  Per triangle (a, b, c):
+ *   dS_t/da = (1/2) n_hat x (c - b),  dS_t/db = (1/2) n_hat x (a - c),  dS_t/dc = (1/2) n_hat x (b - a)
+ *   dV/da = (b x c)/6,  dV/db = (c x a)/6,  dV/dc = (a x b)/6
+ * and dH/dx = [k_s (S^total - S_0^total)/S_0^total + k_t (S_t - S_0,t)/S_0,t] dS_t/dx
+ *            + k_v (V - V_0)/V_0 dV/dx, summed over the triangles at the node. */
+void orc_constraint_forces(int64_t nn, const double* X, const int32_t* tri, int64_t nb, const int32_t* body_tri,
+                           const double* area0, const double* body0, double k_s, double k_t, double k_v, double* F) {
+    memset(F, 0, sizeof(double) * 3 * nn);
+    double* body = (double*)malloc(sizeof(double) * 2 * (nb > 0 ? nb : 1));
+    body_measures(nn, X, tri, nb, body_tri, NULL, body);
+    for (int64_t b = 0; b < nb; ++b) {
+        double cs = k_s * (body[2 * b] - body0[2 * b]) / body0[2 * b];
+        double cv = k_v * (body[2 * b + 1] - body0[2 * b + 1]) / body0[2 * b + 1];
+        for (int64_t t = body_tri[b]; t < body_tri[b + 1]; ++t) {
+            int64_t id[3];
+            double p[3][3], n[3];
+            for (int k = 0; k < 3; ++k) { id[k] = tri[3 * t + k]; getp(X, nn, id[k], p[k]); }
+            double S = tri_area(p[0], p[1], p[2], n);
+            double ct = k_t * (S - area0[t]) / area0[t];
+            double nl = 2.0 * S; /* |n| */
+            double nh[3] = {n[0] / nl, n[1] / nl, n[2] / nl};
+            for (int k = 0; k < 3; ++k) {
+                const double* pb = p[(k + 1) % 3];
+                const double* pc = p[(k + 2) % 3];
+                double e[3], dS[3], dV[3];
+                sub3(pc, pb, e);
+                cross3(nh, e, dS);
+                cross3(pb, pc, dV);
+                for (int d = 0; d < 3; ++d)
+                    F[d * nn + id[k]] -= (cs + ct) * 0.5 * dS[d] + cv * dV[d] / 6.0;
+            }
+        }
+    }
+    free(body);
 }

@@ -72,6 +72,12 @@ def lib():
         L.orc_membrane_energy.restype = C.c_double
         L.orc_membrane_forces.argtypes = [C.c_int64, dp, C.c_int64, ip, dp, C.c_double, C.c_int64, ip, dp,
                                           C.c_double, dp, C.c_double, dp]
+        L.orc_triangle_rest.argtypes = [C.c_int64, dp, ip, C.c_int64, ip, dp, dp]
+        L.orc_constraint_energy.argtypes = [C.c_int64, dp, ip, C.c_int64, ip, dp, dp, C.c_double, C.c_double,
+                                            C.c_double]
+        L.orc_constraint_energy.restype = C.c_double
+        L.orc_constraint_forces.argtypes = [C.c_int64, dp, ip, C.c_int64, ip, dp, dp, C.c_double, C.c_double,
+                                            C.c_double, dp]
         _lib = L
     return _lib
 
@@ -246,11 +252,14 @@ class Lattice:
 
 # ----------------------------------------------------------------- membrane forces
 class Membrane:
-    """Spring network (Eq. 2-3), tethers and the dihedral bending stand-in.
-    Rest lengths / angles are measured on ``X_rest`` by the oracle itself."""
+    """Spring network (Eq. 2-3), tethers, the dihedral bending stand-in and the area and
+    volume constraints of Eq. (4)-(5) (``triangles`` [nt, 3], outward by the right-hand rule,
+    each body's triangles contiguous: ``body_tri`` = [0, ..., nt]; one body if omitted).
+    Rest lengths, angles, areas and volumes are measured on ``X_rest`` by the oracle itself."""
 
     def __init__(self, X_rest, edges, k_spring=0.0, hinges=None, k_bend=0.0, anchors=None,
-                 k_tether=0.0):
+                 k_tether=0.0, triangles=None, body_tri=None, k_area_global=0.0, k_area_local=0.0,
+                 k_volume=0.0):
         X_rest = _f64(X_rest)
         self.n = X_rest.shape[1]
         self.edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
@@ -262,12 +271,37 @@ class Membrane:
         lib().orc_edge_lengths(self.n, _d(X_rest), len(self.edges), _i(self.edges), _d(self.rest_len))
         self.rest_theta = np.zeros(len(self.hinges))
         lib().orc_hinge_angles(self.n, _d(X_rest), len(self.hinges), _i(self.hinges), _d(self.rest_theta))
+        self.tri = (None if triangles is None
+                    else np.ascontiguousarray(triangles, dtype=np.int32).reshape(-1, 3))
+        self.k_area_global, self.k_area_local, self.k_volume = float(k_area_global), float(k_area_local), float(k_volume)
+        if self.tri is not None:
+            nt = len(self.tri)
+            self.body_tri = np.ascontiguousarray([0, nt] if body_tri is None else body_tri, dtype=np.int32)
+            self.nb = len(self.body_tri) - 1
+            self.rest_area = np.zeros(nt)
+            self.rest_body = np.zeros((self.nb, 2))
+            lib().orc_triangle_rest(self.n, _d(X_rest), _i(self.tri), self.nb, _i(self.body_tri),
+                                    _d(self.rest_area), _d(self.rest_body))
+
+    def measures(self, X):
+        """(area, volume) of each body for the shape X (Eq. 4-5's S^total and V)."""
+        X = _f64(X)
+        a0, b = np.zeros(len(self.tri)), np.zeros((self.nb, 2))
+        lib().orc_triangle_rest(self.n, _d(X), _i(self.tri), self.nb, _i(self.body_tri), _d(a0), _d(b))
+        return b[:, 0], b[:, 1]
+
+    def _constraint_args(self):
+        return (_i(self.tri), self.nb, _i(self.body_tri), _d(self.rest_area), _d(self.rest_body),
+                self.k_area_global, self.k_area_local, self.k_volume)
 
     def energy(self, X):
         X = _f64(X)
-        return lib().orc_membrane_energy(self.n, _d(X), len(self.edges), _i(self.edges), _d(self.rest_len),
-                                         self.k_spring, len(self.hinges), _i(self.hinges),
-                                         _d(self.rest_theta), self.k_bend, _d(self.anchors), self.k_tether)
+        E = lib().orc_membrane_energy(self.n, _d(X), len(self.edges), _i(self.edges), _d(self.rest_len),
+                                      self.k_spring, len(self.hinges), _i(self.hinges),
+                                      _d(self.rest_theta), self.k_bend, _d(self.anchors), self.k_tether)
+        if self.tri is not None:
+            E += lib().orc_constraint_energy(self.n, _d(X), *self._constraint_args())
+        return E
 
     def forces(self, X):
         X = _f64(X)
@@ -275,6 +309,10 @@ class Membrane:
         lib().orc_membrane_forces(self.n, _d(X), len(self.edges), _i(self.edges), _d(self.rest_len),
                                   self.k_spring, len(self.hinges), _i(self.hinges), _d(self.rest_theta),
                                   self.k_bend, _d(self.anchors), self.k_tether, _d(F))
+        if self.tri is not None:
+            Fc = np.empty_like(X)
+            lib().orc_constraint_forces(self.n, _d(X), *self._constraint_args(), _d(Fc))
+            F += Fc
         return F
 
 

@@ -391,3 +391,118 @@ def test_paper_timestep(orc):
     g = json.load(open(os.path.join(GOLDEN, "lattice_timestep.json")))
     dt = orc.lattice_timestep(g["tau"], g["h_m"], g["mu_Pa_s"], g["rho_kg_m3"])
     assert abs(dt - g["dt_s_printed"]) < 0.5e-8 * 10 ** (1 - g["printed_digits"]) * 0.1
+
+
+# ----------------------------------------------------------------------------- area / volume constraints
+def _cube():
+    """Unit cube [0,1]^3 as 12 outward triangles."""
+    V = np.array([[x, y, z] for z in (0, 1) for y in (0, 1) for x in (0, 1)], float)
+    q = [(0, 2, 3, 1), (4, 5, 7, 6), (0, 1, 5, 4), (2, 6, 7, 3), (0, 4, 6, 2), (1, 3, 7, 5)]  # outward quads
+    T = []
+    for a, b, c, d in q:
+        T += [(a, b, c), (a, c, d)]
+    return V, np.array(T, np.int32)
+
+
+def _sphere(level=2):
+    from paper_1312_2234_amd import inputs
+
+    V, T = inputs.icosphere(level)
+    return np.asarray(V, float), np.asarray(T, np.int32)
+
+
+def _membrane(orc, V, T, **k):
+    X = np.ascontiguousarray(V.T)
+    return orc.Membrane(X, np.zeros((0, 2), np.int32), triangles=T, **k), X
+
+
+def test_constraint_measures_closed_forms(orc):
+    """Eq. (4)-(5)'s S^total and V: a unit cube has area 6 and volume 1, also translated and
+    scaled by 2 (24, 8); a regular tetrahedron of edge a has sqrt(3) a^2 and a^3 / (6 sqrt 2)."""
+    V, T = _cube()
+    m, X = _membrane(orc, V, T)
+    S, Vol = m.measures(X)
+    assert abs(S[0] - 6) < 1e-14 and abs(Vol[0] - 1) < 1e-14
+    S, Vol = m.measures(2 * X + np.array([5.0, -3.0, 2.0])[:, None])
+    assert abs(S[0] - 24) < 1e-12 and abs(Vol[0] - 8) < 1e-12
+    a = 1.7
+    P = a / math.sqrt(2) * np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float) / 2
+    Tt = np.array([(0, 1, 2), (0, 3, 1), (0, 2, 3), (1, 3, 2)], np.int32)
+    Xt = np.ascontiguousarray(P.T)
+    c = P.mean(axis=0)
+    for t in Tt:  # make each face outward for the check (right-hand normal away from the centre)
+        n = np.cross(P[t[1]] - P[t[0]], P[t[2]] - P[t[0]])
+        assert n @ (P[t].mean(axis=0) - c) > 0
+    mt = orc.Membrane(Xt, np.zeros((0, 2), np.int32), triangles=Tt)
+    S, Vol = mt.measures(Xt)
+    assert abs(S[0] - math.sqrt(3) * a * a) < 1e-13 and abs(Vol[0] - a ** 3 / (6 * math.sqrt(2))) < 1e-13
+
+
+@pytest.mark.parametrize("k", [dict(k_area_global=0.3), dict(k_area_local=0.2), dict(k_volume=0.5),
+                               dict(k_area_global=0.3, k_area_local=0.2, k_volume=0.5)])
+def test_constraint_forces_match_finite_differences(orc, k):
+    """F = -grad H of Eq. (4)-(5) (reading R23) against central differences of the energy."""
+    rng = np.random.default_rng(21)
+    V, T = _sphere(2)
+    m, X0 = _membrane(orc, 3.0 * V, T, **k)
+    X = X0 * (1 + 0.05 * rng.standard_normal(X0.shape))
+    F = m.forces(X)
+    h = 1e-6
+    idx = rng.choice(X.shape[1], 12, replace=False)
+    for i in idx:
+        for d in range(3):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[d, i] += h
+            Xm[d, i] -= h
+            fd = -(m.energy(Xp) - m.energy(Xm)) / (2 * h)
+            assert abs(F[d, i] - fd) <= 1e-6 * np.abs(F).max()
+
+
+def test_constraint_forces_are_free_and_torque_free(orc):
+    """Area and volume of a closed surface do not change under rigid motions, so the forces sum
+    to zero and exert no torque, whatever the shape."""
+    rng = np.random.default_rng(22)
+    V, T = _sphere(2)
+    m, X0 = _membrane(orc, 2.0 * V, T, k_area_global=0.3, k_area_local=0.2, k_volume=0.5)
+    X = X0 * (1 + 0.08 * rng.standard_normal(X0.shape)) + np.array([4.0, -1.0, 7.0])[:, None]
+    F = m.forces(X)
+    scale = np.abs(F).max()
+    assert np.abs(F.sum(axis=1)).max() < 1e-12 * scale * X.shape[1]
+    torque = np.cross(X.T, F.T).sum(axis=0)
+    assert np.abs(torque).max() < 1e-11 * scale * X.shape[1] * np.abs(X).max()
+
+
+def test_constraint_virial_under_uniform_scaling(orc):
+    """X = lam X_0 about the origin: S_t and S^total scale by lam^2, V by lam^3, so
+    sum_i X_i . F_i = -lam dH/dlam with dH/dlam = 2 k_s (lam^2 - 1) lam S_0 + 2 k_t (lam^2 - 1) lam S_0
+    + 3 k_v (lam^3 - 1) lam^2 V_0 (closed form; independent of the gradient formulas)."""
+    V, T = _sphere(2)
+    ks, kt, kv = 0.3, 0.2, 0.5
+    m, X0 = _membrane(orc, 2.5 * V, T, k_area_global=ks, k_area_local=kt, k_volume=kv)
+    S0, V0 = m.rest_body[0]
+    for lam in (0.9, 1.07, 1.3):
+        F = m.forces(lam * X0)
+        virial = np.einsum("di,di->", lam * X0, F)
+        dH = 2 * ks * (lam ** 2 - 1) * lam * S0 + 2 * kt * (lam ** 2 - 1) * lam * S0 + 3 * kv * (lam ** 3 - 1) * lam ** 2 * V0
+        assert abs(virial + lam * dH) < 1e-11 * abs(lam * dH)
+
+
+def test_constraint_volume_force_restores(orc):
+    """An inflated sphere is pushed inwards at every node by the volume term, a shrunk one
+    outwards; two bodies in one membrane act independently."""
+    V, T = _sphere(2)
+    n = len(V)
+    Xa = np.ascontiguousarray((2.0 * V).T)
+    Xb = np.ascontiguousarray((3.0 * V + np.array([10.0, 0, 0])).T)
+    X0 = np.concatenate([Xa, Xb], axis=1)
+    T2 = np.concatenate([T, T + n]).astype(np.int32)
+    m = orc.Membrane(X0, np.zeros((0, 2), np.int32), triangles=T2, body_tri=[0, len(T), 2 * len(T)], k_volume=0.5)
+    X = X0.copy()
+    X[:, :n] *= 1.05                                  # body a inflated
+    cb = np.array([10.0, 0, 0])[:, None]
+    X[:, n:] = cb + (X0[:, n:] - cb) * 0.95           # body b shrunk
+    F = m.forces(X)
+    ra = X[:, :n]
+    rb = X[:, n:] - cb
+    assert np.all(np.einsum("di,di->i", F[:, :n], ra) < 0)
+    assert np.all(np.einsum("di,di->i", F[:, n:], rb) > 0)
