@@ -195,10 +195,28 @@ typedef struct {
     double k_bend;
     const double* anchors;     /* [3][n] tether anchors, or NULL */
     double k_tether;
+    /* Area and volume constraints, Eq. (4)-(5), force -grad H: off when tri is NULL or the three
+     * coefficients are 0.  Triangles (a, b, c) have the outward normal (b - a) x (c - a); each
+     * body's triangles are contiguous.  Per body S^total and V are summed in a fixed order (one
+     * workgroup per body), so the forces are deterministic. */
+    const int32_t* tri;        /* [nt][3] */
+    int64_t nt;
+    const int32_t* tri_ptr;    /* [n+1] CSR node -> triangle incidences */
+    const int32_t* tri_inc;    /* [nnz_t] (triangle id << 2) | corner 0..2 */
+    const int32_t* tri_body;   /* [nt] body of each triangle */
+    const int32_t* body_tri;   /* [nb+1] first triangle of each body, then nt */
+    int64_t nb;
+    double* rest_area;         /* [nt] S_0 of each triangle (filled by ib_membrane_rest) */
+    double* rest_body;         /* [nb][2] S_0^total, V_0 of each body (filled by ib_membrane_rest) */
+    double* body_now;          /* [nb][2] scratch: S^total, V of the current shape */
+    double k_area_global;      /* k_s of Eq. (4) */
+    double k_area_local;       /* k_t of Eq. (4) */
+    double k_volume;           /* k_v of Eq. (5) */
 } ib_membrane;
 
-/* Measure rest lengths and rest dihedral angles on X_rest ([3][n] float64); build
- * hinge_slot.  Requires every hinge vertex's incidences in hinge_ptr / hinge_inc. */
+/* Measure rest lengths, rest dihedral angles and (with triangles) the rest areas and volumes
+ * on X_rest ([3][n] float64); build hinge_slot.  Requires every hinge vertex's incidences in
+ * hinge_ptr / hinge_inc. */
 lbm_status ib_membrane_rest(const ib_membrane* m /*host*/, const double* X_rest, void* stream);
 /* F = -grad(E)(X), float64 arithmetic, float32 output [3][n]. */
 lbm_status ib_membrane_forces(const ib_membrane* m /*host*/, const double* X, float* F, void* stream);

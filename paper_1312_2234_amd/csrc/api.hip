@@ -490,8 +490,16 @@ lbm_status ib_advance(lbm_ctx* c, int64_t n, double* X, const float* U) {
     return hip_ok(launch_ib_advance(c->stream, n, X, U));
 }
 
+// The constraint arrays of Eq. (4)-(5) are all present when triangles are given.
+static bool constraints_ok(const ib_membrane* m) {
+    if (!m->tri) return true;
+    if (m->nt < 0 || m->nb < 0 || (m->nt > 0 && m->nb < 1)) return false;
+    return m->tri_ptr && m->tri_inc && m->tri_body && m->body_tri && m->rest_area && m->rest_body && m->body_now;
+}
+
 lbm_status ib_membrane_rest(const ib_membrane* m, const double* X_rest, void* stream) {
     if (!m || m->n < 0 || (m->n > 0 && !X_rest)) return LBM_ERR_ARG;
+    if (!constraints_ok(m)) return LBM_ERR_ARG;
     if (m->nbr_ptr && (!m->nbr_idx || !m->rest_len)) return LBM_ERR_ARG;
     if (m->nh > 0 && (!m->hinges || !m->rest_cs)) return LBM_ERR_ARG;
     if (m->hinge_ptr && m->nh > 0 && (!m->hinge_inc || !m->hinge_slot)) return LBM_ERR_ARG;
@@ -500,6 +508,7 @@ lbm_status ib_membrane_rest(const ib_membrane* m, const double* X_rest, void* st
 
 lbm_status ib_membrane_forces(const ib_membrane* m, const double* X, float* F, void* stream) {
     if (!m || m->n < 0 || (m->n > 0 && (!X || !F))) return LBM_ERR_ARG;
+    if (!constraints_ok(m)) return LBM_ERR_ARG;
     if (m->nbr_ptr && (!m->nbr_idx || !m->rest_len)) return LBM_ERR_ARG;
     if (m->hinge_ptr && (!m->hinge_inc || !m->hinges || !m->rest_cs ||
                          (m->nh > 0 && (!m->hinge_force || !m->hinge_slot))))
@@ -581,7 +590,7 @@ lbm_status lbm_coupled_steps(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, d
     lbm_status st = check_ib(c, c->n_nodes);
     if (st != LBM_OK) return st;
     if (c->n_nodes > 0 && (!X || !F || !U)) return LBM_ERR_ARG;
-    if (m && m->n != c->n_nodes) return LBM_ERR_ARG;
+    if (m && (m->n != c->n_nodes || !constraints_ok(m))) return LBM_ERR_ARG;
     return coupled(c, m, nsteps, X, F, U);
 }
 
@@ -590,7 +599,7 @@ lbm_status lbm_graph_capture(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, d
     lbm_status st = check_ib(c, c->n_nodes);
     if (st != LBM_OK) return st;
     if (c->n_nodes > 0 && (!X || !F || !U)) return LBM_ERR_ARG;
-    if (m && m->n != c->n_nodes) return LBM_ERR_ARG;
+    if (m && (m->n != c->n_nodes || !constraints_ok(m))) return LBM_ERR_ARG;
     if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
     if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
     const int cur0 = c->cur, set0 = c->ibset;

@@ -898,6 +898,60 @@ __global__ void __launch_bounds__(256) k_mem_hinges(ib_membrane m, const double*
     if (h < m.nh) hinge_one(m, X, h);
 }
 
+// ---------------------------------------------------------------- area and volume (Eq. (4)-(5))
+__host__ __device__ inline bool constraints_on(const ib_membrane& m) {
+    return m.tri && m.nt > 0 && m.nb > 0 && (m.k_area_global != 0.0 || m.k_area_local != 0.0 || m.k_volume != 0.0);
+}
+
+// Per body (one workgroup of BODY_THREADS): S^total = sum of the triangle areas |n|/2 with
+// n = (b - a) x (c - a), and V = sum of a.(b x c)/6 over its outward triangles (divergence
+// theorem), as strided partial sums and a fixed tree, so they do not depend on scheduling.
+constexpr int BODY_THREADS = 256;
+__device__ __forceinline__ void body_block(const ib_membrane& m, const double* X, double* out, int64_t b) {
+    __shared__ double sa[BODY_THREADS], sv[BODY_THREADS];
+    double S = 0.0, V6 = 0.0;
+    for (int64_t t = m.body_tri[b] + threadIdx.x; t < m.body_tri[b + 1]; t += BODY_THREADS) {
+        double p[3][3], u[3], v[3], nn[3], bc[3];
+        for (int k = 0; k < 3; ++k) ld3(X, m.n, m.tri[3 * t + k], p[k]);
+        sub(p[1], p[0], u);
+        sub(p[2], p[0], v);
+        crs(u, v, nn);
+        S += 0.5 * sqrt(dt3(nn, nn));
+        crs(p[1], p[2], bc);
+        V6 += dt3(p[0], bc);
+    }
+    sa[threadIdx.x] = S;
+    sv[threadIdx.x] = V6;
+    __syncthreads();
+    for (int w = BODY_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sa[threadIdx.x] += sa[threadIdx.x + w];
+            sv[threadIdx.x] += sv[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * b] = sa[0];
+        out[2 * b + 1] = sv[0] / 6.0;
+    }
+}
+
+__global__ void __launch_bounds__(BODY_THREADS) k_mem_bodies(ib_membrane m, const double* X, double* out) {
+    body_block(m, X, out, blockIdx.x);
+}
+
+// Rest area S_0 of each triangle.
+__global__ void k_tri_rest(ib_membrane m, const double* X) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m.nt) return;
+    double p[3][3], u[3], v[3], nn[3];
+    for (int k = 0; k < 3; ++k) ld3(X, m.n, m.tri[3 * t + k], p[k]);
+    sub(p[1], p[0], u);
+    sub(p[2], p[0], v);
+    crs(u, v, nn);
+    m.rest_area[t] = 0.5 * sqrt(dt3(nn, nn));
+}
+
 // Inverse of the node -> hinge incidence CSR: position of (hinge, role) in hinge_inc.
 __global__ void k_mem_hinge_slots(ib_membrane m, int64_t nnz) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -905,7 +959,10 @@ __global__ void k_mem_hinge_slots(ib_membrane m, int64_t nnz) {
 }
 
 // Per node (8 lanes each, partial sums combined by a fixed butterfly): springs (CSR), the
-// hinge forces of its incidences, tether.  In the coupled step (rec != NULL) it also puts F
+// hinge forces of its incidences, the area and volume constraints of its triangles, tether.
+// For the corner a of triangle (a, b, c) (any cyclic order), with n = (b - a) x (c - a):
+//   dS/da = n_hat x (c - b) / 2,  dV/da = (b x c) / 6,
+//   F_a -= [k_s (S^total - S_0^total)/S_0^total + k_t (S - S_0)/S_0] dS/da + k_v (V - V_0)/V_0 dV/da.  In the coupled step (rec != NULL) it also puts F
 // into the node records and the workgroup's max |F| into bmax[workgroup], the two parts of
 // the binning that need F.
 __device__ __forceinline__ void forces_block(const ib_membrane& m, const double* X, float* Fout, float* rec,
@@ -928,6 +985,30 @@ __device__ __forceinline__ void forces_block(const ib_membrane& m, const double*
         for (int e = m.hinge_ptr[i] + sl; e < m.hinge_ptr[i + 1]; e += 8) {
             const double* hf = m.hinge_force + 3 * (int64_t)e;
             F[0] += hf[0]; F[1] += hf[1]; F[2] += hf[2];
+        }
+    }
+    if (valid && constraints_on(m)) {
+        for (int e = m.tri_ptr[i] + sl; e < m.tri_ptr[i + 1]; e += 8) {
+            const int32_t code = m.tri_inc[e];
+            const int64_t t = code >> 2;
+            const int k = code & 3;
+            double pa[3], pb[3], pc[3], u[3], v[3], nn[3], ed[3], dS[3], dV[3];
+            ld3(X, m.n, m.tri[3 * t + k], pa);
+            ld3(X, m.n, m.tri[3 * t + (k + 1) % 3], pb);
+            ld3(X, m.n, m.tri[3 * t + (k + 2) % 3], pc);
+            sub(pb, pa, u);
+            sub(pc, pa, v);
+            crs(u, v, nn);
+            const double nl = sqrt(dt3(nn, nn));  // |n| = 2 S
+            const double nh[3] = {nn[0] / nl, nn[1] / nl, nn[2] / nl};
+            const int bd = m.tri_body[t];
+            const double cs = m.k_area_global * (m.body_now[2 * bd] - m.rest_body[2 * bd]) / m.rest_body[2 * bd];
+            const double cv = m.k_volume * (m.body_now[2 * bd + 1] - m.rest_body[2 * bd + 1]) / m.rest_body[2 * bd + 1];
+            const double ct = m.k_area_local * (0.5 * nl - m.rest_area[t]) / m.rest_area[t];
+            sub(pc, pb, ed);
+            crs(nh, ed, dS);
+            crs(pb, pc, dV);
+            for (int d = 0; d < 3; ++d) F[d] -= (cs + ct) * 0.5 * dS[d] + cv * dV[d] / 6.0;
         }
     }
 #pragma unroll
@@ -984,13 +1065,18 @@ __global__ void __launch_bounds__(FS_THREADS) k_forces_scan(ib_membrane m, const
 }
 
 // The coupled step's first launch: the binning of the nodes by position (workgroups
-// [0, nbb), dispatched first: theirs is the longer dependent chain) and the hinge forces (the
-// rest), which it does not depend on.
-__global__ void __launch_bounds__(256) k_hinges_bin(ib_membrane m, const double* X, IbArgs a, int64_t nbb) {
-    if ((int64_t)blockIdx.x < nbb) {
-        bin_block(a, blockIdx.x, false);
+// [0, nbb), dispatched first: theirs is the longer dependent chain), the bodies' areas and
+// volumes for the constraints (the next nbd, one per body) and the hinge forces (the rest);
+// the binning depends on neither.
+__global__ void __launch_bounds__(256) k_hinges_bin(ib_membrane m, const double* X, IbArgs a, int64_t nbb,
+                                                    int64_t nbd) {
+    const int64_t blk = blockIdx.x;
+    if (blk < nbb) {
+        bin_block(a, blk, false);
+    } else if (blk < nbb + nbd) {
+        body_block(m, X, m.body_now, blk - nbb);
     } else {
-        const int64_t h = ((int64_t)blockIdx.x - nbb) * blockDim.x + threadIdx.x;
+        const int64_t h = (blk - nbb - nbd) * blockDim.x + threadIdx.x;
         if (h < m.nh) hinge_one(m, X, h);
     }
 }
@@ -999,6 +1085,10 @@ hipError_t launch_membrane_rest(const ib_membrane* m, const double* X_rest, hipS
     const int64_t n = m->n > m->nh ? m->n : m->nh;
     if (n <= 0) return hipSuccess;
     k_mem_rest<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(*m, X_rest);
+    if (m->tri && m->nt > 0 && m->nb > 0) {
+        k_tri_rest<<<dim3((unsigned)((m->nt + 255) / 256)), dim3(256), 0, s>>>(*m, X_rest);
+        k_mem_bodies<<<dim3((unsigned)m->nb), dim3(BODY_THREADS), 0, s>>>(*m, X_rest, m->rest_body);
+    }
     if (m->hinge_ptr && m->nh > 0) {
         const int64_t nnz = 4 * m->nh;
         k_mem_hinge_slots<<<dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s>>>(*m, nnz);
@@ -1010,6 +1100,8 @@ hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* 
     if (m->n <= 0) return hipSuccess;
     if (m->hinge_ptr && m->k_bend != 0.0 && m->nh > 0)
         k_mem_hinges<<<dim3((unsigned)((m->nh + 255) / 256)), dim3(256), 0, s>>>(*m, X);
+    if (constraints_on(*m))
+        k_mem_bodies<<<dim3((unsigned)m->nb), dim3(BODY_THREADS), 0, s>>>(*m, X, m->body_now);
     k_mem_forces<<<dim3((unsigned)((8 * m->n + 255) / 256)), dim3(256), 0, s>>>(*m, X, F);
     return hipGetLastError();
 }
@@ -1020,7 +1112,9 @@ hipError_t launch_forces_scatter(lbm_ctx* c, const ib_membrane* m, const double*
     const bool hinges = m->hinge_ptr && m->k_bend != 0.0 && m->nh > 0;
     const int64_t nbh = hinges ? (m->nh + 255) / 256 : 0;
     const int64_t nbb = (a.n + 255) / 256;
-    if (nbh + nbb > 0) k_hinges_bin<<<dim3((unsigned)(nbh + nbb)), dim3(256), 0, c->stream>>>(*m, X, a, nbb);
+    const int64_t nbd = constraints_on(*m) ? m->nb : 0;
+    if (nbh + nbb + nbd > 0)
+        k_hinges_bin<<<dim3((unsigned)(nbh + nbb + nbd)), dim3(256), 0, c->stream>>>(*m, X, a, nbb, nbd);
     const int64_t nbf = (8 * m->n + FS_THREADS - 1) / FS_THREADS;
     a.blkmax_n = nbf;
     a.scale_in_scatter = 1;

@@ -18,6 +18,7 @@ them); connectivity as int32.
 """
 from __future__ import annotations
 
+import dataclasses
 import functools
 from dataclasses import dataclass, field
 
@@ -130,6 +131,18 @@ def csr_hinges(n, hinges):
     return np.cumsum(ptr).astype(np.int32), code.astype(np.int32)
 
 
+def csr_triangles(n, tri):
+    """CSR incidence node -> (triangle << 2 | corner), corner 0..2 = position in the triangle."""
+    nt = len(tri)
+    node = np.asarray(tri).reshape(-1).astype(np.int64)
+    code = (np.repeat(np.arange(nt, dtype=np.int64), 3) << 2) | np.tile(np.arange(3), nt)
+    order = np.lexsort((code, node))
+    node, code = node[order], code[order]
+    ptr = np.zeros(n + 1, np.int64)
+    np.add.at(ptr, node + 1, 1)
+    return np.cumsum(ptr).astype(np.int32), code.astype(np.int32)
+
+
 # ----------------------------------------------------------------------------- bodies
 
 
@@ -145,10 +158,30 @@ class Bodies:
     k_bend: float = 0.0
     k_tether: float = 0.0
     body_offsets: list = field(default_factory=list)   # node offset of each body, plus n
+    # area and volume constraints of Eq. (4)-(5) (off unless triangles are set; with_constraints)
+    triangles: np.ndarray | None = None   # [nt, 3] int32, outward, each body's contiguous
+    tri_offsets: list = field(default_factory=list)    # triangle offset of each body, plus nt
+    k_area_global: float = 0.0
+    k_area_local: float = 0.0
+    k_volume: float = 0.0
 
     @property
     def n(self):
         return self.X.shape[1]
+
+
+def with_constraints(b, k_area_global=0.0, k_area_local=0.0, k_volume=0.0):
+    """The same bodies with the area and volume constraints of Eq. (4)-(5): the outward
+    triangles of each body's sphere mesh (the mesh its nodes were made from), with the given
+    coefficients.  Rest areas and volumes are measured on X_rest by the library and the oracle."""
+    T, offs = [], [0]
+    for lo, hi in zip(b.body_offsets[:-1], b.body_offsets[1:]):
+        Tb = _topology(hi - lo)[1] + lo
+        T.append(Tb)
+        offs.append(offs[-1] + len(Tb))
+    return dataclasses.replace(b, triangles=np.concatenate(T).astype(np.int32), tri_offsets=offs,
+                               k_area_global=float(k_area_global), k_area_local=float(k_area_local),
+                               k_volume=float(k_volume))
 
 
 def morton_order(V, bits=10):
@@ -356,10 +389,15 @@ def concat_bodies(channels):
     """Bodies of several channels in one global node numbering (channel order), and the
     node offsets of the channels (len(channels) + 1 entries)."""
     Xs, Xr, E, H, A, offs = [], [], [], [], [], [0]
+    T, TO = [], [0]
     off = 0
-    ks = set()
+    ks, kc = set(), set()
     for ch in channels:
         b = ch.bodies
+        if b.triangles is not None:
+            T.append(b.triangles + off)
+            TO += [o + TO[-1] for o in b.tri_offsets[1:]]
+        kc.add((b.k_area_global, b.k_area_local, b.k_volume))
         Xs.append(b.X)
         Xr.append(b.X_rest)
         E.append(b.edges + off)
@@ -369,11 +407,14 @@ def concat_bodies(channels):
         ks.add((b.k_spring, b.k_bend, b.k_tether))
         off += b.n
         offs.append(off)
-    if len(ks) != 1:
+    if len(ks) != 1 or len(kc) != 1 or len(T) not in (0, len(channels)):
         raise ValueError("channels must share the membrane constants")
     k_spring, k_bend, k_tether = ks.pop()
+    k_area_global, k_area_local, k_volume = kc.pop()
     anchors = np.ascontiguousarray(np.concatenate(A, axis=1)) if A and len(A) == len(channels) else None
     b = Bodies(X=np.ascontiguousarray(np.concatenate(Xs, axis=1)), X_rest=np.ascontiguousarray(np.concatenate(Xr, axis=1)),
                edges=np.concatenate(E).astype(np.int32), hinges=np.concatenate(H).astype(np.int32), anchors=anchors,
-               k_spring=k_spring, k_bend=k_bend, k_tether=k_tether, body_offsets=offs)
+               k_spring=k_spring, k_bend=k_bend, k_tether=k_tether, body_offsets=offs,
+               triangles=np.concatenate(T).astype(np.int32) if T else None, tri_offsets=TO if T else [],
+               k_area_global=k_area_global, k_area_local=k_area_local, k_volume=k_volume)
     return b, offs

@@ -52,7 +52,11 @@ class IbMembrane(C.Structure):
                 ("hinges", C.c_void_p), ("rest_cs", C.c_void_p), ("hinge_slot", C.c_void_p),
                 ("hinge_force", C.c_void_p),
                 ("nh", C.c_int64), ("k_bend", C.c_double),
-                ("anchors", C.c_void_p), ("k_tether", C.c_double)]
+                ("anchors", C.c_void_p), ("k_tether", C.c_double),
+                ("tri", C.c_void_p), ("nt", C.c_int64), ("tri_ptr", C.c_void_p), ("tri_inc", C.c_void_p),
+                ("tri_body", C.c_void_p), ("body_tri", C.c_void_p), ("nb", C.c_int64),
+                ("rest_area", C.c_void_p), ("rest_body", C.c_void_p), ("body_now", C.c_void_p),
+                ("k_area_global", C.c_double), ("k_area_local", C.c_double), ("k_volume", C.c_double)]
 
 
 _lib = None
@@ -483,6 +487,24 @@ class Membrane:
             self._keep.append(a)
             s.anchors = a.data_ptr()
         s.k_tether = float(bodies.k_tether)
+        tri = getattr(bodies, "triangles", None)
+        ks = (float(getattr(bodies, "k_area_global", 0.0)), float(getattr(bodies, "k_area_local", 0.0)),
+              float(getattr(bodies, "k_volume", 0.0)))
+        if tri is not None and len(tri) and any(ks):
+            tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+            toff = np.asarray(bodies.tri_offsets, dtype=np.int64)
+            tp, tinc = inputs.csr_triangles(n, tri)
+            tb = np.repeat(np.arange(len(toff) - 1, dtype=np.int32), np.diff(toff))
+            t_d, tp_d, ti_d, tb_d, bt_d = dev_i32(tri.reshape(-1)), dev_i32(tp), dev_i32(tinc), dev_i32(tb), dev_i32(toff)
+            nb = len(toff) - 1
+            ra = torch.zeros(len(tri), dtype=torch.float64, device=dev)
+            rb = torch.zeros(2 * nb, dtype=torch.float64, device=dev)
+            bn = torch.zeros(2 * nb, dtype=torch.float64, device=dev)
+            self._keep += [ra, rb, bn]
+            s.tri, s.nt, s.tri_ptr, s.tri_inc = t_d.data_ptr(), len(tri), tp_d.data_ptr(), ti_d.data_ptr()
+            s.tri_body, s.body_tri, s.nb = tb_d.data_ptr(), bt_d.data_ptr(), nb
+            s.rest_area, s.rest_body, s.body_now = ra.data_ptr(), rb.data_ptr(), bn.data_ptr()
+            s.k_area_global, s.k_area_local, s.k_volume = ks
         self.struct = s
         self.n = n
         st = stream if stream is not None else _stream_ptr(torch, dev)

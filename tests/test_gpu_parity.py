@@ -250,7 +250,9 @@ def run_oracle_coupled(orc, ch, kernel, steps):
                     u_wall_hi=ch.u_wall_hi, kernel=kernel)
     o.init(u=o.shear_profile()) if ch.init == "shear" else o.init()
     mem = orc.Membrane(b.X_rest, b.edges, k_spring=b.k_spring, hinges=b.hinges, k_bend=b.k_bend,
-                       anchors=b.anchors, k_tether=b.k_tether)
+                       anchors=b.anchors, k_tether=b.k_tether, triangles=b.triangles,
+                       body_tri=b.tri_offsets if b.triangles is not None else None,
+                       k_area_global=b.k_area_global, k_area_local=b.k_area_local, k_volume=b.k_volume)
     X = b.X.copy()
     for _ in range(steps):
         F, U = orc.coupled_step(o, mem, X)
