@@ -32,6 +32,8 @@ DTYPE = {"f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32"}
 
 
 def make_workload(name):
+    import dataclasses
+
     from paper_1312_2234_amd import inputs
 
     if name == "shear":
@@ -40,12 +42,18 @@ def make_workload(name):
                 "(6,2,6) x 2562 IB nodes, spring k=0.005 + bending 1e-4")
         return [ch], desc
     if name == "shear_onsite":
-        import dataclasses
-
         ch = dataclasses.replace(inputs.shear_platelets(seed=0), walls="onsite")
         desc = ("shear channel 256x128x128 with on-site velocity walls (Eq. 23-30) on rows 0 and 127, "
                 "top wall u=0.05, tau=1.0, 16 oblate platelets (6,2,6) x 2562 IB nodes, spring k=0.005 + "
                 "bending 1e-4")
+        return [ch], desc
+    if name == "shear_constrained":
+        ks, kt, kv = inputs.table2_constraint_coefficients()
+        ch = inputs.shear_platelets(seed=0)
+        ch = dataclasses.replace(ch, bodies=inputs.with_constraints(ch.bodies, ks, kt, kv))
+        desc = ("shear channel 256x128x128, top wall u=0.05, tau=1.0, 16 oblate platelets (6,2,6) x 2562 IB "
+                "nodes, spring k=0.005 + bending 1e-4 + area/volume constraints of Eq. 4-5 (Table 2: "
+                "k_s=k_t=%.4f, k_v=%.4f lattice units)" % (ks, kv))
         return [ch], desc
     if name == "batched":
         chans = inputs.batched_channels(seed=0)

@@ -208,7 +208,8 @@ typedef struct {
     int64_t nb;
     double* rest_area;         /* [nt] S_0 of each triangle (filled by ib_membrane_rest) */
     double* rest_body;         /* [nb][2] S_0^total, V_0 of each body (filled by ib_membrane_rest) */
-    double* body_now;          /* [nb][2] scratch: S^total, V of the current shape */
+    double* body_now;          /* [nb][4] scratch: S^total, V of the current shape and the force
+                                  coefficients k_s (S^total - S_0^total)/S_0^total, k_v (V - V_0)/V_0 */
     double k_area_global;      /* k_s of Eq. (4) */
     double k_area_local;       /* k_t of Eq. (4) */
     double k_volume;           /* k_v of Eq. (5) */

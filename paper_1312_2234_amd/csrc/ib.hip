@@ -906,10 +906,14 @@ __host__ __device__ inline bool constraints_on(const ib_membrane& m) {
 // Per body (one workgroup of BODY_THREADS): S^total = sum of the triangle areas |n|/2 with
 // n = (b - a) x (c - a), and V = sum of a.(b x c)/6 over its outward triangles (divergence
 // theorem), as strided partial sums and a fixed tree, so they do not depend on scheduling.
+// out[4b..4b+1] = S^total, V; with coef, also out[4b+2..4b+3] = the force coefficients
+// k_s (S^total - S_0^total)/S_0^total and k_v (V - V_0)/V_0 (rest values in m.rest_body).
 constexpr int BODY_THREADS = 256;
-__device__ __forceinline__ void body_block(const ib_membrane& m, const double* X, double* out, int64_t b) {
+__device__ __forceinline__ void body_block(const ib_membrane& m, const double* X, double* out, int64_t b,
+                                           bool coef) {
     __shared__ double sa[BODY_THREADS], sv[BODY_THREADS];
     double S = 0.0, V6 = 0.0;
+#pragma unroll 4
     for (int64_t t = m.body_tri[b] + threadIdx.x; t < m.body_tri[b + 1]; t += BODY_THREADS) {
         double p[3][3], u[3], v[3], nn[3], bc[3];
         for (int k = 0; k < 3; ++k) ld3(X, m.n, m.tri[3 * t + k], p[k]);
@@ -931,13 +935,21 @@ __device__ __forceinline__ void body_block(const ib_membrane& m, const double* X
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        out[2 * b] = sa[0];
-        out[2 * b + 1] = sv[0] / 6.0;
+        const double St = sa[0], V = sv[0] / 6.0;
+        if (coef) {
+            out[4 * b] = St;
+            out[4 * b + 1] = V;
+            out[4 * b + 2] = m.k_area_global * (St - m.rest_body[2 * b]) / m.rest_body[2 * b];
+            out[4 * b + 3] = m.k_volume * (V - m.rest_body[2 * b + 1]) / m.rest_body[2 * b + 1];
+        } else {
+            out[2 * b] = St;
+            out[2 * b + 1] = V;
+        }
     }
 }
 
-__global__ void __launch_bounds__(BODY_THREADS) k_mem_bodies(ib_membrane m, const double* X, double* out) {
-    body_block(m, X, out, blockIdx.x);
+__global__ void __launch_bounds__(BODY_THREADS) k_mem_bodies(ib_membrane m, const double* X, double* out, bool coef) {
+    body_block(m, X, out, blockIdx.x, coef);
 }
 
 // Rest area S_0 of each triangle.
@@ -965,6 +977,9 @@ __global__ void k_mem_hinge_slots(ib_membrane m, int64_t nnz) {
 //   F_a -= [k_s (S^total - S_0^total)/S_0^total + k_t (S - S_0)/S_0] dS/da + k_v (V - V_0)/V_0 dV/da.  In the coupled step (rec != NULL) it also puts F
 // into the node records and the workgroup's max |F| into bmax[workgroup], the two parts of
 // the binning that need F.
+// CONS: the constraint loop is compiled in (only launched when constraints_on(m)), so the
+// plain membrane keeps the smaller register footprint.
+template <bool CONS>
 __device__ __forceinline__ void forces_block(const ib_membrane& m, const double* X, float* Fout, float* rec,
                                              uint32_t* bmax, int64_t blk) {
     const int64_t i = (blk * blockDim.x + threadIdx.x) >> 3;
@@ -987,7 +1002,7 @@ __device__ __forceinline__ void forces_block(const ib_membrane& m, const double*
             F[0] += hf[0]; F[1] += hf[1]; F[2] += hf[2];
         }
     }
-    if (valid && constraints_on(m)) {
+    if (CONS && valid) {
         for (int e = m.tri_ptr[i] + sl; e < m.tri_ptr[i + 1]; e += 8) {
             const int32_t code = m.tri_inc[e];
             const int64_t t = code >> 2;
@@ -1000,15 +1015,15 @@ __device__ __forceinline__ void forces_block(const ib_membrane& m, const double*
             sub(pc, pa, v);
             crs(u, v, nn);
             const double nl = sqrt(dt3(nn, nn));  // |n| = 2 S
-            const double nh[3] = {nn[0] / nl, nn[1] / nl, nn[2] / nl};
             const int bd = m.tri_body[t];
-            const double cs = m.k_area_global * (m.body_now[2 * bd] - m.rest_body[2 * bd]) / m.rest_body[2 * bd];
-            const double cv = m.k_volume * (m.body_now[2 * bd + 1] - m.rest_body[2 * bd + 1]) / m.rest_body[2 * bd + 1];
             const double ct = m.k_area_local * (0.5 * nl - m.rest_area[t]) / m.rest_area[t];
+            // (cs + ct) dS/da with dS/da = n x (c - b) / (2 |n|); cv dV/da with dV/da = (b x c)/6
+            const double al = (m.body_now[4 * bd + 2] + ct) * 0.5 / nl;
+            const double be = m.body_now[4 * bd + 3] * (1.0 / 6.0);
             sub(pc, pb, ed);
-            crs(nh, ed, dS);
+            crs(nn, ed, dS);
             crs(pb, pc, dV);
-            for (int d = 0; d < 3; ++d) F[d] -= (cs + ct) * 0.5 * dS[d] + cv * dV[d] / 6.0;
+            for (int d = 0; d < 3; ++d) F[d] -= al * dS[d] + be * dV[d];
         }
     }
 #pragma unroll
@@ -1049,32 +1064,35 @@ __device__ __forceinline__ void forces_block(const ib_membrane& m, const double*
     }
 }
 
+template <bool CONS>
 __global__ void __launch_bounds__(256) k_mem_forces(ib_membrane m, const double* X, float* Fout) {
-    forces_block(m, X, Fout, nullptr, nullptr, blockIdx.x);
+    forces_block<CONS>(m, X, Fout, nullptr, nullptr, blockIdx.x);
 }
 
 // The coupled step's second launch: the scan of the tile lists (workgroup 0; it needs only
 // the binning) and the membrane forces (the rest, 128 nodes each), which also fill in the
 // records' F and max |F| per workgroup.
 constexpr int FS_THREADS = 1024;
+template <bool CONS>
 __global__ void __launch_bounds__(FS_THREADS) k_forces_scan(ib_membrane m, const double* X, float* F, IbArgs a) {
     if (blockIdx.x == 0)
         scan_block(a, false);
     else
-        forces_block(m, X, F, a.rec, a.blkmax, (int64_t)blockIdx.x - 1);
+        forces_block<CONS>(m, X, F, a.rec, a.blkmax, (int64_t)blockIdx.x - 1);
 }
 
 // The coupled step's first launch: the binning of the nodes by position (workgroups
 // [0, nbb), dispatched first: theirs is the longer dependent chain), the bodies' areas and
 // volumes for the constraints (the next nbd, one per body) and the hinge forces (the rest);
 // the binning depends on neither.
+template <bool CONS>
 __global__ void __launch_bounds__(256) k_hinges_bin(ib_membrane m, const double* X, IbArgs a, int64_t nbb,
                                                     int64_t nbd) {
     const int64_t blk = blockIdx.x;
     if (blk < nbb) {
         bin_block(a, blk, false);
-    } else if (blk < nbb + nbd) {
-        body_block(m, X, m.body_now, blk - nbb);
+    } else if (CONS && blk < nbb + nbd) {
+        body_block(m, X, m.body_now, blk - nbb, true);
     } else {
         const int64_t h = (blk - nbb - nbd) * blockDim.x + threadIdx.x;
         if (h < m.nh) hinge_one(m, X, h);
@@ -1087,7 +1105,7 @@ hipError_t launch_membrane_rest(const ib_membrane* m, const double* X_rest, hipS
     k_mem_rest<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(*m, X_rest);
     if (m->tri && m->nt > 0 && m->nb > 0) {
         k_tri_rest<<<dim3((unsigned)((m->nt + 255) / 256)), dim3(256), 0, s>>>(*m, X_rest);
-        k_mem_bodies<<<dim3((unsigned)m->nb), dim3(BODY_THREADS), 0, s>>>(*m, X_rest, m->rest_body);
+        k_mem_bodies<<<dim3((unsigned)m->nb), dim3(BODY_THREADS), 0, s>>>(*m, X_rest, m->rest_body, false);
     }
     if (m->hinge_ptr && m->nh > 0) {
         const int64_t nnz = 4 * m->nh;
@@ -1100,9 +1118,13 @@ hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* 
     if (m->n <= 0) return hipSuccess;
     if (m->hinge_ptr && m->k_bend != 0.0 && m->nh > 0)
         k_mem_hinges<<<dim3((unsigned)((m->nh + 255) / 256)), dim3(256), 0, s>>>(*m, X);
-    if (constraints_on(*m))
-        k_mem_bodies<<<dim3((unsigned)m->nb), dim3(BODY_THREADS), 0, s>>>(*m, X, m->body_now);
-    k_mem_forces<<<dim3((unsigned)((8 * m->n + 255) / 256)), dim3(256), 0, s>>>(*m, X, F);
+    const dim3 gf((unsigned)((8 * m->n + 255) / 256)), bf(256);
+    if (constraints_on(*m)) {
+        k_mem_bodies<<<dim3((unsigned)m->nb), dim3(BODY_THREADS), 0, s>>>(*m, X, m->body_now, true);
+        k_mem_forces<true><<<gf, bf, 0, s>>>(*m, X, F);
+    } else {
+        k_mem_forces<false><<<gf, bf, 0, s>>>(*m, X, F);
+    }
     return hipGetLastError();
 }
 
@@ -1113,12 +1135,17 @@ hipError_t launch_forces_scatter(lbm_ctx* c, const ib_membrane* m, const double*
     const int64_t nbh = hinges ? (m->nh + 255) / 256 : 0;
     const int64_t nbb = (a.n + 255) / 256;
     const int64_t nbd = constraints_on(*m) ? m->nb : 0;
-    if (nbh + nbb + nbd > 0)
-        k_hinges_bin<<<dim3((unsigned)(nbh + nbb + nbd)), dim3(256), 0, c->stream>>>(*m, X, a, nbb, nbd);
+    if (nbd > 0)
+        k_hinges_bin<true><<<dim3((unsigned)(nbh + nbb + nbd)), dim3(256), 0, c->stream>>>(*m, X, a, nbb, nbd);
+    else if (nbh + nbb > 0)
+        k_hinges_bin<false><<<dim3((unsigned)(nbh + nbb)), dim3(256), 0, c->stream>>>(*m, X, a, nbb, 0);
     const int64_t nbf = (8 * m->n + FS_THREADS - 1) / FS_THREADS;
     a.blkmax_n = nbf;
     a.scale_in_scatter = 1;
-    k_forces_scan<<<dim3((unsigned)(1 + nbf)), dim3(FS_THREADS), 0, c->stream>>>(*m, X, F, a);
+    if (nbd > 0)
+        k_forces_scan<true><<<dim3((unsigned)(1 + nbf)), dim3(FS_THREADS), 0, c->stream>>>(*m, X, F, a);
+    else
+        k_forces_scan<false><<<dim3((unsigned)(1 + nbf)), dim3(FS_THREADS), 0, c->stream>>>(*m, X, F, a);
     const int64_t nbs = nbb > 0 ? nbb : 1;  // the first workgroup sets the scale, also with no nodes
     k_ib_scatter<<<dim3((unsigned)nbs), dim3(256), 0, c->stream>>>(a);
     return hipGetLastError();

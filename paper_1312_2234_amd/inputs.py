@@ -184,6 +184,16 @@ def with_constraints(b, k_area_global=0.0, k_area_local=0.0, k_volume=0.0):
                                k_volume=float(k_volume))
 
 
+def table2_constraint_coefficients():
+    """k_s, k_t, k_v of Table 2 (6000 k_B T / l_0^2, 6000 k_B T / l_0^2, 6000 k_B T / l_0^3) in
+    lattice units: spacing h = 0.2 um and step dt = 1e-8 s (section 3.3), plasma density
+    1.0239 g/cm^3, T = 300 K and l_0 = 75 nm (Table 2).  Energy unit rho h^5 / dt^2."""
+    h, dt, rho = 0.2e-6, 1e-8, 1023.9
+    kT = 1.380649e-23 * 300.0 / (rho * h ** 5 / dt ** 2)
+    l0 = 75e-9 / h
+    return 6000.0 * kT / l0 ** 2, 6000.0 * kT / l0 ** 2, 6000.0 * kT / l0 ** 3
+
+
 def morton_order(V, bits=10):
     """Permutation that numbers points along a Morton (Z-order) curve of their position, so
     that nodes with nearby numbers are nearby in space."""

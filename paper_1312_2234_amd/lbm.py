@@ -499,7 +499,7 @@ class Membrane:
             nb = len(toff) - 1
             ra = torch.zeros(len(tri), dtype=torch.float64, device=dev)
             rb = torch.zeros(2 * nb, dtype=torch.float64, device=dev)
-            bn = torch.zeros(2 * nb, dtype=torch.float64, device=dev)
+            bn = torch.zeros(4 * nb, dtype=torch.float64, device=dev)
             self._keep += [ra, rb, bn]
             s.tri, s.nt, s.tri_ptr, s.tri_inc = t_d.data_ptr(), len(tri), tp_d.data_ptr(), ti_d.data_ptr()
             s.tri_body, s.body_tri, s.nb = tb_d.data_ptr(), bt_d.data_ptr(), nb

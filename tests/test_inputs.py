@@ -111,3 +111,33 @@ def test_log_log_interpolation():
     assert abs(_interp_log_value(xs, [1e5, 5e4, 2e4], 160) - 5e4) < 1e-6
     w = np.arange(4 * 6, dtype=float).reshape(4, 6)
     assert np.array_equal(_patch_mean(w, (2, 3)), np.array([[3.5, 5.5, 7.5], [15.5, 17.5, 19.5]]))
+
+
+def test_table2_constraint_coefficients_in_lattice_units():
+    """Table 2's k_s = k_t = 6000 k_B T / l_0^2 and k_v = 6000 k_B T / l_0^3 taken to SI (N/m and
+    N/m^2 at 300 K, l_0 = 75 nm) and divided by the lattice units of stiffness rho h^3 / dt^2 and
+    rho h^2 / dt^2 (h = 0.2 um, dt = 1e-8 s, rho = 1023.9 kg/m^3)."""
+    ks, kt, kv = inputs.table2_constraint_coefficients()
+    kT = 1.380649e-23 * 300
+    ks_si, kv_si = 6000 * kT / 75e-9 ** 2, 6000 * kT / 75e-9 ** 3
+    assert abs(ks - ks_si / (1023.9 * 0.2e-6 ** 3 / 1e-16)) < 1e-12 * ks
+    assert ks == kt
+    assert abs(kv - kv_si / (1023.9 * 0.2e-6 ** 2 / 1e-16)) < 1e-12 * kv
+    assert abs(kv / ks - 0.2e-6 / 75e-9) < 1e-12
+
+
+def test_with_constraints_triangles_are_outward_and_complete():
+    """Every body's triangles close its surface (each edge in exactly two triangles, opposite
+    directions) with positive volume, and the offsets partition the triangle list."""
+    ch = inputs.shear_platelets(seed=1, nx=64, ny=32, nz=48, count=2, nodes=642)
+    b = inputs.with_constraints(ch.bodies, 0.1, 0.1, 0.1)
+    assert b.tri_offsets[0] == 0 and b.tri_offsets[-1] == len(b.triangles)
+    X = b.X.T
+    for (lo, hi), (n0, n1) in zip(zip(b.tri_offsets[:-1], b.tri_offsets[1:]), zip(b.body_offsets[:-1], b.body_offsets[1:])):
+        T = b.triangles[lo:hi]
+        assert T.min() >= n0 and T.max() < n1
+        directed = np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]])
+        assert len({tuple(e) for e in directed}) == len(directed)            # each directed edge once
+        assert {tuple(e) for e in directed} == {tuple(e[::-1]) for e in directed}  # and its reverse too
+        a, c, d = X[T[:, 0]], X[T[:, 1]], X[T[:, 2]]
+        assert np.einsum("ij,ij->i", a, np.cross(c, d)).sum() > 0
