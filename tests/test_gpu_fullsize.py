@@ -1,8 +1,12 @@
 """Parity at the benchmark's full sizes, in the launch configuration the benchmark times
 (launch shape from the tuned cache, steps replayed from a 2-step HIP graph), against the
-FP64 oracle on every cell: the 256x128x128 shear channel with 16 platelets of 2562 nodes,
-and the 64-channel batch (17.8 M cells, 0.46 M nodes).  Tolerances as in test_gpu_parity:
-velocity e_max <= 1e-5, interpolated velocities likewise, wall stress 1e-4."""
+FP64 oracle on every cell: the 256x128x128 shear channel with 16 platelets of 2562 nodes
+(with halfway walls, with the on-site walls of Eq. 23-30, and with the area and volume
+constraints of Eq. 4-5 at Table 2's coefficients), and the 64-channel batch (18.2 M cells,
+0.50 M nodes).  Tolerances as in test_gpu_parity: velocity e_max <= 1e-5, interpolated
+velocities likewise, wall stress 1e-4."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -34,15 +38,25 @@ def gpu_bench_config(gpu, channels, steps):
     return g, N(X), N(U), offs
 
 
-def test_full_shear_workload_against_oracle(orc, gpu):
+def shear_workload(variant):
     ch = inputs.shear_platelets(seed=0)
+    if variant == "onsite":
+        ch = dataclasses.replace(ch, walls="onsite")
+    if variant == "constrained":
+        ch = dataclasses.replace(ch, bodies=inputs.with_constraints(ch.bodies, *inputs.table2_constraint_coefficients()))
+    return ch
+
+
+@pytest.mark.parametrize("variant", ["halfway", "onsite", "constrained"])
+def test_full_shear_workload_against_oracle(orc, gpu, variant):
+    ch = shear_workload(variant)
     steps = 4
     g, Xg, Ug, _ = gpu_bench_config(gpu, [ch], steps)
     o, Xo, Uo = run_oracle_coupled(orc, ch, "cos", steps)
     drho, v = g.moments_channel(0)
     e = emax(N(v), o.moments()[1])
     eu = emax(Ug, Uo)
-    print("full shear, %d steps: velocity e_max %.3e, node velocity %.3e" % (steps, e, eu))
+    print("full shear (%s), %d steps: velocity e_max %.3e, node velocity %.3e" % (variant, steps, e, eu))
     assert e <= TOL32 and eu <= TOL32
     assert np.abs(Xg - Xo).max() <= TOL32 * np.abs(Uo).max() * steps
     lo_g, _ = g.wall_stress()
