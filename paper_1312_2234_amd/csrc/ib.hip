@@ -657,17 +657,21 @@ __global__ void __launch_bounds__(512) k_ib_vel(IbArgs a) {
 }
 
 // U_m = sum over the stencil of v(x) phi phi phi, rows inside a wall taking the wall
-// velocity; optionally X_out = X + U.  Sixteen lanes per node: lane (b, c) takes stencil
-// row y = base_y + b, z = base_z + c and its four x cells; the 16 partial sums are
-// combined by a fixed butterfly, so the result does not depend on scheduling.
-template <class St>
+// velocity; optionally X_out = X + U.  GL lanes per node (4 or 2): lane l takes the stencil
+// rows q = l, l + GL, ... (y = base_y + q % 4, z = base_z + q / 4), each with its four x
+// cells; the GL partial sums are combined by a fixed butterfly, so the result does not
+// depend on scheduling.  Few nodes (one wave round or so) gain from more lanes per node,
+// many nodes from more independent loads per lane (the launch picks GL by the node count).
+template <class St, int GL>
 __global__ void __launch_bounds__(256) k_ib_gather(IbArgs a) {
+    static_assert(GL == 2 || GL == 4 || GL == 8 || GL == 16, "lanes per node");
+    constexpr int GR = 16 / GL;  // stencil rows per lane
     using T = typename St::T;
     // consecutive node blocks on the same XCD: neighbouring nodes share tiles in one L2
     const int64_t G = gridDim.x, bx = blockIdx.x, per = G >> 3, rem = G & 7, xcd = bx & 7;
     const int64_t L = xcd * per + (xcd < rem ? xcd : rem) + (bx >> 3);
-    const int64_t m = (L * blockDim.x + threadIdx.x) >> 4;
-    const int sl = threadIdx.x & 15, bq = sl & 3, cq = sl >> 2;
+    const int64_t m = (L * blockDim.x + threadIdx.x) / GL;
+    const int sl = threadIdx.x & (GL - 1);
     float U[3] = {0.f, 0.f, 0.f};
     double X[3] = {0.0, 0.0, 0.0};
     const bool valid = m < a.n;
@@ -707,7 +711,10 @@ __global__ void __launch_bounds__(256) k_ib_gather(IbArgs a) {
             }
         }
         const Chan& ch = a.chan[c];
-        // this lane's stencil row (y index bq, z index cq), selected without dynamic indexing
+#pragma unroll
+        for (int rr = 0; rr < GR; ++rr) {
+        const int q = sl + GL * rr, bq = q & 3, cq = q >> 2;
+        // this stencil row (y index bq, z index cq), its weights selected without dynamic indexing
         const float wy = bq == 0 ? w[1][0] : (bq == 1 ? w[1][1] : (bq == 2 ? w[1][2] : w[1][3]));
         const float wz = cq == 0 ? w[2][0] : (cq == 1 ? w[2][1] : (cq == 2 ? w[2][2] : w[2][3]));
         const float wyz = wy * wz;
@@ -766,9 +773,10 @@ __global__ void __launch_bounds__(256) k_ib_gather(IbArgs a) {
             U[1] += ww * v1;
             U[2] += ww * v2;
         }
+        }
     }
 #pragma unroll
-    for (int d = 1; d < 16; d <<= 1) {
+    for (int d = 1; d < GL; d <<= 1) {
         U[0] += __shfl_xor(U[0], d, 64);
         U[1] += __shfl_xor(U[1], d, 64);
         U[2] += __shfl_xor(U[2], d, 64);
@@ -786,7 +794,15 @@ static void launch_interp_typed(lbm_ctx* c, const IbArgs& a) {
     int64_t g = c->max_slots < c->ib_grid / 2 ? c->max_slots : c->ib_grid / 2;
     if (g < 1) g = 1;
     k_ib_vel<St><<<dim3((unsigned)g), dim3(512), 0, c->stream>>>(a);
-    if (a.n > 0) k_ib_gather<St><<<dim3((unsigned)((16 * a.n + 255) / 256)), dim3(256), 0, c->stream>>>(a);
+    // lanes per node by the node count (measured on 20k, 41k and 0.5 M nodes): 16 while even
+    // that is under one round of waves (32768 nodes), 4 up to about one round at 4 lanes
+    // (131072 nodes), 2 beyond
+    if (a.n > 131072)
+        k_ib_gather<St, 2><<<dim3((unsigned)((2 * a.n + 255) / 256)), dim3(256), 0, c->stream>>>(a);
+    else if (a.n > 32768)
+        k_ib_gather<St, 4><<<dim3((unsigned)((4 * a.n + 255) / 256)), dim3(256), 0, c->stream>>>(a);
+    else if (a.n > 0)
+        k_ib_gather<St, 16><<<dim3((unsigned)((16 * a.n + 255) / 256)), dim3(256), 0, c->stream>>>(a);
 }
 
 hipError_t launch_ib_interp(lbm_ctx* c, const IbArgs& a) {
