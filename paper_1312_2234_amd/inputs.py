@@ -318,6 +318,20 @@ def shear_platelets(seed=0, nx=256, ny=128, nz=128, count=16, nodes=2562, semi_a
     return Channel(nx, ny, nz, tau, u_wall_hi=(u_top, 0.0, 0.0), init="shear", bodies=b)
 
 
+def jeffery_platelet(n=64, nodes=642, semi_axes=(6.0, 2.0, 6.0), u_top=0.05, tau=1.0, seed=0,
+                     k_spring=0.005, k_bend=1e-4):
+    """Jeffery-orbit workload (section 4.1): an n x n x n shear channel (moving top wall,
+    resting bottom wall, linear Couette start) with one oblate platelet, short axis along y,
+    at its centre, as far from the walls as the box allows."""
+    a = np.asarray(semi_axes, float)
+    V = _topology(nodes)[0]
+    c = np.array([(n - 1) / 2.0, (n - 1) / 2.0, (n - 1) / 2.0])
+    X, E, H, O = _concat([(V * a[None, :] + c[None, :], nodes)])
+    b = Bodies(X=X, X_rest=X.copy(), edges=E, hinges=H, anchors=None, k_spring=k_spring, k_bend=k_bend,
+               body_offsets=O)
+    return Channel(n, n, n, tau, u_wall_hi=(u_top, 0.0, 0.0), init="shear", bodies=b)
+
+
 def _suspension_centres(seed, count, fine, semi_axes, y_band):
     rng = np.random.default_rng(seed)
     nx, ny, nz = fine

@@ -141,3 +141,28 @@ def test_with_constraints_triangles_are_outward_and_complete():
         assert {tuple(e) for e in directed} == {tuple(e[::-1]) for e in directed}  # and its reverse too
         a, c, d = X[T[:, 0]], X[T[:, 1]], X[T[:, 2]]
         assert np.einsum("ij,ij->i", a, np.cross(c, d)).sum() > 0
+
+
+def test_director_tracker_counts_half_turns():
+    """A director turning clockwise (seen from +z) at a varying rate, sampled coarsely and
+    with random sign flips: the tracker's pi-crossings match the analytic crossing times."""
+    import math
+
+    from paper_1312_2234_amd.experiments import DirectorTracker, jeffery_period
+
+    rng = np.random.default_rng(5)
+    r, g = 1 / 3, 1e-3
+    T = jeffery_period(r, g)
+    # Jeffery's orbit of the director: tan(phi) = r tan(w t) with w = 2 pi / T (clockwise phi)
+    def axis(t):
+        phi = math.atan2(r * math.sin(2 * math.pi * t / T), math.cos(2 * math.pi * t / T))
+        v = np.array([math.sin(phi), math.cos(phi), 0.0])   # starts along +y, turns clockwise
+        return v if rng.random() < 0.5 else -v
+    tr = DirectorTracker(axis(0.0))
+    chunk = 50
+    for k in range(1, int(1.6 * T / chunk)):
+        tr.update(axis(k * chunk), k * chunk, chunk)
+    # the director passes phi = pi/2 + m pi at t = T/4 + m T/2 ... and phi = m pi at t = m T/2
+    assert len(tr.marks) == 3
+    for m, t in enumerate(tr.marks, start=1):
+        assert abs(t - m * T / 2) < 0.02 * T
