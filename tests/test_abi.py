@@ -94,3 +94,38 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120, cwd=root)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_ctypes_structs_match_the_c_layout(tmp_path):
+    """The binding's ctypes mirrors of lbm_params, lbm_launch and ib_membrane have the C
+    header's field offsets and sizes (a C program built against include/lbm.h prints them)."""
+    import subprocess
+
+    from paper_1312_2234_amd import lbm
+
+    structs = {"lbm_params": lbm.LbmParams, "lbm_launch": lbm.LbmLaunch, "ib_membrane": lbm.IbMembrane}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append('    printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in cls._fields_:
+            lines.append('    printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines())
+    for cname, cls in structs.items():
+        assert int(got[cname]) == C.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got["%s.%s" % (cname, f)]) == getattr(cls, f).offset, (cname, f)
+
+
+def test_wall_kinds_validated_on_host():
+    from paper_1312_2234_amd import lbm
+
+    L = lbm.lib()
+    assert L.lbm_workspace_bytes(_params(walls=2), 1, 0, 0) > 0          # on-site walls
+    assert L.lbm_workspace_bytes(_params(walls=3), 1, 0, 0) == 0         # unknown wall kind
+    assert L.lbm_workspace_bytes(_params(walls=2, ny=2), 1, 0, 0) == 0   # two wall rows, no fluid row
+    assert L.lbm_workspace_bytes(_params(walls=1, ny=2), 1, 0, 0) > 0
