@@ -179,6 +179,11 @@ def with_constraints(b, k_area_global=0.0, k_area_local=0.0, k_volume=0.0):
         Tb = _topology(hi - lo)[1] + lo
         T.append(Tb)
         offs.append(offs[-1] + len(Tb))
+    # the triangles must be those of the bodies' own meshes: their edges are the spring edges
+    tri_edges = mesh_edges(np.concatenate(T))
+    springs = np.unique(np.sort(np.asarray(b.edges, np.int64), axis=1), axis=0)
+    if len(b.edges) == 0 or not np.array_equal(tri_edges.astype(np.int64), springs):
+        raise ValueError("with_constraints needs bodies built from the sphere meshes (platelets)")
     return dataclasses.replace(b, triangles=np.concatenate(T).astype(np.int32), tri_offsets=offs,
                                k_area_global=float(k_area_global), k_area_local=float(k_area_local),
                                k_volume=float(k_volume))

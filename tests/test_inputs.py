@@ -1,5 +1,6 @@
 """Seeded workload generators: mesh sizes, topology, placement rules, determinism."""
 import numpy as np
+import pytest
 
 from paper_1312_2234_amd import inputs
 
@@ -166,3 +167,10 @@ def test_director_tracker_counts_half_turns():
     assert len(tr.marks) == 3
     for m, t in enumerate(tr.marks, start=1):
         assert abs(t - m * T / 2) < 0.02 * T
+
+
+def test_with_constraints_rejects_bodies_of_other_meshes():
+    rng = np.random.default_rng(0)
+    t = inputs.tethered_sphere(rng, (16, 10, 16), 4.0, 642, 0.01, 0.1)
+    with pytest.raises(ValueError):
+        inputs.with_constraints(t, 0.1, 0.1, 0.1)
