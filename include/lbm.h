@@ -190,7 +190,8 @@ typedef struct {
     double* rest_cs;           /* [nh][2] cos and sin of the rest dihedral angle */
     int32_t* hinge_slot;       /* [nh][4] scratch: position of (hinge, role) in hinge_inc (set by
                                   ib_membrane_rest) */
-    double* hinge_force;       /* [nh*4][3] scratch: bending force of each incidence, CSR order */
+    float* hinge_force;        /* [nh*4][3] scratch: bending force of each incidence, CSR order
+                                  (FP64 arithmetic, stored as FP32; the node sum is FP64) */
     int64_t nh;
     double k_bend;
     const double* anchors;     /* [3][n] tether anchors, or NULL */

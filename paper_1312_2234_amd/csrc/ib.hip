@@ -904,7 +904,7 @@ __device__ __forceinline__ void hinge_one(const ib_membrane& m, const double* X,
     hinge(x, gr, true, c, sn);
     const double dE = m.k_bend * (sn * m.rest_cs[2 * h] - c * m.rest_cs[2 * h + 1]);
     for (int k = 0; k < 4; ++k) {
-        double* out = m.hinge_force + 3 * (int64_t)m.hinge_slot[4 * h + k];
+        float* out = m.hinge_force + 3 * (int64_t)m.hinge_slot[4 * h + k];
         for (int d = 0; d < 3; ++d) out[d] = -dE * gr[k][d];
     }
 }
@@ -1014,7 +1014,7 @@ __device__ __forceinline__ void forces_block(const ib_membrane& m, const double*
     }
     if (valid && m.hinge_ptr && m.k_bend != 0.0) {
         for (int e = m.hinge_ptr[i] + sl; e < m.hinge_ptr[i + 1]; e += 8) {
-            const double* hf = m.hinge_force + 3 * (int64_t)e;
+            const float* hf = m.hinge_force + 3 * (int64_t)e;
             F[0] += hf[0]; F[1] += hf[1]; F[2] += hf[2];
         }
     }

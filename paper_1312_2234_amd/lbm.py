@@ -475,7 +475,7 @@ class Membrane:
             hp, hi = inputs.csr_hinges(n, bodies.hinges)
             hpt, hit, ht = dev_i32(hp), dev_i32(hi), dev_i32(bodies.hinges.reshape(-1))
             rt = torch.zeros(2 * len(bodies.hinges), dtype=torch.float64, device=dev)
-            hf = torch.zeros(12 * len(bodies.hinges), dtype=torch.float64, device=dev)
+            hf = torch.zeros(12 * len(bodies.hinges), dtype=torch.float32, device=dev)
             hs = torch.zeros(4 * len(bodies.hinges), dtype=torch.int32, device=dev)
             self._keep += [rt, hf, hs]
             s.hinge_ptr, s.hinge_inc, s.hinges, s.rest_cs = hpt.data_ptr(), hit.data_ptr(), ht.data_ptr(), rt.data_ptr()
