@@ -162,6 +162,7 @@ IbArgs ib_args(lbm_ctx* c, int set) {
     a.blkmax = c->d_blkmax;
     a.blkmax_n = (c->n_nodes + 255) / 256;
     a.max_items = c->max_items;
+    a.chunk = SP_CHUNK;
     return a;
 }
 
@@ -553,6 +554,8 @@ static lbm_status coupled(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, doub
         // fused update.
         const bool split_update =
             m && !ov && !c->closure && (c->launch.split == 1 || (c->launch.split == -1 && c->nch == 1));
+        // longer spread work items only where the lattice update is long enough to hide them
+        if (split_update && c->total_cells >= SP_SPLIT_MIN_CELLS) a.chunk = SP_CHUNK_SPLIT;
         if (m) {
             // the binning and the scan need only X: they run beside the hinge and node forces,
             // and the force kernel fills in what the spread needs of F

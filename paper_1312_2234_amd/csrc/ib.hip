@@ -320,11 +320,12 @@ __device__ __forceinline__ void scan_block(const IbArgs& a, bool with_scale) {
     if (tid < 3) carry[tid] = 0;
     __syncthreads();  // every thread has read the other set's count before it is reset below
     // three exclusive prefixes over the flagged tiles: list offsets (node count), spread
-    // work items (chunks of SP_CHUNK nodes) and the partial blocks of split tiles
+    // work items (chunks of a.chunk nodes) and the partial blocks of split tiles
     for (int base = 0; base < nf; base += blockDim.x) {
         const int k = base + tid;
         const int v = k < nf ? a.set.cnt[a.set.flag_list[k]] : 0;
-        const int nch = k < nf ? (v > SP_CHUNK ? (v + SP_CHUNK - 1) / SP_CHUNK : 1) : 0;
+        const int ck = a.chunk;
+        const int nch = k < nf ? (v > ck ? (v + ck - 1) / ck : 1) : 0;
         const int val[3] = {v, nch, nch > 1 ? nch : 0};
         int incl[3], excl[3];
 #pragma unroll
@@ -394,7 +395,7 @@ __global__ void __launch_bounds__(256) k_ib_scatter(IbArgs a) {
 }
 
 // ---------------------------------------------------------------- spread (LDS, fixed point)
-// Work item = one chunk of up to SP_CHUNK nodes of a flagged 8x8x8 tile's node list.  The
+// Work item = one chunk of up to a.chunk nodes of a flagged 8x8x8 tile's node list.  The
 // chunk's node records are staged in LDS; then each wavefront takes one node at a time with
 // lane = stencil point (x = lane & 3, y = (lane >> 2) & 3, z = lane >> 4): the lanes whose
 // cell lies in the tile (and not inside a wall) add w_x w_y w_z F to a 64-bit fixed-point
@@ -403,7 +404,7 @@ __global__ void __launch_bounds__(256) k_ib_scatter(IbArgs a) {
 // kernel adds the tile's blocks and writes the force block.  Integer sums are exact, so the
 // result does not depend on the order in which nodes were listed or chunks ran.
 constexpr int SP_THREADS = 512;   // 8 wavefronts per work item (four work items per CU)
-constexpr int SP_BATCH = 256;     // node records staged at a time (>= SP_CHUNK)
+constexpr int SP_BATCH = 256;     // node records staged at a time (a chunk is spread in batches)
 
 __device__ __forceinline__ unsigned fixed_round(float c, float scale) {
     // round-to-nearest-even of c * scale (a power of two: the product is exact) for
@@ -440,8 +441,8 @@ __device__ __forceinline__ void spread_items(const IbArgs& a, int64_t first, int
         if (nch > 1 && bigid < 0 && c != 0) continue;  // no accumulator left: chunk 0 takes the list
         int64_t beg = a.set.slot_off[slot], end = a.set.slot_off[slot + 1];
         if (split) {
-            beg += (int64_t)c * SP_CHUNK;
-            if (end > beg + SP_CHUNK) end = beg + SP_CHUNK;
+            beg += (int64_t)c * a.chunk;
+            if (end > beg + a.chunk) end = beg + a.chunk;
         }
         if (end > a.list_cap) end = a.list_cap;
         for (int k = tid; k < 3 * TILE_CELLS; k += SP_THREADS) {

@@ -39,6 +39,14 @@ struct IbSet {
 // tile stores its exact fixed-point partial sums in one of `part_cap` partial blocks, and a
 // merge kernel adds them up.
 constexpr int SP_CHUNK = 256;
+// Chunk of the split coupled step: there the spread runs hidden under the lattice update, and
+// fewer split tiles leave less merging to the flagged-tile update (results are the same exact
+// integer sums whatever the chunking).  Capacities are sized for SP_CHUNK, the smaller one.
+constexpr int SP_CHUNK_SPLIT = 1024;
+// ... used from this many cells on: on the 0.5 M-cell coarse twin the update (15 us) cannot
+// hide the longer items (step 77.5 -> 99.2 us), on the 4.2 M-cell shear channel it can
+// (185.6 -> 182.3 us)
+constexpr int64_t SP_SPLIT_MIN_CELLS = int64_t(1) << 21;
 // Binning: per-block LDS hash of tile counts (HS entries).
 constexpr int HS_BITS = 9;
 constexpr int HS = 1 << HS_BITS;
@@ -103,6 +111,7 @@ struct IbArgs {
     int32_t scale_in_scatter;  // the scatter's first workgroup sets the scale (not the scan)
     int32_t* item_slot;     // [max_items] slot of each spread work item
     int64_t max_items;
+    int32_t chunk;          // nodes per spread work item: SP_CHUNK, or SP_CHUNK_SPLIT
 };
 
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
