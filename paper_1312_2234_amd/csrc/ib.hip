@@ -633,14 +633,16 @@ template <class St>
 __global__ void __launch_bounds__(512) k_ib_vel(IbArgs a) {
     using T = typename St::T;
     const int nf = a.set.hdr->nflag;
-    for (int slot = blockIdx.x; slot < nf; slot += gridDim.x) {
+    constexpr int PART = TILE_CELLS / TILE_PARTS;  // cells of a tile per workgroup
+    const int part = (int)(blockIdx.x % TILE_PARTS);
+    for (int slot = blockIdx.x / TILE_PARTS; slot < nf; slot += gridDim.x / TILE_PARTS) {
         const int T_ = a.set.flag_list[slot];
         const Chan& ch = a.chan[a.set.flag_ch[slot]];
         const int t = (int)(T_ - ch.tile_off);
         const int ox = (t % ch.tnx) * TILE, oy = ((t / ch.tnx) % ch.tny) * TILE, oz = (t / (ch.tnx * ch.tny)) * TILE;
         const float* fb = a.force + (int64_t)slot * (3 * TILE_CELLS);
         float4* vb = (float4*)(a.vel + (int64_t)slot * (4 * TILE_CELLS));
-        for (int l = threadIdx.x; l < TILE_CELLS; l += blockDim.x) {
+        for (int l = part * PART + threadIdx.x; l < (part + 1) * PART; l += blockDim.x) {
             const int x = ox + (l & 7), y = oy + ((l >> 3) & 7), z = oz + (l >> 6);
             if (x >= ch.nx || y >= ch.ny || z >= ch.nz) continue;
             const int32_t n = x + ch.nx * (y + ch.ny * z);
@@ -794,7 +796,7 @@ template <class St>
 static void launch_interp_typed(lbm_ctx* c, const IbArgs& a) {
     int64_t g = c->max_slots < c->ib_grid / 2 ? c->max_slots : c->ib_grid / 2;
     if (g < 1) g = 1;
-    k_ib_vel<St><<<dim3((unsigned)g), dim3(512), 0, c->stream>>>(a);
+    k_ib_vel<St><<<dim3((unsigned)(g * TILE_PARTS)), dim3(TILE_CELLS / TILE_PARTS), 0, c->stream>>>(a);
     // lanes per node by the node count (measured on 20k, 41k and 0.5 M nodes): 16 while even
     // that is under one round of waves (32768 nodes), 4 up to about one round at 4 lanes
     // (131072 nodes), 2 beyond

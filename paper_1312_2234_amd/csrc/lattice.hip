@@ -49,8 +49,8 @@ __global__ void __launch_bounds__(1024) k_step(LatArgs a) {
     });
 }
 
-// The same update for the cells of the flagged IB tiles only (one workgroup of 512 threads
-// per tile, one cell per thread), with their force.  Used after a full update with the body
+// The same update for the cells of the flagged IB tiles only (TILE_PARTS workgroups per tile,
+// one cell per thread), with their force.  Used after a full update with the body
 // force alone: it overwrites exactly the cells whose IB force may be nonzero, with the
 // values the fused update produces.  MERGE: a tile spread in several work items has only
 // partial fixed-point blocks yet; this cell's sums are added here (as the merge kernel adds
@@ -59,8 +59,8 @@ template <class St, bool MERGE>
 __global__ void __launch_bounds__(TILE_CELLS) k_step_tiles(LatArgs a) {
     using T = typename St::T;
     const int nf = a.hdr->nflag;
-    const int l = threadIdx.x;
-    for (int slot = blockIdx.x; slot < nf; slot += gridDim.x) {
+    const int l = threadIdx.x + (int)(blockIdx.x % TILE_PARTS) * (TILE_CELLS / TILE_PARTS);
+    for (int slot = blockIdx.x / TILE_PARTS; slot < nf; slot += gridDim.x / TILE_PARTS) {
         float f3[3];
         const int bigid = MERGE ? a.big[slot] : -1;
         if (MERGE && bigid >= 0) {
@@ -498,7 +498,7 @@ static void launch_tiles_typed(lbm_ctx* c, const LatArgs& a, bool merge, dim3 gr
 hipError_t launch_step_tiles(lbm_ctx* c, const LatArgs& a, bool merge) {
     int64_t g = c->max_slots < c->ib_grid ? c->max_slots : c->ib_grid;
     if (g < 1) g = 1;
-    const dim3 grid((unsigned)g), block(TILE_CELLS);
+    const dim3 grid((unsigned)(g * TILE_PARTS)), block(TILE_CELLS / TILE_PARTS);
     with_storage(c, [&](auto st) { launch_tiles_typed<decltype(st)>(c, a, merge, grid, block); });
     return hipGetLastError();
 }

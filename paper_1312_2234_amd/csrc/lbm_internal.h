@@ -38,6 +38,10 @@ struct IbSet {
 // Spreading splits a tile's node list into chunks of SP_CHUNK nodes; each chunk of a split
 // tile stores its exact fixed-point partial sums in one of `part_cap` partial blocks, and a
 // merge kernel adds them up.
+// The kernels that walk the flagged tiles cell by cell (flagged-tile update, velocity blocks)
+// give each tile TILE_PARTS workgroups of TILE_CELLS / TILE_PARTS threads: a few hundred tiles
+// then reach every CU.
+constexpr int TILE_PARTS = 2;
 constexpr int SP_CHUNK = 256;
 // Chunk of the split coupled step: there the spread runs hidden under the lattice update, and
 // fewer split tiles leave less merging to the flagged-tile update (results are the same exact
