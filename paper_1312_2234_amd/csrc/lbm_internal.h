@@ -39,9 +39,11 @@ struct IbSet {
 // tile stores its exact fixed-point partial sums in one of `part_cap` partial blocks, and a
 // merge kernel adds them up.
 // The kernels that walk the flagged tiles cell by cell (flagged-tile update, velocity blocks)
-// give each tile TILE_PARTS workgroups of TILE_CELLS / TILE_PARTS threads: a few hundred tiles
-// then reach every CU.
-constexpr int TILE_PARTS = 2;
+// give each tile TILE_PARTS workgroups of TILE_CELLS / TILE_PARTS threads (one wavefront
+// each): a few hundred tiles then spread over every CU and XCD.  Measured on the shear
+// channel's 219 tiles, tile update / velocity blocks: 1 part 14.0 / 10.3 us, 2 parts
+// 13.3 / 9.9, 4 parts 12.4 / 9.5, 8 parts 10.3 / 8.9.
+constexpr int TILE_PARTS = 8;
 constexpr int SP_CHUNK = 256;
 // Chunk of the split coupled step: there the spread runs hidden under the lattice update, and
 // fewer split tiles leave less merging to the flagged-tile update (results are the same exact
