@@ -129,3 +129,26 @@ def test_wall_kinds_validated_on_host():
     assert L.lbm_workspace_bytes(_params(walls=3), 1, 0, 0) == 0         # unknown wall kind
     assert L.lbm_workspace_bytes(_params(walls=2, ny=2), 1, 0, 0) == 0   # two wall rows, no fluid row
     assert L.lbm_workspace_bytes(_params(walls=1, ny=2), 1, 0, 0) > 0
+
+
+def test_bench_workloads_build():
+    """Every workload bench.py names builds on the host with the shape its description states."""
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    chans, desc = bench.make_workload("shear")
+    assert (chans[0].nx, chans[0].ny, chans[0].nz) == (256, 128, 128) and chans[0].bodies.n == 16 * 2562
+    assert chans[0].walls is True and chans[0].bodies.triangles is None
+    chans, desc = bench.make_workload("shear_onsite")
+    assert chans[0].walls == "onsite" and "on-site" in desc
+    chans, desc = bench.make_workload("shear_constrained")
+    b = chans[0].bodies
+    assert b.triangles is not None and len(b.triangles) == 16 * 5120 and b.k_volume > b.k_area_global > 0
+    chans, desc = bench.make_workload("batched")
+    assert len(chans) == 64
+    chans, desc = bench.make_workload("coarse")
+    assert (chans[0].nx, chans[0].ny, chans[0].nz) == (128, 64, 64)
+    with pytest.raises(SystemExit):
+        bench.make_workload("nonexistent")
