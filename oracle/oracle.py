@@ -19,6 +19,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# A prebuilt variant of the same source (the sanitizer build of the tests) may be named here;
+# it is then loaded as is, never rebuilt.
+_LIB_OVERRIDE = os.environ.get("ORACLE_LIB")
 _lib = None
 
 KERNELS = {"cos": 0, "peskin4": 1}
@@ -43,9 +46,12 @@ class _Params(C.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = C.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = C.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            L = C.CDLL(_LIB)
         dp, ip, pp = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(_Params)
         L.orc_feq.argtypes = [C.c_double, dp, dp]
         L.orc_source.argtypes = [C.c_double, dp, dp, dp]

@@ -132,6 +132,29 @@ def test_couette_steady_state_exact(orc):
         assert np.abs(lo[1]).max() < 1e-14
 
 
+def test_forced_stress_of_uniform_accelerating_flow_vanishes(orc):
+    """The Guo term of the stress (Eq. 19's forced scheme, reading R12).  In a periodic box with
+    a uniform state and a uniform body force nothing streams, and the momentum grows by F per
+    step.  The second moment then relaxes to Pi_neq = -(vF + Fv)/2 (the fixed point of
+    Pi_neq' = (1 - 1/tau) Pi_neq - (vF + Fv)/(2 tau) - FF/rho under v' = v + F/rho), so
+    sigma = -(1 - 1/2tau) [Pi_neq + (vF + Fv)/2] is exactly zero.  A dropped or sign-flipped
+    force term leaves (1 - 1/2tau)(F_x v_y + F_y v_x) ~ 1e-7 here."""
+    tau, F = 0.8, (1e-5, 2e-5, -1e-5)
+    L = orc.Lattice(4, 4, 4, tau, walls=False, body=F)
+    u0 = np.broadcast_to(np.array([0.02, 0.01, 0.005])[:, None, None, None], (3, 4, 4, 4)).copy()
+    L.init(u=u0)
+    L.step(200)
+    _, v = L.moments()
+    # j starts at u0 and gains F per step; v = (j + F/2)/rho
+    assert np.abs(v[:, 0, 0, 0] - (u0[:, 0, 0, 0] + 200.5 * np.array(F))).max() < 1e-14
+    lo, hi = L.wall_stress()
+    assert np.abs(lo).max() <= 1e-15 and np.abs(hi).max() <= 1e-15
+    vx, vy, vz = v[:, 0, 0, 0]
+    guo_xy = (1 - 0.5 / tau) * (F[0] * vy + F[1] * vx)
+    guo_zy = (1 - 0.5 / tau) * (F[2] * vy + F[1] * vz)
+    assert min(abs(guo_xy), abs(guo_zy)) > 1e-8  # the term the test pins is not negligible
+
+
 def test_poiseuille_steady_state_exact(orc):
     """Body-force channel: u_x = g/(2 nu) (y+1/2)(ny-1/2-y) + u_s with the BGK bounce-back slip
     u_s = g (16 t^2 - 3)/(8 t), t = tau - 1/2 (vanishes at tau = 1/2 + sqrt(3)/4); nu from Eq. (22)."""
@@ -339,6 +362,22 @@ def test_coupled_step_moves_node_with_force(orc):
     F, U = orc.coupled_step(L, mem, X1)
     assert F[0, 0] > 0 and U[0, 0] > 0 and X1[0, 0] > X[0, 0]
     assert abs(U[1, 0]) < 1e-3 * U[0, 0] and abs(U[2, 0]) < 1e-3 * U[0, 0]
+
+
+def test_coupled_step_advects_force_free_node_with_uniform_flow(orc):
+    """Position update after Eq. (36) (Fig. 1): with no force a uniform flow u0 stays uniform,
+    the interpolation returns u0 by the partition of unity of Eq. (36) and the node moves by
+    exactly n u0 in n steps, across a periodic face too."""
+    for kernel in ("cos", "peskin4"):
+        L = orc.Lattice(8, 8, 8, 0.9, walls=False, kernel=kernel)
+        u0 = np.array([0.03, -0.01, 0.02])
+        L.init(u=np.broadcast_to(u0[:, None, None, None], (3, 8, 8, 8)).copy())
+        X0 = np.array([[3.3, 7.9, 0.05], [4.6, 0.2, 7.99], [2.1, 5.5, 3.0]])
+        X = X0.copy()
+        for n in range(1, 11):
+            F, U = orc.coupled_step(L, None, X)
+            assert np.abs(U - u0[:, None]).max() < 1e-15
+            assert np.abs(X - (X0 + n * u0[:, None])).max() < 1e-13
 
 
 # ----------------------------------------------------------------------------- membrane forces
