@@ -8,10 +8,12 @@ populations).  The step sequence is replayed from a captured HIP graph; inputs a
 in HBM before the timed region starts.
 
 Prints ONE JSON line.  Besides the contract fields it carries:
-  roofline      the lattice kernel (which moves >99% of the bytes): algorithmic bytes per
-                launch (152 B per cell in float32, 76 B in 16-bit) over its average launch
-                time, measured here with HIP events around back-to-back launches on the
-                library's stream, against the 8 TB/s HBM peak;
+  roofline      the coupled step's lattice-update launch (which moves >97% of the bytes: in the
+                single-channel schedule the body-force update of every cell, in the same launch
+                as the IB spread): algorithmic bytes per launch (152 B per cell in float32, 76 B
+                in 16-bit) over its mean duration, timed with HIP events recorded by the library
+                around that launch on its own stream, against the 8 TB/s HBM peak; `step_frac`
+                is the same bytes over the whole step time, i.e. the step's own fraction of peak;
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample of the same workload.
 """
 import argparse
@@ -71,10 +73,15 @@ def make_workload(name):
     raise SystemExit("unknown workload " + name)
 
 
-# Sources of the lattice kernel: a counter summary under profiles/ applies only while they are
+# Sources of the lattice kernels: a counter summary under profiles/ applies only while they are
 # unchanged (their SHA-256 is recorded in the summary).
-KERNEL_SOURCES = ("paper_1312_2234_amd/csrc/lattice.hip", "paper_1312_2234_amd/csrc/lbm_device.h",
-                  "paper_1312_2234_amd/csrc/lbm_internal.h")
+KERNEL_SOURCES = ("paper_1312_2234_amd/csrc/lattice.hip", "paper_1312_2234_amd/csrc/ib.hip",
+                  "paper_1312_2234_amd/csrc/lbm_device.h", "paper_1312_2234_amd/csrc/lbm_internal.h")
+# the launch the library's timer brackets, by the kind it reports
+TIMED_KERNEL = {0: "k_step", 1: "k_spread_far", 2: "k_step_cl"}
+TIMED_KERNEL_DESC = {0: "k_step (fused lattice step with the IB force)",
+                     1: "k_spread_far (body-force lattice update of every cell + the IB spread, one launch)",
+                     2: "k_step_cl (lattice step + learned closure)"}
 
 
 def kernel_sources_sha256():
@@ -85,11 +92,11 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(storage, workload):
-    """HBM bytes per lattice launch from the committed FETCH_SIZE / WRITE_SIZE summary for this
-    storage form and workload (counter readings scaled by the same counters' reading of a plain
-    copy of known size), or None if there is none or the kernel's sources changed since."""
-    path = os.path.join(ROOT, "profiles", "k_step_%s_%s_hbm_counters.md" % (storage, workload))
+def measured_traffic(kernel, storage, workload):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE summary for
+    this storage form and workload (counter readings scaled by the same counters' reading of a
+    plain copy of known size), or None if there is none or the kernel's sources changed since."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_%s_hbm_counters.md" % (kernel, storage, workload))
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -175,7 +182,10 @@ def main():
     ap.add_argument("--cpu-single-steps", type=int, default=4, help="steps of the one-thread oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lbm-only-steps", type=int, default=200)
-    ap.add_argument("--tune", action="store_true", help="re-time the lattice kernel's launch shapes")
+    ap.add_argument("--timer-steps", type=int, default=60,
+                    help="eager coupled steps over which the lattice-update launch is timed")
+    ap.add_argument("--tune", action="store_true",
+                    help="re-time the coupled step over the lattice launch shapes and schedules")
     ap.add_argument("--launch", default=None,
                     help="lattice launch shape as JSON, e.g. '{\"block\": 256, \"xcd_remap\": 0}' (skips the tuner cache)")
     ap.add_argument("--closure", action="store_true",
@@ -199,17 +209,7 @@ def main():
     cells = sum(c.cells for c in channels)
     lat = lbm.Lattice(channels, storage=args.storage, kernel=args.kernel, max_nodes=nodes, device=dev)
     lat.init()
-    from paper_1312_2234_amd import tune
-
-    if args.launch:
-        cfg = dict(tune.DEFAULT, **json.loads(args.launch))
-        lat.set_launch(**cfg)
-    else:
-        tune.apply_cached_or_tune(lat, retune=args.tune)
-    lat.init()
-    if args.closure:
-        lat.set_closure(*closure_weights(torch, dev), 1.0)
-    from paper_1312_2234_amd import inputs
+    from paper_1312_2234_amd import inputs, tune
 
     b, offs = inputs.concat_bodies(channels)
     lat.set_nodes(b.n, offs if len(channels) > 1 else None)
@@ -217,24 +217,45 @@ def main():
     X = torch.from_numpy(b.X.copy()).to(dev)
     F = torch.zeros((3, b.n), dtype=torch.float32, device=dev)
     U = torch.zeros_like(F)
+    if args.closure:
+        lat.set_closure(*closure_weights(torch, dev), 1.0)
+    if args.launch:
+        cfg = dict(tune.DEFAULT, **json.loads(args.launch))
+        lat.set_launch(**cfg)
+    else:
+        # the cached launch and schedule of this size class (tuned on the graph-replayed
+        # coupled step), or a tuning run now, which advances the state: start again after it
+        tune.apply_cached_or_tune(lat, retune=args.tune, coupled=(mem, X, F, U))
+    lat.init()
+    X.copy_(torch.from_numpy(b.X))
+    F.zero_()
+    U.zero_()
+    # the graph replays two steps from the buffer parities current at capture: an odd warm-up
+    # step runs eagerly before the capture, an odd timed step after the last replay
+    if args.warmup % 2:
+        lat.coupled_steps(mem, 1, X, F, U)
     lat.graph_capture(mem, 2, X, F, U)
     stream = lat.stream  # the library's stream: events are recorded on it
-
-    def run(k):
-        if k // 2:
-            lat.graph_launch(k // 2)
-        if k % 2:
-            lat.coupled_steps(mem, 1, X, F, U)
-
-    run(args.warmup)
+    if args.warmup // 2:
+        lat.graph_launch(args.warmup // 2)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    run(args.steps)
+    if args.steps // 2:
+        lat.graph_launch(args.steps // 2)
+    if args.steps % 2:
+        lat.coupled_steps(mem, 1, X, F, U)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     flags = lat.error_flags()
+
+    # the coupled step's lattice-update launch, timed by the library's event pairs around it
+    lat.launch_timer(True)
+    lat.coupled_steps(mem, args.timer_steps, X, F, U)
+    n_timed, us_update, kind = lat.launch_timer_read()
+    lat.launch_timer(False)
+    flags |= lat.error_flags()
 
     # lattice kernel alone: back-to-back launches on the same stream
     lat.step(10)
@@ -245,10 +266,11 @@ def main():
     torch.cuda.synchronize()
     ms_lbm = e0.elapsed_time(e1) / args.lbm_only_steps
     bytes_launch = BYTES_PER_CELL[args.storage] * cells
-    achieved = bytes_launch / (ms_lbm * 1e-3)
+    achieved = bytes_launch / (us_update * 1e-6)
+    achieved_lbm = bytes_launch / (ms_lbm * 1e-3)
+    achieved_step = bytes_launch / (ms * 1e-3)
     ceiling, ceiling_cfg = tune.copy_ceiling(torch, lat.device, bytes_launch // 2)
-
-    kname = "k_step_cl (lattice step + learned closure)" if args.closure else "k_step (lattice step)"
+    kernel = TIMED_KERNEL[kind]
     out = {
         "metric": METRIC,
         "value": round(cells / (ms * 1e-3) / 1e6, 2),
@@ -269,15 +291,22 @@ def main():
         "mlups_fine_equivalent": round(16 * cells / (ms * 1e-3) / 1e6, 2) if args.workload == "coarse" else None,
         "lbm_only_mlups": round(cells / (ms_lbm * 1e-3) / 1e6, 2),
         "error_flags": flags,
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved / 1e9, 1),
+        "roofline": {"bound": "hbm", "kernel": TIMED_KERNEL_DESC[kind], "achieved": round(achieved / 1e9, 1),
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
-                     "traffic": measured_traffic(args.storage, args.workload), "bytes_per_launch": bytes_launch,
-                     "avg_launch_us": round(ms_lbm * 1e3, 2),
+                     "traffic": measured_traffic(kernel, args.storage, args.workload),
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": round(us_update, 2),
+                     "timed_launches": n_timed,
+                     "step_frac": round(achieved_step / HBM_PEAK, 4),
                      "copy_ceiling_GBps": round(ceiling / 1e9, 1),
-                     "frac_of_copy_ceiling": round(achieved / ceiling, 4)},
+                     "frac_of_copy_ceiling": round(achieved / ceiling, 4),
+                     "lattice_only": {"kernel": "k_step_cl" if args.closure else "k_step",
+                                      "avg_launch_us": round(ms_lbm * 1e3, 2),
+                                      "achieved": round(achieved_lbm / 1e9, 1),
+                                      "frac": round(achieved_lbm / HBM_PEAK, 4),
+                                      "note": "back-to-back lbm_step launches, outside the timed step"}},
     }
     if args.closure:
-        fl = MLP_FLOP_PER_CELL * cells / (ms_lbm * 1e-3)
+        fl = MLP_FLOP_PER_CELL * cells / (us_update * 1e-6)
         out["roofline"]["mfma"] = {"achieved": round(fl / 1e12, 2), "peak": MFMA_BF16_PEAK / 1e12, "unit": "TFLOP/s",
                                    "frac": round(fl / MFMA_BF16_PEAK, 4), "flop_per_cell": MLP_FLOP_PER_CELL}
         out["closure_guarded"] = lat.closure_guarded()

@@ -232,7 +232,12 @@ lbm_status lbm_coupled_steps(lbm_ctx* ctx, const ib_membrane* m /*host*/, int32_
 
 /* Capture `nsteps` coupled steps (even, >= 2) into a HIP graph held by the context, then
  * replay it `repeats` times per lbm_graph_launch.  The captured pointers must stay valid.
- * The context's stream must not be the legacy default (NULL) stream: LBM_ERR_UNSUPPORTED. */
+ * The context's stream must not be the legacy default (NULL) stream: LBM_ERR_UNSUPPORTED.
+ * The graph reads and writes the population buffer and IB tile set that were current at
+ * capture; a replay leaves them current again.  lbm_graph_launch returns LBM_ERR_STATE
+ * (and launches nothing) when other calls since the capture left a different buffer or
+ * tile set current: an odd number of eager coupled steps, a lone lbm_step or ib_spread.
+ * Even numbers of eager steps between replays are fine. */
 lbm_status lbm_graph_capture(lbm_ctx* ctx, const ib_membrane* m /*host*/, int32_t nsteps, double* X,
                              float* F, float* U);
 lbm_status lbm_graph_launch(lbm_ctx* ctx, int32_t repeats);
@@ -341,6 +346,19 @@ typedef struct {
 
 lbm_status lbm_set_launch(lbm_ctx* ctx, const lbm_launch* cfg /*host*/);
 lbm_status lbm_get_launch(const lbm_ctx* ctx, lbm_launch* cfg /*host*/);
+
+/* Measurement helper, not part of the method: with enable = 1 every later eager
+ * lbm_coupled_steps call (not graph capture, not the overlapped schedule) records a pair of
+ * timing events on the context's stream around the launch that updates the lattice: the
+ * body-force update of every cell that also runs the spread (split schedule, kind 1), the
+ * fused lattice step (kind 0) or the closure step (kind 2); at most LBM_TIMER_PAIRS launches
+ * are timed.  lbm_launch_timer_read synchronises the stream, returns the number of timed
+ * launches, their mean duration in microseconds and the kind of the last one (kind may be
+ * NULL), and starts a new count.  Enabling again resets the count. */
+#define LBM_TIMER_PAIRS 1024
+lbm_status lbm_launch_timer(lbm_ctx* ctx, int32_t enable);
+lbm_status lbm_launch_timer_read(lbm_ctx* ctx, int64_t* count /*host*/, double* mean_us /*host*/,
+                                 int32_t* kind /*host*/);
 
 /* Measurement helper, not part of the method: copy `bytes` (multiple of 16) from src to dst
  * with 16-byte accesses (variant 0: plain stores, 1: non-temporal stores), `grid`

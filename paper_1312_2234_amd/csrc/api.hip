@@ -344,6 +344,7 @@ lbm_status lbm_destroy(lbm_ctx* c) {
         if (e == hipSuccess) e = e2;
         hipStreamDestroy(c->side);
     }
+    for (hipEvent_t ev : c->tev) hipEventDestroy(ev);
     if (c->ev_state) hipEventDestroy(c->ev_state);
     if (c->ev_far) hipEventDestroy(c->ev_far);
     if (c->gexec) hipGraphExecDestroy(c->gexec);
@@ -566,14 +567,23 @@ static lbm_status coupled(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, doub
         }
         LatArgs la = lat_args(c);
         hipError_t e;
+        // the launch timer brackets the launch that updates the lattice (eager calls only)
+        const bool timed = c->timer && !c->capturing && !ov && c->tcount < LBM_TIMER_PAIRS;
+        if (timed && hipEventRecord(c->tev[2 * c->tcount], c->stream) != hipSuccess) return LBM_ERR_HIP;
         if (split_update) {
             e = launch_spread_far(c, a, la);
+            if (timed && e == hipSuccess) e = hipEventRecord(c->tev[2 * c->tcount + 1], c->stream);
             if (e == hipSuccess) e = launch_step_tiles(c, la, true);
         } else if (ov) {
             e = hipStreamWaitEvent(c->stream, c->ev_far, 0);
             if (e == hipSuccess) e = launch_step_tiles(c, la);
         } else {
             e = c->closure ? launch_step_closure(c, la) : launch_lattice(c, LK_STEP, la);
+            if (timed && e == hipSuccess) e = hipEventRecord(c->tev[2 * c->tcount + 1], c->stream);
+        }
+        if (timed) {
+            c->tkind = split_update ? 1 : (c->closure ? 2 : 0);
+            ++c->tcount;
         }
         if (e != hipSuccess) return LBM_ERR_HIP;
         c->cur ^= 1;
@@ -608,7 +618,9 @@ lbm_status lbm_graph_capture(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, d
     const int cur0 = c->cur, set0 = c->ibset;
     if (c->stream == nullptr) return LBM_ERR_UNSUPPORTED;  // the legacy default stream cannot be captured
     if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LBM_ERR_HIP;
+    c->capturing = true;
     st = coupled(c, m, nsteps, X, F, U);
+    c->capturing = false;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     // nothing ran during capture; with an even step count the buffer and tile-set
@@ -625,12 +637,18 @@ lbm_status lbm_graph_capture(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, d
         return LBM_ERR_HIP;
     }
     c->graph = g;
+    c->graph_cur = cur0;
+    c->graph_set = set0;
     return LBM_OK;
 }
 
 lbm_status lbm_graph_launch(lbm_ctx* c, int32_t repeats) {
     if (!c || repeats < 0) return LBM_ERR_ARG;
     if (!c->gexec) return LBM_ERR_STATE;
+    // the graph's kernels read and write the buffers and tile sets of the parities it was
+    // captured at: an odd number of eager steps (or a lone lbm_step / ib_spread) since then
+    // would make it replay from stale state
+    if (c->cur != c->graph_cur || c->ibset != c->graph_set) return LBM_ERR_STATE;
     for (int r = 0; r < repeats; ++r)
         if (hipGraphLaunch(c->gexec, c->stream) != hipSuccess) return LBM_ERR_HIP;
     return LBM_OK;
@@ -651,6 +669,41 @@ lbm_status lbm_set_launch(lbm_ctx* c, const lbm_launch* cfg) {
 lbm_status lbm_get_launch(const lbm_ctx* c, lbm_launch* cfg) {
     if (!c || !cfg) return LBM_ERR_ARG;
     *cfg = c->launch;
+    return LBM_OK;
+}
+
+lbm_status lbm_launch_timer(lbm_ctx* c, int32_t enable) {
+    if (!c || (enable != 0 && enable != 1)) return LBM_ERR_ARG;
+    if (enable && c->tev.empty()) {
+        std::vector<hipEvent_t> evs(2 * LBM_TIMER_PAIRS, nullptr);
+        for (hipEvent_t& ev : evs)
+            if (hipEventCreate(&ev) != hipSuccess) {
+                for (hipEvent_t made : evs)
+                    if (made) hipEventDestroy(made);
+                return LBM_ERR_HIP;
+            }
+        c->tev.swap(evs);
+    }
+    c->timer = enable != 0;
+    c->tcount = 0;
+    c->tkind = -1;
+    return LBM_OK;
+}
+
+lbm_status lbm_launch_timer_read(lbm_ctx* c, int64_t* count, double* mean_us, int32_t* kind) {
+    if (!c || !count || !mean_us) return LBM_ERR_ARG;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return LBM_ERR_HIP;
+    double tot = 0.0;
+    for (int64_t k = 0; k < c->tcount; ++k) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->tev[2 * k], c->tev[2 * k + 1]) != hipSuccess) return LBM_ERR_HIP;
+        tot += ms;
+    }
+    *count = c->tcount;
+    *mean_us = c->tcount ? 1e3 * tot / (double)c->tcount : 0.0;
+    if (kind) *kind = c->tkind;
+    c->tcount = 0;
+    c->tkind = -1;
     return LBM_OK;
 }
 

@@ -291,11 +291,13 @@ __device__ __forceinline__ void spread_scale(const IbArgs& a) {
             frexpf(fm, &e);  // fm < 2^e
             int L = 1;
             while ((1ll << L) < a.n) ++L;
-            // one contribution |w_x w_y w_z F| <= max|F|/8 < 2^(e-3) stays below 2^31 after
-            // scaling, hence below 2^23 at the spread's per-batch scale 2^(s-8) (so it converts
-            // exactly through int32), and a sum of <= n of them stays below 2^62; the quantum
-            // of a contribution is 2^-26 max|F| or finer
-            s = 34 - e;
+            // one contribution |w_x w_y w_z F| <= max|F|/8 < 2^(e-3) stays below 2^30 after
+            // scaling, hence below 2^22 at the spread's per-batch scale 2^(s-8): rounded to an
+            // integer it is at most 2^22 (a value just below 2^22 may round up to it), so a batch
+            // of <= 256 of them sums to at most 2^30 < 2^31 and converts exactly through int32;
+            // a sum of <= n of them stays below 2^62; the quantum of a contribution is
+            // 2^-25 max|F| or finer
+            s = 33 - e;
             if (s > 65 - e - L) s = 65 - e - L;
         }
         a.set.hdr->scale_exp = s;
@@ -408,14 +410,14 @@ constexpr int SP_BATCH = 256;     // node records staged at a time (a chunk is s
 
 __device__ __forceinline__ unsigned fixed_round(float c, float scale) {
     // round-to-nearest-even of c * scale (a power of two: the product is exact) for
-    // |c * scale| < 2^23, as a two's-complement 32-bit word
+    // |c * scale| < 2^22, as a two's-complement 32-bit word
     return (unsigned)(int)__builtin_rintf(c * scale);
 }
 
 // Contributions are summed per staged batch in 32-bit LDS words (cheaper atomics than 64-bit
-// ones), at 2^-8 of the tile accumulator's scale: each is below 2^23 there and a batch adds
-// at most SP_BATCH of them to a cell, so a batch sum stays below 2^31 and is exact.  After
-// each batch the words are added, scaled by 2^8, to the tile's 64-bit accumulator.
+// ones), at 2^-8 of the tile accumulator's scale: each rounds to at most 2^22 there and a batch
+// adds at most SP_BATCH of them to a cell, so a batch sum stays at or below 2^30 and is exact.
+// After each batch the words are added, scaled by 2^8, to the tile's 64-bit accumulator.
 constexpr int SP_BATCH_SHIFT = 8;
 static_assert(SP_BATCH <= (1 << SP_BATCH_SHIFT), "a batch sum must stay below 2^31");
 
@@ -1089,8 +1091,8 @@ __global__ void __launch_bounds__(256) k_mem_forces(ib_membrane m, const double*
 }
 
 // The coupled step's second launch: the scan of the tile lists (workgroup 0; it needs only
-// the binning) and the membrane forces (the rest, 128 nodes each), which also fill in the
-// records' F and max |F| per workgroup.
+// the binning) and the membrane forces (the rest, FS_THREADS / 8 nodes each), which also fill
+// in the records' F and max |F| per workgroup.
 // 512 threads: node-force workgroups of 64 nodes spread over more CUs (shear channel, 41 k
 // nodes: launch 8.4 -> 7.7 us against 1024 threads), while the scan workgroup still covers a
 // few hundred flagged tiles per pass (on the 3,600-tile batch 1024 is 0.4% faster per step)

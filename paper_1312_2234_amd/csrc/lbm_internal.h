@@ -108,7 +108,7 @@ struct IbArgs {
     int32_t use_rec;        // interpolation at the positions of the latest spread: reuse its node records
     int32_t nch;
     int32_t* rank;          // [n][27] packed rank of a node in each tile list it joins
-    int32_t* blkbase;       // [ceil(n/256)][2048] per-block base of each hashed tile
+    int32_t* blkbase;       // [ceil(n/256)][HS] per-block base of each hashed tile
     int4* nbase;            // [n] stencil base (x, y, z) and channel of every node
     unsigned long long* part;  // [part_cap][3][512] fixed-point partial sums of split tiles' chunks
     int64_t part_cap;
@@ -225,6 +225,16 @@ struct lbm_ctx {
     bool closure = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // buffer and tile-set parities the captured graph was recorded at (it reads and writes
+    // fixed buffers, so it may only be replayed from the same parities)
+    int graph_cur = 0, graph_set = 0;
+    bool capturing = false;  // inside lbm_graph_capture
+    // launch timer (measurement helper): event pairs around the lattice-update launches of eager
+    // coupled steps
+    bool timer = false;
+    std::vector<hipEvent_t> tev;
+    int64_t tcount = 0;
+    int32_t tkind = -1;
 };
 
 namespace lbmib {

@@ -27,7 +27,7 @@ EXPORTS = [
     "lbm_coupled_steps", "lbm_graph_capture", "lbm_graph_launch", "lbm_set_launch", "lbm_get_launch",
     "lbm_stream_copy", "mlp_pack", "lbm_set_closure", "lbm_closure_guarded", "mlp_forward",
     "mlp_grad_workspace_bytes", "mlp_grad", "mlp_adam", "mlp_norm_workspace_bytes", "mlp_norm",
-    "lbm_restrict", "closure_targets",
+    "lbm_restrict", "closure_targets", "lbm_launch_timer", "lbm_launch_timer_read",
 ]
 
 MLP_PARAMS, MLP_NORM, MLP_PACKED_BYTES = 6288, 48, 23360
@@ -115,6 +115,8 @@ def lib():
         L.mlp_norm.argtypes = [vp, vp, i64, vp, vp, C.c_size_t, vp]
         L.lbm_restrict.argtypes = [vp, f32, vp, vp]
         L.closure_targets.argtypes = [P, vp, vp, vp, vp, vp, vp]
+        L.lbm_launch_timer.argtypes = [vp, i32]
+        L.lbm_launch_timer_read.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         for name in EXPORTS:
             if name not in _SIZE_FNS:
                 getattr(L, name).restype = C.c_int32
@@ -347,6 +349,19 @@ class Lattice:
         with self.ordered:
             _check(lib().lbm_restrict(self.h, float(tau_coarse), _ptr(g), _ptr(F)), "lbm_restrict")
         return g, F
+
+    def launch_timer(self, enable=True):
+        """Time the lattice-update launch of later eager coupled steps (measurement helper)."""
+        _check(lib().lbm_launch_timer(self.h, 1 if enable else 0), "lbm_launch_timer")
+
+    def launch_timer_read(self):
+        """(count, mean microseconds, kind) of the timed launches since the last read; kind 0 =
+        fused lattice step, 1 = body-force update with the spread (split schedule), 2 = closure step."""
+        n, us, kind = C.c_int64(), C.c_double(), C.c_int32()
+        with self.ordered:
+            _check(lib().lbm_launch_timer_read(self.h, C.byref(n), C.byref(us), C.byref(kind)),
+                   "lbm_launch_timer_read")
+        return n.value, us.value, kind.value
 
     def set_launch(self, block=256, xcd_remap=1, persistent=0, nontemporal=0, vec=0, overlap=0, split=-1):
         cfg = LbmLaunch(block, xcd_remap, persistent, nontemporal, vec, overlap, split)

@@ -2,9 +2,9 @@
 (launch shape from the tuned cache, steps replayed from a 2-step HIP graph), against the
 FP64 oracle on every cell: the 256x128x128 shear channel with 16 platelets of 2562 nodes
 (with halfway walls, with the on-site walls of Eq. 23-30, and with the area and volume
-constraints of Eq. 4-5 at Table 2's coefficients), and the 64-channel batch (18.2 M cells,
-0.50 M nodes).  Tolerances as in test_gpu_parity: velocity e_max <= 1e-5, interpolated
-velocities likewise, wall stress 1e-4."""
+constraints of Eq. 4-5 at Table 2's coefficients) over 100 coupled steps, and the 64-channel
+batch (18.2 M cells, 0.50 M nodes) over 20.  Tolerances as in test_gpu_parity: velocity
+e_max <= 1e-5, interpolated velocities likewise, wall stress 1e-4."""
 import dataclasses
 
 import numpy as np
@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 
 def gpu_bench_config(gpu, channels, steps):
-    """The benchmark's launch configuration: tuned launch shape, 2-step graph replay."""
+    """The benchmark's launch configuration: tuned launch shape and schedule, 2-step graph replay."""
     import torch
 
     from paper_1312_2234_amd import tune
@@ -25,13 +25,14 @@ def gpu_bench_config(gpu, channels, steps):
     b, offs = inputs.concat_bodies(channels)
     g = gpu.Lattice(channels, kernel="cos", max_nodes=b.n, device=DEV)
     g.init()
-    tune.apply_cached_or_tune(g)
-    g.init()
     g.set_nodes(b.n, offs if len(channels) > 1 else None)
     mem = gpu.Membrane(b, device=DEV)
     X = T(b.X)
     F = torch.zeros((3, b.n), dtype=torch.float32, device=DEV)
     U = torch.zeros_like(F)
+    tune.apply_cached_or_tune(g, coupled=(mem, X, F, U))
+    g.init()
+    X.copy_(T(b.X))
     g.graph_capture(mem, 2, X, F, U)
     g.graph_launch(steps // 2)
     torch.cuda.synchronize()
@@ -50,7 +51,7 @@ def shear_workload(variant):
 @pytest.mark.parametrize("variant", ["halfway", "onsite", "constrained"])
 def test_full_shear_workload_against_oracle(orc, gpu, variant):
     ch = shear_workload(variant)
-    steps = 4
+    steps = 100
     g, Xg, Ug, _ = gpu_bench_config(gpu, [ch], steps)
     o, Xo, Uo = run_oracle_coupled(orc, ch, "cos", steps)
     drho, v = g.moments_channel(0)
@@ -67,7 +68,7 @@ def test_full_shear_workload_against_oracle(orc, gpu, variant):
 
 def test_full_batched_workload_against_oracle(orc, gpu):
     chans = inputs.batched_channels(seed=0)
-    steps = 2
+    steps = 20
     g, Xg, Ug, offs = gpu_bench_config(gpu, chans, steps)
     worst = 0.0
     for c, ch in enumerate(chans):

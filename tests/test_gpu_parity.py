@@ -214,6 +214,92 @@ def test_spread_partial_capacity_exhausted(orc, gpu):
     assert g.error_flags() == 0
 
 
+def test_spread_full_batch_of_coincident_nodes(orc, gpu):
+    """256 nodes on one lattice point (a whole staged batch on one cell, weight 1/8 there), each
+    with the largest force below a power of two: every rounded contribution takes the full
+    headroom of the 32-bit batch sum, which must neither wrap nor lose a unit."""
+    ch = inputs.Channel(16, 16, 16, 0.8)
+    n = 256
+    X = np.tile(np.array([[5.0], [6.0], [7.0]]), (1, n))
+    F32 = np.zeros((3, n), np.float32)
+    F32[0] = np.nextafter(np.float32(1.0), np.float32(0.0))
+    F32[1] = -F32[0]
+    F32[2] = np.float32(0.5)
+    o, g = pair(orc, gpu, ch, max_nodes=n)
+    o.spread(X, F32.astype(np.float64))
+    g.set_nodes(n)
+    g.spread(T(X), T(F32))
+    _, v_g = gpu_fields(g)
+    assert abs(o.g[0, 7, 6, 5] - 32 * float(F32[0, 0])) < 1e-12
+    assert emax(2 * v_g, o.g) <= 2e-6
+    assert g.error_flags() == 0
+
+
+def _scattered_nodes(rng, n, dims):
+    nx, ny, nz = dims
+    return np.stack([rng.uniform(0, nx, n), rng.uniform(-0.5, ny - 0.5, n), rng.uniform(0, nz, n)])
+
+
+def test_spread_scattered_nodes_fill_the_bin_hash(orc, gpu):
+    """4096 nodes scattered over the 256x128x128 lattice: a block of 256 nodes touches ~670
+    distinct tiles, more than its 512-entry LDS table, so the binning's direct-count branch
+    runs; the field must still match the oracle."""
+    rng = np.random.default_rng(16)
+    dims = (256, 128, 128)
+    n = 4096
+    X = _scattered_nodes(rng, n, dims)
+    blocks = [X[:, k:k + 256] for k in range(0, n, 256)]
+    distinct = [len({tuple(t) for t in _node_tiles(B, dims)}) for B in blocks]
+    assert min(distinct) > 512, distinct          # every bin block overflows its table
+    F32 = (1e-3 * rng.standard_normal((3, n))).astype(np.float32)
+    ch = inputs.Channel(*dims, 0.8)
+    o, g = pair(orc, gpu, ch, max_nodes=n)
+    o.spread(X, F32.astype(np.float64))
+    g.set_nodes(n)
+    g.spread(T(X), T(F32))
+    _, v_g = gpu_fields(g)
+    assert emax(2 * v_g, o.g) <= 2e-6
+    assert g.error_flags() == 0
+
+
+def test_coupled_scattered_tethered_nodes_fill_the_bin_hash(orc, gpu):
+    """The coupled step's binning (beside the membrane forces) with 4096 scattered tethered
+    nodes on the 256x128x128 shear channel: the direct-count branch of every bin block runs
+    in the split schedule; 3 coupled steps against the oracle."""
+    rng = np.random.default_rng(17)
+    dims = (256, 128, 128)
+    n = 4096
+    X0 = _scattered_nodes(rng, n, dims)
+    X0[1] = np.clip(X0[1], 1.0, dims[1] - 2.0)
+    assert min(len(set(_node_tiles(X0[:, k:k + 256], dims))) for k in range(0, n, 256)) > 512
+    anchors = X0 + 0.3 * rng.standard_normal(X0.shape)
+    anchors[1] = np.clip(anchors[1], 1.0, dims[1] - 2.0)
+    bodies = inputs.Bodies(X=X0, X_rest=X0.copy(), edges=np.zeros((0, 2), np.int32), hinges=np.zeros((0, 4), np.int32),
+                           anchors=anchors, k_tether=0.01, body_offsets=[0, n])
+    ch = inputs.Channel(*dims, 1.0, u_wall_hi=(0.05, 0.0, 0.0), init="shear", bodies=bodies)
+    o, Xo, Uo = run_oracle_coupled(orc, ch, "cos", 3)
+    g, Xg, Ug = run_gpu_coupled(gpu, ch, "cos", 3)
+    assert emax(gpu_fields(g)[1], o.moments()[1]) <= TOL32
+    assert emax(N(Ug), Uo) <= TOL32
+    assert g.error_flags() == 0
+
+
+def _node_tiles(X, dims):
+    """(tx, ty, tz) of every 8^3 tile any node's 4^3 stencil touches (walls in y)."""
+    out = []
+    for m in range(X.shape[1]):
+        ax = []
+        for d, n in enumerate(dims):
+            cells = int(np.floor(X[d, m])) - 1 + np.arange(4)
+            if d == 1:
+                cells = cells[(cells >= 0) & (cells < n)]
+            else:
+                cells = cells % n
+            ax.append(sorted({int(c) // 8 for c in cells}))
+        out += [(a, b, c) for a in ax[0] for b in ax[1] for c in ax[2]]
+    return out
+
+
 def test_error_flags(gpu):
     ch = inputs.Channel(16, 16, 16, 0.8)
     g = gpu.Lattice([ch], max_nodes=2, device=DEV)
@@ -282,7 +368,7 @@ def run_gpu_coupled(gpu, ch, kernel, steps, graph=False, storage="f32"):
 @pytest.mark.parametrize("kernel", ["peskin4", "cos"])
 def test_coupled_poiseuille_sphere_100_steps(orc, gpu, kernel):
     """32^3 box, body force 1e-6, tethered 642-node sphere (k = 0.01, N(0, 0.1^2) start), 100 steps."""
-    for seed in (0, 1):
+    for seed in range(5):
         ch = inputs.poiseuille_sphere(seed=seed)
         o, Xo, Uo = run_oracle_coupled(orc, ch, kernel, 100)
         g, Xg, Ug = run_gpu_coupled(gpu, ch, kernel, 100)
@@ -298,6 +384,67 @@ def test_graph_replay_matches_eager(gpu):
     g2, X2, U2 = run_gpu_coupled(gpu, ch, "peskin4", 20, graph=True)
     assert np.array_equal(N(X1), N(X2)) and np.array_equal(N(U1), N(U2))
     assert np.array_equal(N(g1.moments()[1]), N(g2.moments()[1]))
+
+
+def test_graph_launch_checks_buffer_parity(gpu):
+    """A captured 2-step graph replays from the population buffer and tile set current at
+    capture: after an odd number of eager steps (or a lone lbm_step) the replay is refused;
+    even interleaves of eager steps and replays equal eager execution bit for bit."""
+    import torch
+
+    ch = inputs.poiseuille_sphere(seed=3)
+    g1, X1, U1 = run_gpu_coupled(gpu, ch, "peskin4", 10)
+    b = ch.bodies
+    g = gpu.Lattice([ch], kernel="peskin4", max_nodes=b.n, device=DEV)
+    g.init()
+    g.set_nodes(b.n)
+    mem = gpu.Membrane(b, device=DEV)
+    X = T(b.X)
+    F = torch.zeros((3, b.n), dtype=torch.float32, device=DEV)
+    U = torch.zeros_like(F)
+    g.graph_capture(mem, 2, X, F, U)
+    g.graph_launch(2)                  # 4 steps
+    g.coupled_steps(mem, 2, X, F, U)   # 6
+    g.graph_launch(1)                  # 8
+    g.coupled_steps(mem, 1, X, F, U)   # 9: odd, a replay would read the stale buffer
+    with pytest.raises(gpu.LbmError):
+        g.graph_launch(1)
+    g.coupled_steps(mem, 1, X, F, U)   # 10
+    torch.cuda.synchronize()
+    assert np.array_equal(N(X1), N(X)) and np.array_equal(N(U1), N(U))
+    assert np.array_equal(N(g1.moments()[1]), N(g.moments()[1]))
+    g.step(1)                          # a lone lattice step flips the buffer only
+    with pytest.raises(gpu.LbmError):
+        g.graph_launch(1)
+
+
+def test_launch_timer_brackets_the_lattice_update(gpu):
+    """The measurement helper times the lattice-update launch of eager coupled steps only."""
+    import torch
+
+    ch = inputs.poiseuille_sphere(seed=4)
+    b = ch.bodies
+    g = gpu.Lattice([ch], kernel="cos", max_nodes=b.n, device=DEV)
+    g.init()
+    g.set_nodes(b.n)
+    mem = gpu.Membrane(b, device=DEV)
+    X = T(b.X)
+    F = torch.zeros((3, b.n), dtype=torch.float32, device=DEV)
+    U = torch.zeros_like(F)
+    g.launch_timer(True)
+    g.coupled_steps(mem, 3, X, F, U)
+    n, us, kind = g.launch_timer_read()
+    assert n == 3 and 0.0 < us < 1e5 and kind == 1   # one channel: split schedule
+    g.graph_capture(mem, 2, X, F, U)
+    g.graph_launch(1)
+    assert g.launch_timer_read()[0] == 0             # graph replays are not timed
+    g.set_launch(split=0)
+    g.coupled_steps(mem, 2, X, F, U)
+    n, us, kind = g.launch_timer_read()
+    assert n == 2 and us > 0.0 and kind == 0
+    g.launch_timer(False)
+    g.coupled_steps(mem, 2, X, F, U)
+    assert g.launch_timer_read()[0] == 0
 
 
 def test_coupled_shear_platelets_crop(orc, gpu):
