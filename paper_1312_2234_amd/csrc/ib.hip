@@ -288,16 +288,18 @@ __device__ __forceinline__ void spread_scale(const IbArgs& a) {
             atomicOr(a.flags, LBM_FLAG_FORCE_NONFINITE);
         } else if (fm > 0.0f) {
             int e;
-            frexpf(fm, &e);  // fm < 2^e
+            const float m = frexpf(fm, &e);  // fm = m 2^e, 1/2 <= m < 1
+            // a force within 2^-16 of the next power of two takes the next exponent: the margin
+            // absorbs the float rounding of the weights (each 1/2 at most, up to an ulp)
+            if (m > 1.0f - 0x1p-16f) ++e;
             int L = 1;
             while ((1ll << L) < a.n) ++L;
-            // one contribution |w_x w_y w_z F| <= max|F|/8 < 2^(e-3) stays below 2^30 after
-            // scaling, hence below 2^22 at the spread's per-batch scale 2^(s-8): rounded to an
-            // integer it is at most 2^22 (a value just below 2^22 may round up to it), so a batch
-            // of <= 256 of them sums to at most 2^30 < 2^31 and converts exactly through int32;
-            // a sum of <= n of them stays below 2^62; the quantum of a contribution is
-            // 2^-25 max|F| or finer
-            s = 33 - e;
+            // one contribution |w_x w_y w_z F| <= (1 + 2^-20) max|F|/8 < (1 - 2^-17) 2^(e-3)
+            // stays below 2^23 - 64 at the spread's per-batch scale 2^(s-8), also once rounded
+            // to an integer, so a batch of <= 256 of them sums to less than 2^31 and converts
+            // exactly through int32; a sum of <= n of them stays below 2^62; the quantum of a
+            // contribution is 2^-26 max|F| or finer (2^-25 in the margin)
+            s = 34 - e;
             if (s > 65 - e - L) s = 65 - e - L;
         }
         a.set.hdr->scale_exp = s;
@@ -410,13 +412,13 @@ constexpr int SP_BATCH = 256;     // node records staged at a time (a chunk is s
 
 __device__ __forceinline__ unsigned fixed_round(float c, float scale) {
     // round-to-nearest-even of c * scale (a power of two: the product is exact) for
-    // |c * scale| < 2^22, as a two's-complement 32-bit word
+    // |c * scale| < 2^23 - 64, as a two's-complement 32-bit word
     return (unsigned)(int)__builtin_rintf(c * scale);
 }
 
 // Contributions are summed per staged batch in 32-bit LDS words (cheaper atomics than 64-bit
-// ones), at 2^-8 of the tile accumulator's scale: each rounds to at most 2^22 there and a batch
-// adds at most SP_BATCH of them to a cell, so a batch sum stays at or below 2^30 and is exact.
+// ones), at 2^-8 of the tile accumulator's scale: each rounds to less than 2^23 - 64 there and
+// a batch adds at most SP_BATCH of them to a cell, so a batch sum stays below 2^31 and is exact.
 // After each batch the words are added, scaled by 2^8, to the tile's 64-bit accumulator.
 constexpr int SP_BATCH_SHIFT = 8;
 static_assert(SP_BATCH <= (1 << SP_BATCH_SHIFT), "a batch sum must stay below 2^31");

@@ -216,8 +216,9 @@ def test_spread_partial_capacity_exhausted(orc, gpu):
 
 def test_spread_full_batch_of_coincident_nodes(orc, gpu):
     """256 nodes on one lattice point (a whole staged batch on one cell, weight 1/8 there), each
-    with the largest force below a power of two: every rounded contribution takes the full
-    headroom of the 32-bit batch sum, which must neither wrap nor lose a unit."""
+    with the largest force below a power of two: at the scale of that power of two every
+    contribution would round to 2^23 and the 32-bit batch sum would wrap; the scale must keep
+    the sum below 2^31."""
     ch = inputs.Channel(16, 16, 16, 0.8)
     n = 256
     X = np.tile(np.array([[5.0], [6.0], [7.0]]), (1, n))
