@@ -29,6 +29,20 @@ import numpy as np
 
 def icosphere(level: int):
     """Unit icosphere: 10*4**level + 2 vertices; triangles oriented outward."""
+    V, T, _ = _icosphere(level)
+    return V, T
+
+
+def icosphere_quadratic(level: int):
+    """The icosphere of `level` >= 1 as six-node triangles: each triangle of level - 1 with its
+    three edge midpoints, rows (a, b, c, m_ab, m_bc, m_ca), corners outward.  Returns (V, E6)."""
+    if level < 1:
+        raise ValueError("six-node triangles need level >= 1")
+    V, _, E6 = _icosphere(level)
+    return V, E6
+
+
+def _icosphere(level):
     t = (1.0 + 5.0 ** 0.5) / 2.0
     V = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t),
          (0, 1, -t), (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
@@ -47,14 +61,20 @@ def icosphere(level: int):
                 cache[key] = len(V) - 1
             return cache[key]
 
-        T2 = []
+        T2, E6 = [], []
         for a, b, c in T:
             ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
             T2 += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+            E6.append((a, b, c, ab, bc, ca))
         T = T2
     V = np.array(V)
     T = np.array(T, dtype=np.int32)
-    return V, _orient_outward(V, T)
+    E6 = np.array(E6 if level > 0 else [], dtype=np.int32).reshape(-1, 6)
+    if len(E6):
+        # outward corners; reversing (a, b, c) to (a, c, b) renames the midpoints to (ca, bc, ab)
+        flip = _orient_outward(V, E6[:, :3])[:, 1] != E6[:, 1]
+        E6[flip] = E6[flip][:, [0, 2, 1, 5, 4, 3]]
+    return V, _orient_outward(V, T), E6
 
 
 def fibonacci_sphere(n: int):
@@ -164,6 +184,9 @@ class Bodies:
     k_area_global: float = 0.0
     k_area_local: float = 0.0
     k_volume: float = 0.0
+    # finite-element bending of Eq. (6)-(10) (off unless elements are set; with_fe_bending)
+    elements6: np.ndarray | None = None   # [ne, 6] int32 six-node triangles, corners outward
+    k_fe: float = 0.0                      # k_0 of Eq. (6)
 
     @property
     def n(self):
@@ -187,6 +210,29 @@ def with_constraints(b, k_area_global=0.0, k_area_local=0.0, k_volume=0.0):
     return dataclasses.replace(b, triangles=np.concatenate(T).astype(np.int32), tri_offsets=offs,
                                k_area_global=float(k_area_global), k_area_local=float(k_area_local),
                                k_volume=float(k_volume))
+
+
+def with_fe_bending(b, k0):
+    """The same bodies with the finite-element bending of Eq. (6)-(10) (modulus k0) in place of
+    the dihedral stand-in: each body's icosphere mesh as six-node triangles (its nodes are the
+    corners and edge midpoints of the icosphere one level down)."""
+    E, off = [], 0
+    for lo, hi in zip(b.body_offsets[:-1], b.body_offsets[1:]):
+        E.append(_quadratic(hi - lo) + lo)
+    E = np.concatenate(E).astype(np.int32)
+    # the six-node triangles must be the bodies' own meshes: their half-edges are spring edges
+    half = np.concatenate([E[:, [0, 3]], E[:, [3, 1]], E[:, [1, 4]], E[:, [4, 2]], E[:, [2, 5]], E[:, [5, 0]]])
+    springs = {tuple(e) for e in np.sort(np.asarray(b.edges, np.int64), axis=1).tolist()}
+    if len(b.edges) == 0 or any(tuple(e) not in springs for e in np.sort(half, axis=1).tolist()):
+        raise ValueError("with_fe_bending needs bodies built from icosphere meshes (642, 2562, ... nodes)")
+    return dataclasses.replace(b, elements6=E, k_fe=float(k0), k_bend=0.0)
+
+
+def table2_bending_modulus():
+    """k_0 of Table 2 (200 k_B T at 300 K) in lattice units (energy unit rho h^5 / dt^2 with
+    h = 0.2 um, dt = 1e-8 s, plasma density 1.0239 g/cm^3)."""
+    h, dt, rho = 0.2e-6, 1e-8, 1023.9
+    return 200.0 * 1.380649e-23 * 300.0 / (rho * h ** 5 / dt ** 2)
 
 
 def table2_constraint_coefficients():
@@ -223,6 +269,19 @@ def _topology(nodes):
     V0, T = unit_sphere(nodes)
     V0, T = renumber(V0, T, morton_order(V0))
     return V0, T, mesh_edges(T), mesh_hinges(T)
+
+
+@functools.lru_cache(maxsize=None)
+def _quadratic(nodes):
+    """Six-node triangles of the icosphere mesh of `nodes` nodes, in _topology's numbering."""
+    for lev in range(1, 7):
+        if 10 * 4 ** lev + 2 == nodes:
+            V0, E6 = icosphere_quadratic(lev)
+            order = morton_order(V0)
+            inv = np.empty(len(order), np.int64)
+            inv[order] = np.arange(len(order))
+            return inv[E6].astype(np.int32)
+    raise ValueError("six-node triangles exist for icosphere node counts only, not %d" % nodes)
 
 
 def _concat(parts):
@@ -418,7 +477,7 @@ def concat_bodies(channels):
     """Bodies of several channels in one global node numbering (channel order), and the
     node offsets of the channels (len(channels) + 1 entries)."""
     Xs, Xr, E, H, A, offs = [], [], [], [], [], [0]
-    T, TO = [], [0]
+    T, TO, E6, kf = [], [0], [], set()
     off = 0
     ks, kc = set(), set()
     for ch in channels:
@@ -427,6 +486,9 @@ def concat_bodies(channels):
             T.append(b.triangles + off)
             TO += [o + TO[-1] for o in b.tri_offsets[1:]]
         kc.add((b.k_area_global, b.k_area_local, b.k_volume))
+        if b.elements6 is not None:
+            E6.append(b.elements6 + off)
+        kf.add(b.k_fe)
         Xs.append(b.X)
         Xr.append(b.X_rest)
         E.append(b.edges + off)
@@ -436,7 +498,8 @@ def concat_bodies(channels):
         ks.add((b.k_spring, b.k_bend, b.k_tether))
         off += b.n
         offs.append(off)
-    if len(ks) != 1 or len(kc) != 1 or len(T) not in (0, len(channels)):
+    if len(ks) != 1 or len(kc) != 1 or len(kf) != 1 or len(T) not in (0, len(channels)) or \
+            len(E6) not in (0, len(channels)):
         raise ValueError("channels must share the membrane constants")
     k_spring, k_bend, k_tether = ks.pop()
     k_area_global, k_area_local, k_volume = kc.pop()
@@ -445,5 +508,6 @@ def concat_bodies(channels):
                edges=np.concatenate(E).astype(np.int32), hinges=np.concatenate(H).astype(np.int32), anchors=anchors,
                k_spring=k_spring, k_bend=k_bend, k_tether=k_tether, body_offsets=offs,
                triangles=np.concatenate(T).astype(np.int32) if T else None, tri_offsets=TO if T else [],
-               k_area_global=k_area_global, k_area_local=k_area_local, k_volume=k_volume)
+               k_area_global=k_area_global, k_area_local=k_area_local, k_volume=k_volume,
+               elements6=np.concatenate(E6).astype(np.int32) if E6 else None, k_fe=kf.pop())
     return b, offs
