@@ -24,7 +24,7 @@
  *                by the caller.  The library never allocates device memory: the caller
  *                provides one workspace of lbm_workspace_bytes() bytes to lbm_create() and
  *                keeps it alive until lbm_destroy().  The library owns only the small host
- *                handle.
+ *                handle, and one fixed device array per GPU that mlp_grad_noalloc uses.
  *   Streams      every call only enqueues work on the context's stream (a hipStream_t
  *                passed as void*); outputs are valid after that stream synchronises.
  *                Calls that return data to the host (lbm_error_flags) synchronise it.
@@ -289,6 +289,20 @@ lbm_status mlp_forward(const void* packed, const float* raw, int64_t B, float* d
 size_t mlp_grad_workspace_bytes(int64_t B);
 lbm_status mlp_grad(const void* packed, const float* raw, const float* target, int64_t B, float* grad,
                     float* loss, void* work, size_t work_bytes, void* stream);
+
+/* mlp_grad for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * training loops, harnesses that forbid hipMalloc): the same kernels, the same partition of the
+ * B samples over workgroups and so the same bits as mlp_grad, with the per-workgroup partial
+ * sums in a scratch array the library holds per GPU (1024 rows of MLP_PARAMS + 1 floats,
+ * 25.8 MB, kept until the process ends) instead of a caller workspace.  It calls no allocating
+ * routine.  The scratch's address on the current device is looked up on the first call there;
+ * `stream` must belong to the current device (else LBM_ERR_ARG).  B >= 1; every B fits, since
+ * the kernel never runs more than 1024 workgroups (a B needing more rows than the scratch holds
+ * is rejected with LBM_ERR_ARG).  All calls on one GPU share its scratch: calls that overlap in
+ * time on that GPU (different streams, host threads) race and must be serialised by the caller;
+ * calls in order on one stream are safe, and nothing needs clearing between them. */
+lbm_status mlp_grad_noalloc(const void* packed, const float* raw, const float* target, int64_t B, float* grad,
+                            float* loss, void* stream);
 
 /* Adam (Kingma & Ba 2015) on n float32 parameters: m, v are the moment buffers (zero at
  * step 1), step counts from 1. */

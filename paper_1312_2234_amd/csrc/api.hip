@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "lbm_internal.h"
 
@@ -714,12 +715,14 @@ lbm_status lbm_stream_copy(const void* src, void* dst, size_t bytes, int32_t var
 }
 
 // ---------------------------------------------------------------- learned closure
+}  // extern "C"
 namespace {
 constexpr int64_t MLP_GRID = 1024;  // fixed workgroup counts: results do not depend on the GPU
 constexpr int64_t NORM_GRID = 1024;
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 }  // namespace
+extern "C" {
 
 lbm_status mlp_pack(const float* params, const float* norm, float c_guard, void* packed, void* stream) {
     if (!params || !norm || !packed || !(c_guard >= 0.0f) || !aligned16(packed)) return LBM_ERR_ARG;
@@ -765,6 +768,56 @@ lbm_status mlp_grad(const void* packed, const float* raw, const float* target, i
     const int64_t nblk = mlp_grad_blocks(B, MLP_GRID);
     return hip_ok(launch_mlp_grad((hipStream_t)stream, (const MlpPacked*)packed, raw, target, B, (float*)work, nblk,
                                   grad, loss));
+}
+
+// ---------------------------------------------------------------- mlp_grad without allocation
+}  // extern "C"
+namespace {
+// Scratch of mlp_grad_noalloc: the partial row (MLP_PARAMS gradient entries + the loss) of each
+// k_mlp_grad workgroup, as many rows as that kernel ever has workgroups (MLP_GRID), so the
+// variant partitions every B exactly as mlp_grad does.  k_mlp_grad writes every entry of its
+// rows before k_grad_reduce reads them, so nothing needs clearing between calls.  Each GPU holds
+// its own copy (MLP_GRID * 6289 floats = 25.8 MB) until the process ends.  In host code the
+// array's name stands for a host-side shadow: only the address looked up per device is used.
+constexpr int64_t NOALLOC_ROWS = MLP_GRID;
+static __device__ __align__(256) float scratch[NOALLOC_ROWS * (MLP_PARAMS + 1)];
+
+constexpr int NOALLOC_MAX_DEVICES = 256;
+std::mutex noalloc_mu;
+float* noalloc_ptr[NOALLOC_MAX_DEVICES];  // device address of each GPU's scratch, once looked up
+
+// The device address of the current GPU's scratch (looked up on the first call on that GPU).
+lbm_status noalloc_scratch(int dev, float** out) {
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LBM_ERR_HIP;
+        noalloc_ptr[dev] = (float*)p;
+    }
+    *out = noalloc_ptr[dev];
+    return LBM_OK;
+}
+}  // namespace
+extern "C" {
+
+lbm_status mlp_grad_noalloc(const void* packed, const float* raw, const float* target, int64_t B, float* grad,
+                            float* loss, void* stream) {
+    if (!packed || !raw || !target || !grad || B < 1 || !aligned16(packed)) return LBM_ERR_ARG;
+    const int64_t nblk = mlp_grad_blocks(B, MLP_GRID);
+    if (nblk > NOALLOC_ROWS) return LBM_ERR_ARG;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return LBM_ERR_HIP;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return LBM_ERR_UNSUPPORTED;
+    if (stream) {
+        hipDevice_t sdev = -1;
+        if (hipStreamGetDevice((hipStream_t)stream, &sdev) != hipSuccess) return LBM_ERR_HIP;
+        if (sdev != dev) return LBM_ERR_ARG;  // the scratch looked up is the current GPU's
+    }
+    float* work = nullptr;
+    lbm_status st = noalloc_scratch(dev, &work);
+    if (st != LBM_OK) return st;
+    return hip_ok(launch_mlp_grad((hipStream_t)stream, (const MlpPacked*)packed, raw, target, B, work, nblk, grad,
+                                  loss));
 }
 
 lbm_status mlp_adam(float* params, const float* grad, float* m, float* v, int64_t n, int32_t step, float lr,

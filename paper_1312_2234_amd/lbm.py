@@ -27,7 +27,7 @@ EXPORTS = [
     "lbm_coupled_steps", "lbm_graph_capture", "lbm_graph_launch", "lbm_set_launch", "lbm_get_launch",
     "lbm_stream_copy", "mlp_pack", "lbm_set_closure", "lbm_closure_guarded", "mlp_forward",
     "mlp_grad_workspace_bytes", "mlp_grad", "mlp_adam", "mlp_norm_workspace_bytes", "mlp_norm",
-    "lbm_restrict", "closure_targets", "lbm_launch_timer", "lbm_launch_timer_read",
+    "lbm_restrict", "closure_targets", "lbm_launch_timer", "lbm_launch_timer_read", "mlp_grad_noalloc",
 ]
 
 MLP_PARAMS, MLP_NORM, MLP_PACKED_BYTES = 6288, 48, 23360
@@ -109,6 +109,7 @@ def lib():
         L.mlp_grad_workspace_bytes.argtypes = [i64]
         L.mlp_grad_workspace_bytes.restype = C.c_size_t
         L.mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp, C.c_size_t, vp]
+        L.mlp_grad_noalloc.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.mlp_adam.argtypes = [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp]
         L.mlp_norm_workspace_bytes.argtypes = [i64]
         L.mlp_norm_workspace_bytes.restype = C.c_size_t
@@ -419,6 +420,20 @@ def mlp_grad(packed, raw, target, work=None):
     loss = torch.empty(1, dtype=torch.float32, device=raw.device)
     _check(lib().mlp_grad(_ptr(packed), _ptr(raw), _ptr(target), B, _ptr(grad), _ptr(loss), _ptr(work), nbytes,
                           _cur(torch, raw)), "mlp_grad")
+    return grad, loss
+
+
+def mlp_grad_noalloc(packed, raw, target, grad=None, loss=None):
+    """mlp_grad with the library's own per-GPU scratch: allocates no device memory when the caller
+    passes grad[6288] and loss[1]."""
+    import torch
+
+    if grad is None:
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=raw.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=raw.device)
+    _check(lib().mlp_grad_noalloc(_ptr(packed), _ptr(raw), _ptr(target), raw.shape[0], _ptr(grad), _ptr(loss),
+                                  _cur(torch, raw)), "mlp_grad_noalloc")
     return grad, loss
 
 
