@@ -57,6 +57,14 @@ def make_workload(name):
                 "nodes, spring k=0.005 + bending 1e-4 + area/volume constraints of Eq. 4-5 (Table 2: "
                 "k_s=k_t=%.4f, k_v=%.4f lattice units)" % (ks, kv))
         return [ch], desc
+    if name == "shear_fe":
+        k0 = inputs.table2_bending_modulus()
+        ch = inputs.shear_platelets(seed=0)
+        ch = dataclasses.replace(ch, bodies=inputs.with_fe_bending(ch.bodies, k0))
+        desc = ("shear channel 256x128x128, top wall u=0.05, tau=1.0, 16 oblate platelets (6,2,6) x 2562 IB "
+                "nodes, spring k=0.005 + finite-element bending of Eq. 6-10 on six-node triangles (Table 2: "
+                "k_0 = 200 k_BT = %.3e lattice units) in place of the dihedral stand-in" % k0)
+        return [ch], desc
     if name == "batched":
         chans = inputs.batched_channels(seed=0)
         desc = ("64 independent shear channels, sizes uniform over {48x32x32, 64x48x48, 96x64x64, 128x64x64}, "
@@ -136,7 +144,10 @@ def cpu_baseline(channels, kernel, steps, single_steps=4):
                        u_wall_hi=ch.u_wall_hi, kernel=kernel)
     o.init(u=o.shear_profile()) if ch.init == "shear" else o.init()
     mem = oracle.Membrane(b.X_rest, b.edges, k_spring=b.k_spring, hinges=b.hinges, k_bend=b.k_bend,
-                          anchors=b.anchors, k_tether=b.k_tether)
+                          anchors=b.anchors, k_tether=b.k_tether, triangles=b.triangles,
+                          body_tri=b.tri_offsets if b.triangles is not None else None,
+                          k_area_global=b.k_area_global, k_area_local=b.k_area_local, k_volume=b.k_volume,
+                          elements6=b.elements6, k_fe=b.k_fe)
     X = b.X.copy()
     oracle.coupled_step(o, mem, X)  # first touch of the arrays, not timed
     cores = oracle.threads()

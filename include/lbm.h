@@ -214,11 +214,30 @@ typedef struct {
     double k_area_global;      /* k_s of Eq. (4) */
     double k_area_local;       /* k_t of Eq. (4) */
     double k_volume;           /* k_v of Eq. (5) */
+    /* Finite-element bending of Eq. (6)-(10) (section 3.1): off when elem6 is NULL or k_fe is 0.
+     * Six-node quadratic triangles (Eq. (7)): corners a, b, c with outward normal
+     * (b - a) x (c - a), then the midpoint nodes of a-b, b-c, c-a.  At every node of every
+     * element the curvature tensor kappa of the interpolated surface solves Eq. (9), with the
+     * surface normal n and the node's share of the area (a third of each of the element's four
+     * flat sub-triangles around it); averaged over the node's elements they give the mean
+     * curvature K = tr(kappa)/2 (Eq. (10)), the Gaussian curvature G = ((tr kappa)^2 -
+     * tr(kappa kappa))/2, the unit normal and the area A.  Lap K is the node average of the
+     * surface divergence of the node-averaged surface gradient of K.  Force on a node:
+     * (k_fe/2)(Lap K + 2K(K^2 - G)) n A, the variational derivative of Eq. (6) (the force
+     * printed after Eq. (10) omits k_fe/2 and the Gaussian-curvature term).  FP64 arithmetic. */
+    const int32_t* elem6;      /* [ne][6] node ids */
+    int64_t ne;
+    const int32_t* elem_ptr;   /* [n+1] CSR node -> element-node incidences (6 ne in total) */
+    const int32_t* elem_inc;   /* [6 ne] (element id << 3) | local node 0..5 */
+    int32_t* elem_slot;        /* [ne][6] scratch: position of (element, local node) in elem_inc
+                                  (set by ib_membrane_rest) */
+    double* fe_work;           /* [84 ne + 6 n] scratch */
+    double k_fe;               /* k_0 of Eq. (6) */
 } ib_membrane;
 
 /* Measure rest lengths, rest dihedral angles and (with triangles) the rest areas and volumes
- * on X_rest ([3][n] float64); build hinge_slot.  Requires every hinge vertex's incidences in
- * hinge_ptr / hinge_inc. */
+ * on X_rest ([3][n] float64); build hinge_slot (and elem_slot).  Requires every hinge vertex's
+ * incidences in hinge_ptr / hinge_inc (every element node's in elem_ptr / elem_inc). */
 lbm_status ib_membrane_rest(const ib_membrane* m /*host*/, const double* X_rest, void* stream);
 /* F = -grad(E)(X), float64 arithmetic, float32 output [3][n]. */
 lbm_status ib_membrane_forces(const ib_membrane* m /*host*/, const double* X, float* F, void* stream);

@@ -16,6 +16,8 @@ import subprocess
 
 import numpy as np
 
+from . import bending_oracle
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
@@ -265,7 +267,7 @@ class Membrane:
 
     def __init__(self, X_rest, edges, k_spring=0.0, hinges=None, k_bend=0.0, anchors=None,
                  k_tether=0.0, triangles=None, body_tri=None, k_area_global=0.0, k_area_local=0.0,
-                 k_volume=0.0):
+                 k_volume=0.0, elements6=None, k_fe=0.0):
         X_rest = _f64(X_rest)
         self.n = X_rest.shape[1]
         self.edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
@@ -277,6 +279,9 @@ class Membrane:
         lib().orc_edge_lengths(self.n, _d(X_rest), len(self.edges), _i(self.edges), _d(self.rest_len))
         self.rest_theta = np.zeros(len(self.hinges))
         lib().orc_hinge_angles(self.n, _d(X_rest), len(self.hinges), _i(self.hinges), _d(self.rest_theta))
+        # finite-element bending of Eq. (6)-(10) (bending_oracle.py)
+        self.elements6 = None if elements6 is None else np.asarray(elements6, dtype=np.int64).reshape(-1, 6)
+        self.k_fe = float(k_fe)
         self.tri = (None if triangles is None
                     else np.ascontiguousarray(triangles, dtype=np.int32).reshape(-1, 3))
         self.k_area_global, self.k_area_local, self.k_volume = float(k_area_global), float(k_area_local), float(k_volume)
@@ -307,6 +312,8 @@ class Membrane:
                                       _d(self.rest_theta), self.k_bend, _d(self.anchors), self.k_tether)
         if self.tri is not None:
             E += lib().orc_constraint_energy(self.n, _d(X), *self._constraint_args())
+        if self.elements6 is not None and self.k_fe != 0.0:
+            E += bending_oracle.energy(X, self.elements6, self.k_fe)
         return E
 
     def forces(self, X):
@@ -319,6 +326,8 @@ class Membrane:
             Fc = np.empty_like(X)
             lib().orc_constraint_forces(self.n, _d(X), *self._constraint_args(), _d(Fc))
             F += Fc
+        if self.elements6 is not None and self.k_fe != 0.0:
+            F += bending_oracle.forces(X, self.elements6, self.k_fe)
         return F
 
 

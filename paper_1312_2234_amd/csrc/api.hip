@@ -493,8 +493,13 @@ lbm_status ib_advance(lbm_ctx* c, int64_t n, double* X, const float* U) {
     return hip_ok(launch_ib_advance(c->stream, n, X, U));
 }
 
-// The constraint arrays of Eq. (4)-(5) are all present when triangles are given.
+// The constraint arrays of Eq. (4)-(5) are all present when triangles are given, and the FE
+// bending arrays of Eq. (6)-(10) when elements are given with a nonzero modulus.
 static bool constraints_ok(const ib_membrane* m) {
+    if (m->elem6 && m->k_fe != 0.0) {
+        if (m->ne < 0 || (m->ne > 0 && (!m->elem_ptr || !m->elem_inc || !m->elem_slot || !m->fe_work)))
+            return false;
+    }
     if (!m->tri) return true;
     if (m->nt < 0 || m->nb < 0 || (m->nt > 0 && m->nb < 1)) return false;
     return m->tri_ptr && m->tri_inc && m->tri_body && m->body_tri && m->rest_area && m->rest_body && m->body_now;

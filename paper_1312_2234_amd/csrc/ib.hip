@@ -987,6 +987,252 @@ __global__ void k_tri_rest(ib_membrane m, const double* X) {
     m.rest_area[t] = 0.5 * sqrt(dt3(nn, nn));
 }
 
+// ---------------------------------------------------------------- FE bending (Eq. (6)-(10))
+__host__ __device__ inline bool fe_on(const ib_membrane& m) { return m.elem6 && m.ne > 0 && m.k_fe != 0.0; }
+
+// Scratch layout (CSR order of the element-node incidences, nnz = 6 ne): per incidence the
+// symmetric curvature tensor (xx, yy, zz, xy, xz, yz), the unit normal and the area share (10),
+// then the surface gradient of K (3), then the surface divergence of grad K (1); per node K, G,
+// the averaged unit normal and the area (6).
+struct FeWork {
+    double *kap, *grad, *div, *node;
+};
+__device__ __forceinline__ FeWork fe_work(const ib_membrane& m) {
+    const int64_t nnz = 6 * m.ne;
+    return {m.fe_work, m.fe_work + 10 * nnz, m.fe_work + 13 * nnz, m.fe_work + 14 * nnz};
+}
+
+// Parametric position (xi, eta) of local node k: corners (0,0), (1,0), (0,1), then the midpoints
+// (1/2,0), (1/2,1/2), (0,1/2).
+__device__ __forceinline__ void fe_node_xi(int k, double& xi, double& eta) {
+    xi = (k == 1) ? 1.0 : ((k == 3 || k == 4) ? 0.5 : 0.0);
+    eta = (k == 2) ? 1.0 : ((k == 4 || k == 5) ? 0.5 : 0.0);
+}
+
+// d N_j / d xi and d N_j / d eta of the quadratic six-node basis at (xi, eta); with z = 1 - xi - eta
+// the basis is z(2z-1), xi(2xi-1), eta(2eta-1), 4 xi z, 4 xi eta, 4 eta z.
+__device__ __forceinline__ void fe_dbasis(double xi, double eta, double dx[6], double de[6]) {
+    const double z = 1.0 - xi - eta;
+    dx[0] = 1.0 - 4.0 * z;  de[0] = 1.0 - 4.0 * z;
+    dx[1] = 4.0 * xi - 1.0; de[1] = 0.0;
+    dx[2] = 0.0;            de[2] = 4.0 * eta - 1.0;
+    dx[3] = 4.0 * (z - xi); de[3] = -4.0 * xi;
+    dx[4] = 4.0 * eta;      de[4] = 4.0 * xi;
+    dx[5] = -4.0 * eta;     de[5] = 4.0 * (z - eta);
+}
+
+// Geometry of the interpolated surface of an element (node positions P) at its local node k:
+// tangents a1 = dX/dxi, a2 = dX/deta, |a1 x a2|, unit normal n, dual tangents d1, d2
+// (d_a . a_b = delta_ab, in the tangent plane) and with `curv` the normal's derivatives
+// dn/dxi, dn/deta (from the constant second derivatives of the quadratic interpolation).
+struct FeFrame {
+    double a1[3], a2[3], n[3], d1[3], d2[3], dn1[3], dn2[3], mn;
+};
+__device__ void fe_frame(const double P[6][3], int k, bool curv, FeFrame& f) {
+    double xi, eta, dx[6], de[6];
+    fe_node_xi(k, xi, eta);
+    fe_dbasis(xi, eta, dx, de);
+    for (int c = 0; c < 3; ++c) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int j = 0; j < 6; ++j) {
+            s1 += dx[j] * P[j][c];
+            s2 += de[j] * P[j][c];
+        }
+        f.a1[c] = s1;
+        f.a2[c] = s2;
+    }
+    double m[3];
+    crs(f.a1, f.a2, m);
+    f.mn = sqrt(dt3(m, m));
+    const double im = 1.0 / f.mn;
+    for (int c = 0; c < 3; ++c) f.n[c] = m[c] * im;
+    const double g11 = dt3(f.a1, f.a1), g12 = dt3(f.a1, f.a2), g22 = dt3(f.a2, f.a2);
+    const double idet = 1.0 / (g11 * g22 - g12 * g12);
+    for (int c = 0; c < 3; ++c) {
+        f.d1[c] = (g22 * f.a1[c] - g12 * f.a2[c]) * idet;
+        f.d2[c] = (g11 * f.a2[c] - g12 * f.a1[c]) * idet;
+    }
+    if (!curv) return;
+    // second derivatives: X_xixi = 4(a + b) - 8 m_ab, X_xieta = 4(a - m_ab + m_bc - m_ca),
+    // X_etaeta = 4(a + c) - 8 m_ca
+    double a11[3], a12[3], a22[3];
+    for (int c = 0; c < 3; ++c) {
+        a11[c] = 4.0 * (P[0][c] + P[1][c]) - 8.0 * P[3][c];
+        a12[c] = 4.0 * (P[0][c] - P[3][c] + P[4][c] - P[5][c]);
+        a22[c] = 4.0 * (P[0][c] + P[2][c]) - 8.0 * P[5][c];
+    }
+    // d(a1 x a2)/dxi = a11 x a2 + a1 x a12, d(a1 x a2)/deta = a12 x a2 + a1 x a22; the unit
+    // normal's derivative is the tangential part over |a1 x a2|
+    double u[3], v[3], dm1[3], dm2[3];
+    crs(a11, f.a2, u); crs(f.a1, a12, v);
+    for (int c = 0; c < 3; ++c) dm1[c] = u[c] + v[c];
+    crs(a12, f.a2, u); crs(f.a1, a22, v);
+    for (int c = 0; c < 3; ++c) dm2[c] = u[c] + v[c];
+    const double p1 = dt3(f.n, dm1), p2 = dt3(f.n, dm2);
+    for (int c = 0; c < 3; ++c) {
+        f.dn1[c] = (dm1[c] - p1 * f.n[c]) * im;
+        f.dn2[c] = (dm2[c] - p2 * f.n[c]) * im;
+    }
+}
+
+__device__ __forceinline__ void fe_load(const ib_membrane& m, const double* X, int64_t e, double P[6][3]) {
+    for (int j = 0; j < 6; ++j) ld3(X, m.n, m.elem6[6 * e + j], P[j]);
+}
+
+__device__ __forceinline__ double tri_area(const double a[3], const double b[3], const double c[3]) {
+    double u[3], v[3], w[3];
+    sub(b, a, u);
+    sub(c, a, v);
+    crs(u, v, w);
+    return 0.5 * sqrt(dt3(w, w));
+}
+
+// First pass, one element node per lane (8 lanes per element, 6 in use): Eq. (9)'s curvature
+// tensor kappa = d1 (x) dn/dxi + d2 (x) dn/deta (symmetric part), the normal, and the node's area
+// share: a third of the flat sub-triangles (a, m_ab, m_ca), (m_ab, b, m_bc), (m_ca, m_bc, c),
+// (m_ab, m_bc, m_ca) that contain it.
+__device__ __forceinline__ void fe_kappa_one(const ib_membrane& m, const double* X, int64_t t) {
+    const int64_t e = t >> 3;
+    const int k = (int)(t & 7);
+    if (e >= m.ne || k >= 6) return;
+    double P[6][3];
+    fe_load(m, X, e, P);
+    FeFrame f;
+    fe_frame(P, k, true, f);
+    double* o = fe_work(m).kap + 10 * (int64_t)m.elem_slot[6 * e + k];
+    o[0] = f.d1[0] * f.dn1[0] + f.d2[0] * f.dn2[0];
+    o[1] = f.d1[1] * f.dn1[1] + f.d2[1] * f.dn2[1];
+    o[2] = f.d1[2] * f.dn1[2] + f.d2[2] * f.dn2[2];
+    o[3] = 0.5 * (f.d1[0] * f.dn1[1] + f.d2[0] * f.dn2[1] + f.d1[1] * f.dn1[0] + f.d2[1] * f.dn2[0]);
+    o[4] = 0.5 * (f.d1[0] * f.dn1[2] + f.d2[0] * f.dn2[2] + f.d1[2] * f.dn1[0] + f.d2[2] * f.dn2[0]);
+    o[5] = 0.5 * (f.d1[1] * f.dn1[2] + f.d2[1] * f.dn2[2] + f.d1[2] * f.dn1[1] + f.d2[2] * f.dn2[1]);
+    o[6] = f.n[0];
+    o[7] = f.n[1];
+    o[8] = f.n[2];
+    double A;
+    if (k < 3) {  // corner: its one sub-triangle
+        const int mprev = k == 0 ? 5 : k + 2, mnext = k + 3;
+        A = tri_area(P[k], P[mnext], P[mprev]);
+    } else {      // midpoint: the centre sub-triangle and the two corner ones beside it
+        const int c0 = k - 3, c1 = (k - 2) % 3;
+        A = tri_area(P[3], P[4], P[5]) + tri_area(P[c0], P[k], P[c0 == 0 ? 5 : c0 + 2]) +
+            tri_area(P[c1], P[c1 + 3], P[k]);
+    }
+    o[9] = A * (1.0 / 3.0);
+}
+
+__global__ void __launch_bounds__(256) k_fe_kappa(ib_membrane m, const double* X) {
+    fe_kappa_one(m, X, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Node averages of the first pass for node i: K = tr(kappa)/2, G = ((tr kappa)^2 - tr(kappa^2))/2,
+// the unit normal, the area.
+__device__ __forceinline__ void fe_node_avg(const ib_membrane& m, int64_t i, double out[6]) {
+    const double* w = fe_work(m).kap;
+    double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int p0 = m.elem_ptr[i], p1 = m.elem_ptr[i + 1];
+    for (int p = p0; p < p1; ++p)
+        for (int q = 0; q < 10; ++q) s[q] += w[10 * (int64_t)p + q];
+    const double ic = 1.0 / (double)(p1 - p0);
+    double kap[6];
+    for (int q = 0; q < 6; ++q) kap[q] = s[q] * ic;
+    const double tr = kap[0] + kap[1] + kap[2];
+    const double sq = kap[0] * kap[0] + kap[1] * kap[1] + kap[2] * kap[2] +
+                      2.0 * (kap[3] * kap[3] + kap[4] * kap[4] + kap[5] * kap[5]);
+    const double nl = 1.0 / sqrt(s[6] * s[6] + s[7] * s[7] + s[8] * s[8]);
+    out[0] = 0.5 * tr;
+    out[1] = 0.5 * (tr * tr - sq);
+    out[2] = s[6] * nl;
+    out[3] = s[7] * nl;
+    out[4] = s[8] * nl;
+    out[5] = s[9];
+}
+
+// Second pass: node averages of the first (stored once per node, by the node's first incidence),
+// then at every element node the surface gradient of the quadratically interpolated K:
+// d1 dK/dxi + d2 dK/deta.  The element's six lanes exchange their nodes' K by lane shuffles.
+__global__ void __launch_bounds__(256) k_fe_grad(ib_membrane m, const double* X) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = t >> 3;
+    const int k = (int)(t & 7);
+    const bool on = e < m.ne && k < 6;
+    const FeWork W = fe_work(m);
+    double K = 0.0;
+    if (on) {
+        const int64_t i = m.elem6[6 * e + k];
+        double nd[6];
+        fe_node_avg(m, i, nd);
+        K = nd[0];
+        if (m.elem_slot[6 * e + k] == m.elem_ptr[i])
+            for (int q = 0; q < 6; ++q) W.node[6 * i + q] = nd[q];
+    }
+    const int base = threadIdx.x & ~7;  // first lane of this element's group
+    double Kj[6];
+    for (int j = 0; j < 6; ++j) Kj[j] = __shfl(K, base + j, 64);
+    if (!on) return;
+    double P[6][3];
+    fe_load(m, X, e, P);
+    FeFrame f;
+    fe_frame(P, k, false, f);
+    double xi, eta, dx[6], de[6];
+    fe_node_xi(k, xi, eta);
+    fe_dbasis(xi, eta, dx, de);
+    double k1 = 0.0, k2 = 0.0;
+    for (int j = 0; j < 6; ++j) {
+        k1 += dx[j] * Kj[j];
+        k2 += de[j] * Kj[j];
+    }
+    double* o = W.grad + 3 * (int64_t)m.elem_slot[6 * e + k];
+    for (int c = 0; c < 3; ++c) o[c] = f.d1[c] * k1 + f.d2[c] * k2;
+}
+
+// Third pass: node averages of the gradient, then at every element node the surface divergence
+// d1 . d(grad K)/dxi + d2 . d(grad K)/deta of the interpolated gradient field.
+__global__ void __launch_bounds__(256) k_fe_div(ib_membrane m, const double* X) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = t >> 3;
+    const int k = (int)(t & 7);
+    const bool on = e < m.ne && k < 6;
+    const FeWork W = fe_work(m);
+    double g[3] = {0.0, 0.0, 0.0};
+    if (on) {
+        const int64_t i = m.elem6[6 * e + k];
+        const int p0 = m.elem_ptr[i], p1 = m.elem_ptr[i + 1];
+        for (int p = p0; p < p1; ++p)
+            for (int c = 0; c < 3; ++c) g[c] += W.grad[3 * (int64_t)p + c];
+        const double ic = 1.0 / (double)(p1 - p0);
+        for (int c = 0; c < 3; ++c) g[c] *= ic;
+    }
+    const int base = threadIdx.x & ~7;
+    double G[6][3];
+    for (int j = 0; j < 6; ++j)
+        for (int c = 0; c < 3; ++c) G[j][c] = __shfl(g[c], base + j, 64);
+    if (!on) return;
+    double P[6][3];
+    fe_load(m, X, e, P);
+    FeFrame f;
+    fe_frame(P, k, false, f);
+    double xi, eta, dx[6], de[6];
+    fe_node_xi(k, xi, eta);
+    fe_dbasis(xi, eta, dx, de);
+    double g1[3] = {0.0, 0.0, 0.0}, g2[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < 6; ++j)
+        for (int c = 0; c < 3; ++c) {
+            g1[c] += dx[j] * G[j][c];
+            g2[c] += de[j] * G[j][c];
+        }
+    W.div[m.elem_slot[6 * e + k]] = dt3(f.d1, g1) + dt3(f.d2, g2);
+}
+
+// Inverse of the node -> element-node incidence CSR: position of (element, local node).
+__global__ void k_fe_slots(ib_membrane m, int64_t nnz) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnz) {
+        const int32_t code = m.elem_inc[p];
+        m.elem_slot[6 * (int64_t)(code >> 3) + (code & 7)] = (int32_t)p;
+    }
+}
+
 // Inverse of the node -> hinge incidence CSR: position of (hinge, role) in hinge_inc.
 __global__ void k_mem_hinge_slots(ib_membrane m, int64_t nnz) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1049,11 +1295,24 @@ __device__ __forceinline__ void forces_block(const ib_membrane& m, const double*
             for (int d = 0; d < 3; ++d) F[d] -= al * dS[d] + be * dV[d];
         }
     }
+    // FE bending: the node average of the third pass's divergence is Lap K
+    double lap = 0.0;
+    const bool fe = fe_on(m);
+    if (fe && valid)
+        for (int e = m.elem_ptr[i] + sl; e < m.elem_ptr[i + 1]; e += 8) lap += fe_work(m).div[e];
 #pragma unroll
     for (int d = 1; d < 8; d <<= 1) {
         F[0] += __shfl_xor(F[0], d, 64);
         F[1] += __shfl_xor(F[1], d, 64);
         F[2] += __shfl_xor(F[2], d, 64);
+        if (fe) lap += __shfl_xor(lap, d, 64);
+    }
+    if (fe && valid) {
+        const double* nd = fe_work(m).node + 6 * i;
+        const double K = nd[0];
+        lap /= (double)(m.elem_ptr[i + 1] - m.elem_ptr[i]);
+        const double f = 0.5 * m.k_fe * (lap + 2.0 * K * (K * K - nd[1])) * nd[5];
+        for (int d = 0; d < 3; ++d) F[d] += f * nd[2 + d];
     }
     if (valid && m.anchors)
         for (int d = 0; d < 3; ++d) F[d] -= m.k_tether * (xi[d] - m.anchors[d * m.n + i]);
@@ -1109,19 +1368,21 @@ __global__ void __launch_bounds__(FS_THREADS) k_forces_scan(ib_membrane m, const
 
 // The coupled step's first launch: the binning of the nodes by position (workgroups
 // [0, nbb), dispatched first: theirs is the longer dependent chain), the bodies' areas and
-// volumes for the constraints (the next nbd, one per body) and the hinge forces (the rest);
-// the binning depends on neither.
+// volumes for the constraints (the next nbd, one per body), the hinge forces (the next nbh)
+// and the first pass of the FE bending (the rest); the binning depends on none of them.
 template <bool CONS>
 __global__ void __launch_bounds__(256) k_hinges_bin(ib_membrane m, const double* X, IbArgs a, int64_t nbb,
-                                                    int64_t nbd) {
+                                                    int64_t nbd, int64_t nbh) {
     const int64_t blk = blockIdx.x;
     if (blk < nbb) {
         bin_block(a, blk, false);
     } else if (CONS && blk < nbb + nbd) {
         body_block(m, X, m.body_now, blk - nbb, true);
-    } else {
+    } else if (blk < nbb + nbd + nbh) {
         const int64_t h = (blk - nbb - nbd) * blockDim.x + threadIdx.x;
         if (h < m.nh) hinge_one(m, X, h);
+    } else {
+        fe_kappa_one(m, X, (blk - nbb - nbd - nbh) * blockDim.x + threadIdx.x);
     }
 }
 
@@ -1137,13 +1398,28 @@ hipError_t launch_membrane_rest(const ib_membrane* m, const double* X_rest, hipS
         const int64_t nnz = 4 * m->nh;
         k_mem_hinge_slots<<<dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s>>>(*m, nnz);
     }
+    if (fe_on(*m)) {
+        const int64_t nnz = 6 * m->ne;
+        k_fe_slots<<<dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s>>>(*m, nnz);
+    }
     return hipGetLastError();
+}
+
+// The second and third FE bending passes (the first shares a launch or runs before them).
+static void launch_fe_passes(const ib_membrane* m, const double* X, hipStream_t s) {
+    const dim3 g((unsigned)((8 * m->ne + 255) / 256)), b(256);
+    k_fe_grad<<<g, b, 0, s>>>(*m, X);
+    k_fe_div<<<g, b, 0, s>>>(*m, X);
 }
 
 hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* F, hipStream_t s) {
     if (m->n <= 0) return hipSuccess;
     if (m->hinge_ptr && m->k_bend != 0.0 && m->nh > 0)
         k_mem_hinges<<<dim3((unsigned)((m->nh + 255) / 256)), dim3(256), 0, s>>>(*m, X);
+    if (fe_on(*m)) {
+        k_fe_kappa<<<dim3((unsigned)((8 * m->ne + 255) / 256)), dim3(256), 0, s>>>(*m, X);
+        launch_fe_passes(m, X, s);
+    }
     const dim3 gf((unsigned)((8 * m->n + 255) / 256)), bf(256);
     if (constraints_on(*m)) {
         k_mem_bodies<<<dim3((unsigned)m->nb), dim3(BODY_THREADS), 0, s>>>(*m, X, m->body_now, true);
@@ -1161,10 +1437,13 @@ hipError_t launch_forces_scatter(lbm_ctx* c, const ib_membrane* m, const double*
     const int64_t nbh = hinges ? (m->nh + 255) / 256 : 0;
     const int64_t nbb = (a.n + 255) / 256;
     const int64_t nbd = constraints_on(*m) ? m->nb : 0;
+    const int64_t nbe = fe_on(*m) ? (8 * m->ne + 255) / 256 : 0;
+    const dim3 g1((unsigned)(nbh + nbb + nbd + nbe));
     if (nbd > 0)
-        k_hinges_bin<true><<<dim3((unsigned)(nbh + nbb + nbd)), dim3(256), 0, c->stream>>>(*m, X, a, nbb, nbd);
-    else if (nbh + nbb > 0)
-        k_hinges_bin<false><<<dim3((unsigned)(nbh + nbb)), dim3(256), 0, c->stream>>>(*m, X, a, nbb, 0);
+        k_hinges_bin<true><<<g1, dim3(256), 0, c->stream>>>(*m, X, a, nbb, nbd, nbh);
+    else if (nbh + nbb + nbe > 0)
+        k_hinges_bin<false><<<g1, dim3(256), 0, c->stream>>>(*m, X, a, nbb, 0, nbh);
+    if (nbe > 0) launch_fe_passes(m, X, c->stream);
     const int64_t nbf = (8 * m->n + FS_THREADS - 1) / FS_THREADS;
     a.blkmax_n = nbf;
     a.scale_in_scatter = 1;

@@ -151,6 +151,19 @@ def csr_hinges(n, hinges):
     return np.cumsum(ptr).astype(np.int32), code.astype(np.int32)
 
 
+def csr_elements(n, E6):
+    """CSR incidence node -> (element << 3 | local node), local node 0..5; per node in element
+    order."""
+    ne = len(E6)
+    node = np.asarray(E6, np.int64).reshape(-1)
+    code = (np.repeat(np.arange(ne, dtype=np.int64), 6) << 3) | np.tile(np.arange(6), ne)
+    order = np.lexsort((code, node))
+    node, code = node[order], code[order]
+    ptr = np.zeros(n + 1, np.int64)
+    np.add.at(ptr, node + 1, 1)
+    return np.cumsum(ptr).astype(np.int32), code.astype(np.int32)
+
+
 def csr_triangles(n, tri):
     """CSR incidence node -> (triangle << 2 | corner), corner 0..2 = position in the triangle."""
     nt = len(tri)
@@ -233,6 +246,50 @@ def table2_bending_modulus():
     h = 0.2 um, dt = 1e-8 s, plasma density 1.0239 g/cm^3)."""
     h, dt, rho = 0.2e-6, 1e-8, 1023.9
     return 200.0 * 1.380649e-23 * 300.0 / (rho * h ** 5 / dt ** 2)
+
+
+def receptor_points(b, per_body=5344, seed=0):
+    """Receptor points of the adhesion model (section 3.2: 5344 per platelet, each standing for two
+    GPIb-alpha receptors), uniform over each body's rest surface: a triangle of the body's sphere
+    mesh drawn with probability proportional to its rest area, then uniform barycentric weights.
+    Returns (rec_tri [nr, 3] int32 node ids, rec_bary [nr, 3] float64)."""
+    rng = np.random.default_rng(seed)
+    T_all, W_all = [], []
+    for lo, hi in zip(b.body_offsets[:-1], b.body_offsets[1:]):
+        T = _topology(hi - lo)[1] + lo
+        P = b.X_rest.T[T]
+        area = 0.5 * np.linalg.norm(np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]), axis=1)
+        t = rng.choice(len(T), size=per_body, p=area / area.sum())
+        u1, u2 = rng.uniform(size=per_body), rng.uniform(size=per_body)
+        s1 = np.sqrt(u1)
+        W_all.append(np.stack([1.0 - s1, s1 * (1.0 - u2), s1 * u2], axis=1))
+        T_all.append(T[t])
+    return np.concatenate(T_all).astype(np.int32), np.concatenate(W_all)
+
+
+def wall_ligands(nx, nz, density=1.0, seed=0):
+    """Immobilised ligand (vWF) points on the lower wall, uniform over the nx x nz plane:
+    round(density nx nz) of them, as (x, z) [nl, 2] float64 (25 per um^2 is 1.0 per lattice
+    unit^2 at h = 0.2 um)."""
+    rng = np.random.default_rng(seed)
+    nl = int(round(density * nx * nz))
+    return np.stack([rng.uniform(0.0, nx, nl), rng.uniform(0.0, nz, nl)], axis=1)
+
+
+def table2_adhesion(sigma_si=1e-3, l_b_si=128e-9, gamma_si=0.7e-9):
+    """Adhesion parameters in lattice units (h = 0.2 um, dt = 1e-8 s, plasma density
+    1.0239 g/cm^3): per-step rates k_on0 dt and k_off0 dt of Table 2 (1e-5 and 3.45 per s), kT at
+    300 K, the capture radius (the 128 nm bond length of section 3.2) and the receptor and ligand
+    densities of section 3.2.  The spring constant sigma (N/m), the rest length l_b (m) and the
+    reactive compliance gamma (m) are not in Table 2: the caller supplies them (the default rest
+    length is the bond length of section 3.2; sigma and gamma default to assumptions of this
+    workload, not values of the paper)."""
+    h, dt, rho = 0.2e-6, 1e-8, 1023.9
+    force = rho * h ** 4 / dt ** 2
+    energy = rho * h ** 5 / dt ** 2
+    return dict(k_on0=1e-5 * dt, k_off0=3.45 * dt, kT=1.380649e-23 * 300.0 / energy, capture=128e-9 / h,
+                sigma=sigma_si / (force / h), l_b=l_b_si / h, gamma=gamma_si / h, receptors_per_body=5344,
+                ligand_density=25e12 * h * h)
 
 
 def table2_constraint_coefficients():

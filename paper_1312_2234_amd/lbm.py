@@ -56,7 +56,9 @@ class IbMembrane(C.Structure):
                 ("tri", C.c_void_p), ("nt", C.c_int64), ("tri_ptr", C.c_void_p), ("tri_inc", C.c_void_p),
                 ("tri_body", C.c_void_p), ("body_tri", C.c_void_p), ("nb", C.c_int64),
                 ("rest_area", C.c_void_p), ("rest_body", C.c_void_p), ("body_now", C.c_void_p),
-                ("k_area_global", C.c_double), ("k_area_local", C.c_double), ("k_volume", C.c_double)]
+                ("k_area_global", C.c_double), ("k_area_local", C.c_double), ("k_volume", C.c_double),
+                ("elem6", C.c_void_p), ("ne", C.c_int64), ("elem_ptr", C.c_void_p), ("elem_inc", C.c_void_p),
+                ("elem_slot", C.c_void_p), ("fe_work", C.c_void_p), ("k_fe", C.c_double)]
 
 
 _lib = None
@@ -535,6 +537,17 @@ class Membrane:
             s.tri_body, s.body_tri, s.nb = tb_d.data_ptr(), bt_d.data_ptr(), nb
             s.rest_area, s.rest_body, s.body_now = ra.data_ptr(), rb.data_ptr(), bn.data_ptr()
             s.k_area_global, s.k_area_local, s.k_volume = ks
+        e6 = getattr(bodies, "elements6", None)
+        if e6 is not None and len(e6) and float(getattr(bodies, "k_fe", 0.0)) != 0.0:
+            e6 = np.ascontiguousarray(e6, dtype=np.int32).reshape(-1, 6)
+            ep, einc = inputs.csr_elements(n, e6)
+            e_d, ep_d, ei_d = dev_i32(e6.reshape(-1)), dev_i32(ep), dev_i32(einc)
+            es = torch.zeros(6 * len(e6), dtype=torch.int32, device=dev)
+            fw = torch.zeros(84 * len(e6) + 6 * n, dtype=torch.float64, device=dev)
+            self._keep += [es, fw]
+            s.elem6, s.ne, s.elem_ptr, s.elem_inc = e_d.data_ptr(), len(e6), ep_d.data_ptr(), ei_d.data_ptr()
+            s.elem_slot, s.fe_work, s.k_fe = es.data_ptr(), fw.data_ptr(), float(bodies.k_fe)
+            self.fe_work = fw
         self.struct = s
         self.n = n
         st = stream if stream is not None else _stream_ptr(torch, dev)

@@ -146,6 +146,10 @@ def test_bench_workloads_build():
     chans, desc = bench.make_workload("shear_constrained")
     b = chans[0].bodies
     assert b.triangles is not None and len(b.triangles) == 16 * 5120 and b.k_volume > b.k_area_global > 0
+    chans, desc = bench.make_workload("shear_fe")
+    b = chans[0].bodies
+    assert b.elements6 is not None and b.elements6.shape == (16 * 1280, 6) and b.k_bend == 0.0
+    assert abs(b.k_fe / 2.53e-4 - 1) < 1e-2 and "Eq. 6-10" in desc
     chans, desc = bench.make_workload("batched")
     assert len(chans) == 64
     chans, desc = bench.make_workload("coarse")

@@ -1,8 +1,9 @@
 """Parity at the benchmark's full sizes, in the launch configuration the benchmark times
 (launch shape from the tuned cache, steps replayed from a 2-step HIP graph), against the
 FP64 oracle on every cell: the 256x128x128 shear channel with 16 platelets of 2562 nodes
-(with halfway walls, with the on-site walls of Eq. 23-30, and with the area and volume
-constraints of Eq. 4-5 at Table 2's coefficients) over 100 coupled steps, and the 64-channel
+(with halfway walls, with the on-site walls of Eq. 23-30, with the area and volume
+constraints of Eq. 4-5 at Table 2's coefficients, and with the FE bending of Eq. 6-10 at Table 2's
+modulus in place of the dihedral stand-in) over 100 coupled steps, and the 64-channel
 batch (18.2 M cells, 0.50 M nodes) over 20.  Tolerances as in test_gpu_parity: velocity
 e_max <= 1e-5, interpolated velocities likewise, wall stress 1e-4."""
 import dataclasses
@@ -45,10 +46,12 @@ def shear_workload(variant):
         ch = dataclasses.replace(ch, walls="onsite")
     if variant == "constrained":
         ch = dataclasses.replace(ch, bodies=inputs.with_constraints(ch.bodies, *inputs.table2_constraint_coefficients()))
+    if variant == "fe_bending":
+        ch = dataclasses.replace(ch, bodies=inputs.with_fe_bending(ch.bodies, inputs.table2_bending_modulus()))
     return ch
 
 
-@pytest.mark.parametrize("variant", ["halfway", "onsite", "constrained"])
+@pytest.mark.parametrize("variant", ["halfway", "onsite", "constrained", "fe_bending"])
 def test_full_shear_workload_against_oracle(orc, gpu, variant):
     ch = shear_workload(variant)
     steps = 100

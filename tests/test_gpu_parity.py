@@ -339,7 +339,8 @@ def run_oracle_coupled(orc, ch, kernel, steps):
     mem = orc.Membrane(b.X_rest, b.edges, k_spring=b.k_spring, hinges=b.hinges, k_bend=b.k_bend,
                        anchors=b.anchors, k_tether=b.k_tether, triangles=b.triangles,
                        body_tri=b.tri_offsets if b.triangles is not None else None,
-                       k_area_global=b.k_area_global, k_area_local=b.k_area_local, k_volume=b.k_volume)
+                       k_area_global=b.k_area_global, k_area_local=b.k_area_local, k_volume=b.k_volume,
+                       elements6=b.elements6, k_fe=b.k_fe)
     X = b.X.copy()
     for _ in range(steps):
         F, U = orc.coupled_step(o, mem, X)
