@@ -65,6 +65,13 @@ def make_workload(name):
                 "nodes, spring k=0.005 + finite-element bending of Eq. 6-10 on six-node triangles (Table 2: "
                 "k_0 = 200 k_BT = %.3e lattice units) in place of the dihedral stand-in" % k0)
         return [ch], desc
+    if name == "shear_adhesion":
+        ch = inputs.shear_platelets(seed=0, y_band=(2.3, 2.6))
+        desc = ("shear channel 256x128x128, top wall u=0.05, tau=1.0, 16 oblate platelets (6,2,6) x 2562 IB nodes "
+                "resting 0.1-0.6 lattice units above the lower wall, spring k=0.005 + bending 1e-4, with the "
+                "adhesion of section 3.2: 5344 receptor points per platelet, vWF ligands at 25 per um^2 on the "
+                "wall, Table 2's k_on0 and k_off0 (sigma = 1e-3 N/m, gamma = 0.7 nm assumed, l_b = 128 nm)")
+        return [ch], desc
     if name == "batched":
         chans = inputs.batched_channels(seed=0)
         desc = ("64 independent shear channels, sizes uniform over {48x32x32, 64x48x48, 96x64x64, 128x64x64}, "
@@ -132,7 +139,22 @@ def closure_weights(torch, dev):
     return (torch.from_numpy(th.astype(np.float32)).to(dev), torch.from_numpy(norm.astype(np.float32)).to(dev))
 
 
-def cpu_baseline(channels, kernel, steps, single_steps=4):
+def adhesion_of(workload, channels):
+    """The adhesion description of the shear_adhesion workload (None for the others)."""
+    if workload != "shear_adhesion":
+        return None
+    from paper_1312_2234_amd import inputs
+
+    ch = channels[0]
+    p = inputs.table2_adhesion()
+    rt, rb = inputs.receptor_points(ch.bodies, per_body=p["receptors_per_body"], seed=0)
+    lig = inputs.wall_ligands(ch.nx, ch.nz, density=p["ligand_density"], seed=1)
+    return dict(rec_tri=rt, rec_bary=rb, ligands=lig, wall_y=-0.5, nx=float(ch.nx), nz=float(ch.nz),
+                capture=p["capture"], sigma=p["sigma"], l_b=p["l_b"], gamma=p["gamma"], kT=p["kT"],
+                k_on0=p["k_on0"], k_off0=p["k_off0"], seed=0)
+
+
+def cpu_baseline(channels, kernel, steps, single_steps=4, adhesion=None):
     """The FP64 oracle (as it stands) on `steps` coupled steps of the first channel."""
     import numpy as np
 
@@ -148,12 +170,20 @@ def cpu_baseline(channels, kernel, steps, single_steps=4):
                           body_tri=b.tri_offsets if b.triangles is not None else None,
                           k_area_global=b.k_area_global, k_area_local=b.k_area_local, k_volume=b.k_volume,
                           elements6=b.elements6, k_fe=b.k_fe)
+    adh = None
+    if adhesion is not None:
+        from oracle import dam_oracle
+
+        a = adhesion
+        adh = dam_oracle.Adhesion(a["rec_tri"], a["rec_bary"], a["ligands"], a["wall_y"], a["nx"], a["nz"],
+                                  a["capture"], a["sigma"], a["l_b"], a["gamma"], a["kT"], a["k_on0"],
+                                  a["k_off0"], a["seed"])
     X = b.X.copy()
-    oracle.coupled_step(o, mem, X)  # first touch of the arrays, not timed
+    oracle.coupled_step(o, mem, X, adhesion=adh)  # first touch of the arrays, not timed
     cores = oracle.threads()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        oracle.coupled_step(o, mem, X)
+    for s in range(steps):
+        oracle.coupled_step(o, mem, X, adhesion=adh, step=s + 1)
     dt = time.perf_counter() - t0
     out = {"value": round(ch.cells * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": cores, "kind": "oracle",
            "sample": "%d coupled steps (forces, spread, LBM, interpolation, move) of the full %dx%dx%d "
@@ -162,8 +192,8 @@ def cpu_baseline(channels, kernel, steps, single_steps=4):
     if single_steps > 0:
         oracle.set_threads(1)
         t0 = time.perf_counter()
-        for _ in range(single_steps):
-            oracle.coupled_step(o, mem, X)
+        for s in range(single_steps):
+            oracle.coupled_step(o, mem, X, adhesion=adh, step=steps + 1 + s)
         d1 = time.perf_counter() - t0
         oracle.set_threads(cores)
         out["single_core"] = {"value": round(ch.cells * single_steps / d1 / 1e6, 4), "unit": "MLUPS", "cores": 1,
@@ -224,7 +254,7 @@ def main():
 
     b, offs = inputs.concat_bodies(channels)
     lat.set_nodes(b.n, offs if len(channels) > 1 else None)
-    mem = lbm.Membrane(b, device=dev)
+    mem = lbm.Membrane(b, device=dev, adhesion=adhesion_of(args.workload, channels))
     X = torch.from_numpy(b.X.copy()).to(dev)
     F = torch.zeros((3, b.n), dtype=torch.float32, device=dev)
     U = torch.zeros_like(F)
@@ -333,7 +363,8 @@ def main():
         del src, dst
     if not args.no_cpu_baseline and args.cpu_steps > 0 and len(channels) == 1:
         del lat
-        out["cpu_baseline"] = cpu_baseline(channels, args.kernel, args.cpu_steps, args.cpu_single_steps)
+        out["cpu_baseline"] = cpu_baseline(channels, args.kernel, args.cpu_steps, args.cpu_single_steps,
+                                           adhesion_of(args.workload, channels))
     print(json.dumps(out), flush=True)
 
 

@@ -72,6 +72,8 @@ typedef enum { IB_PHI_COS4 = 0, IB_PHI_PESKIN4 = 1 } ib_kernel;
 #define LBM_FLAG_LIST_OVERFLOW 0x2u /* IB tile lists exceeded their capacity (contributions lost) */
 #define LBM_FLAG_FORCE_NONFINITE 0x4u /* a Lagrangian force was Inf/NaN (force field set to NaN) */
 #define LBM_FLAG_CLOSURE_FALLBACK 0x8u /* the learned closure fell back to plain BGK at some node */
+#define LBM_FLAG_ADHESION_BIDS 0x10u /* a ligand received more adhesion bids in one step than its bid
+                                        list holds (ADH_MAX_BIDS): some were dropped */
 
 /* One channel (an independent lattice).  Section 3.3: lattice size, relaxation time tau
  * (Eq. (16), viscosity (tau - 1/2)/3 by Eq. (22)), constant body force added to the IB
@@ -233,7 +235,45 @@ typedef struct {
                                   (set by ib_membrane_rest) */
     double* fe_work;           /* [84 ne + 6 n] scratch */
     double k_fe;               /* k_0 of Eq. (6) */
+    /* Adhesion to the lower wall, section 3.2 (Eq. (12)-(14)): off when adh_nr is 0.  Receptor
+     * point r lies in the triangle rec_tri[r] at barycentric weights rec_bary[r]; ligands are
+     * points (x, z) on the wall plane y = adh_wall_y (x, z periodic with periods adh_nx, adh_nz).
+     * A bond joins one receptor to one ligand (at most one per receptor, four per ligand) and
+     * pulls as a spring of rest length adh_lb: F = -adh_sigma (|d| - adh_lb) d / |d|, d = receptor
+     * - ligand, shared among the triangle's nodes by the weights; ib_membrane_forces adds it
+     * (the H_wall term of Eq. (11)).  ib_adhesion_step (and every coupled step, after the move)
+     * runs one Monte-Carlo step: bonds present at the start break with P_r = 1 - exp(-k_off),
+     * k_off = adh_koff0 exp(adh_gamma F_b / adh_kT), F_b = adh_sigma | |d| - adh_lb | (Eq. (12));
+     * receptors unbound at the start bid with P_f = 1 - exp(-k_on), k_on = adh_kon0
+     * exp(adh_sigma s (adh_gamma - s/2) / adh_kT), s = | |d| - adh_lb | (Eq. (13) as printed), for
+     * the nearest ligand (lower id on a tie) closer than adh_capture that had fewer than four
+     * bonds at the start; each ligand accepts bids in ascending receptor id up to four bonds.
+     * Rates are per step (rate times dt).  Uniforms: Philox4x32-10, key adh_seed, counter
+     * (receptor, step, 0) with the step counted on the device from 0 (reset by ib_membrane_rest);
+     * words 0-1 decide the break, 2-3 the bid, as (w0 >> 5) 2^-27 + (w1 >> 6) 2^-53.  FP64. */
+    int64_t adh_nr;
+    const int32_t* rec_tri;    /* [nr][3] node ids */
+    const double* rec_bary;    /* [nr][3] barycentric weights */
+    const int32_t* rec_ptr;    /* [n+1] CSR node -> receptor incidences (3 nr in total) */
+    const int32_t* rec_inc;    /* [3 nr] (receptor << 2) | corner 0..2 */
+    int64_t adh_nl;            /* ligands */
+    const double* lig_xz;      /* [nl][2] */
+    int32_t* bond;             /* [nr] state: ligand id or -1 (the caller sets the initial bonds) */
+    int32_t* lig_count;        /* [nl] state: bonds per ligand (consistent with bond) */
+    int32_t* adh_work;         /* [ib_adhesion_work_ints()] scratch: the ligand table by wall
+                                  cell (built by ib_membrane_rest), the step counter, per-ligand
+                                  bids; word 2 counts bids lost to a full bid list (results then
+                                  differ from the stated rule) */
+    double adh_wall_y, adh_nx, adh_nz, adh_capture, adh_sigma, adh_lb, adh_gamma, adh_kT;
+    double adh_kon0, adh_koff0;
+    uint64_t adh_seed;
 } ib_membrane;
+
+#define ADH_MAX_BIDS 32 /* bids a ligand can receive in one step */
+/* int32 words of ib_membrane::adh_work for nl ligands on an nx x nz wall and the capture radius:
+ * 8 + nl (3 + ADH_MAX_BIDS) + 2 (cells + 1), cells = gx gz, gx = max(1, floor(nx / capture)) and gz
+ * likewise (evaluated in double precision); 0 on invalid arguments. */
+int64_t ib_adhesion_work_ints(int64_t nl, double nx, double nz, double capture);
 
 /* Measure rest lengths, rest dihedral angles and (with triangles) the rest areas and volumes
  * on X_rest ([3][n] float64); build hinge_slot (and elem_slot).  Requires every hinge vertex's
@@ -241,10 +281,14 @@ typedef struct {
 lbm_status ib_membrane_rest(const ib_membrane* m /*host*/, const double* X_rest, void* stream);
 /* F = -grad(E)(X), float64 arithmetic, float32 output [3][n]. */
 lbm_status ib_membrane_forces(const ib_membrane* m /*host*/, const double* X, float* F, void* stream);
+/* One Monte-Carlo step of the adhesion (section 3.2) at the positions X ([3][n] float64): updates
+ * bond, lig_count and the step counter.  LBM_ERR_ARG without adhesion. */
+lbm_status ib_adhesion_step(const ib_membrane* m /*host*/, const double* X, void* stream);
 
 /* ---------------------------------------------------------------- coupled sequence
  * `nsteps` full steps of Fig. 1 on the context's stream: ib_membrane_forces(X) ->
- * ib_spread(X, F) -> lbm_step(1) -> ib_interp(X) -> X += U.  m may be NULL (F given,
+ * ib_spread(X, F) -> lbm_step(1) -> ib_interp(X) -> X += U (-> ib_adhesion_step(X) when the
+ * membrane has adhesion).  m may be NULL (F given,
  * kept constant).  X is updated in place; F and U hold the last step's values. */
 lbm_status lbm_coupled_steps(lbm_ctx* ctx, const ib_membrane* m /*host*/, int32_t nsteps, double* X,
                              float* F, float* U);

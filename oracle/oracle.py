@@ -331,12 +331,18 @@ class Membrane:
         return F
 
 
-def coupled_step(lat: Lattice, mem: Membrane | None, X: np.ndarray):
-    """One step of Fig. 1: membrane forces F(X^n) -> spread g^n -> LBM step ->
-    interpolate v^{n+1} at X^n -> X^{n+1} = X^n + U.  Returns (F, U); X is updated in place."""
+def coupled_step(lat: Lattice, mem: Membrane | None, X: np.ndarray, adhesion=None, step=0):
+    """One step of Fig. 1: membrane forces F(X^n) (with the bonds of `adhesion`, a
+    dam_oracle.Adhesion) -> spread g^n -> LBM step -> interpolate v^{n+1} at X^n ->
+    X^{n+1} = X^n + U -> the adhesion's Monte-Carlo step `step` at X^{n+1}.  Returns (F, U); X is
+    updated in place."""
     F = mem.forces(X) if mem is not None else np.zeros_like(X)
+    if adhesion is not None:
+        F = F + adhesion.forces(X)
     lat.spread(X, F)
     lat.step(1)
     U = lat.interp(X)
     lib().orc_advance(X.shape[1], _d(X), _d(U))
+    if adhesion is not None:
+        adhesion.step(X, step)
     return F, U

@@ -496,6 +496,15 @@ lbm_status ib_advance(lbm_ctx* c, int64_t n, double* X, const float* U) {
 // The constraint arrays of Eq. (4)-(5) are all present when triangles are given, and the FE
 // bending arrays of Eq. (6)-(10) when elements are given with a nonzero modulus.
 static bool constraints_ok(const ib_membrane* m) {
+    if (m->adh_nr < 0 || m->adh_nl < 0) return false;
+    if (m->adh_nr > 0) {
+        if (m->adh_nl > 0 && (!m->rec_tri || !m->rec_bary || !m->rec_ptr || !m->rec_inc || !m->lig_xz || !m->bond ||
+                              !m->lig_count || !m->adh_work))
+            return false;
+        if (!(m->adh_capture > 0.0) || !(m->adh_nx > 0.0) || !(m->adh_nz > 0.0) || !(m->adh_kT > 0.0)) return false;
+        if (m->adh_nx / m->adh_capture > 1e7 || m->adh_nz / m->adh_capture > 1e7) return false;
+        if (m->adh_nl > 0 && !m->rec_ptr) return false;
+    }
     if (m->elem6 && m->k_fe != 0.0) {
         if (m->ne < 0 || (m->ne > 0 && (!m->elem_ptr || !m->elem_inc || !m->elem_slot || !m->fe_work)))
             return false;
@@ -522,6 +531,16 @@ lbm_status ib_membrane_forces(const ib_membrane* m, const double* X, float* F, v
                          (m->nh > 0 && (!m->hinge_force || !m->hinge_slot))))
         return LBM_ERR_ARG;
     return hip_ok(launch_membrane_forces(m, X, F, (hipStream_t)stream));
+}
+
+int64_t ib_adhesion_work_ints(int64_t nl, double nx, double nz, double capture) {
+    if (nl < 0 || !(nx > 0.0) || !(nz > 0.0) || !(capture > 0.0) || nx / capture > 1e7 || nz / capture > 1e7) return 0;
+    return adhesion_work_ints(nl, nx, nz, capture);
+}
+
+lbm_status ib_adhesion_step(const ib_membrane* m, const double* X, void* stream) {
+    if (!m || !X || !constraints_ok(m) || !adhesion_on(*m)) return LBM_ERR_ARG;
+    return hip_ok(launch_adhesion_step(m, X, nullptr, (hipStream_t)stream));
 }
 
 // Lattice update of the whole context with the body force alone, on the second stream,
@@ -600,6 +619,8 @@ static lbm_status coupled(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, doub
         b.Xout = X;  // X <- X + U, fused into the gather
         b.use_rec = 1;  // X is the spread's X
         if (launch_ib_interp(c, b) != hipSuccess) return LBM_ERR_HIP;
+        // the adhesion's Monte-Carlo step at the moved positions (the last box of Fig. 1)
+        if (m && launch_adhesion_step(m, X, (uint32_t*)c->d_flags, c->stream) != hipSuccess) return LBM_ERR_HIP;
     }
     return LBM_OK;
 }

@@ -1295,6 +1295,31 @@ __device__ __forceinline__ void forces_block(const ib_membrane& m, const double*
             for (int d = 0; d < 3; ++d) F[d] -= al * dS[d] + be * dV[d];
         }
     }
+    // adhesion bonds (Eq. (14)): each bonded receptor of the node's incidences pulls with the
+    // spring force times the node's barycentric weight
+    if (m.adh_nr > 0 && valid) {
+        for (int e = m.rec_ptr[i] + sl; e < m.rec_ptr[i + 1]; e += 8) {
+            const int32_t code = m.rec_inc[e];
+            const int64_t rr = code >> 2;
+            const int32_t l = m.bond[rr];
+            if (l < 0) continue;
+            double xr[3];
+            for (int c = 0; c < 3; ++c) {
+                double sacc = 0.0;
+                for (int k = 0; k < 3; ++k) sacc += m.rec_bary[3 * rr + k] * X[c * m.n + m.rec_tri[3 * rr + k]];
+                xr[c] = sacc;
+            }
+            double dx = xr[0] - m.lig_xz[2 * l], dz = xr[2] - m.lig_xz[2 * l + 1];
+            dx -= m.adh_nx * rint(dx / m.adh_nx);
+            dz -= m.adh_nz * rint(dz / m.adh_nz);
+            const double dy = xr[1] - m.adh_wall_y;
+            const double L = sqrt(dx * dx + dy * dy + dz * dz);
+            const double f = -m.adh_sigma * (L - m.adh_lb) / L * m.rec_bary[3 * rr + (code & 3)];
+            F[0] += f * dx;
+            F[1] += f * dy;
+            F[2] += f * dz;
+        }
+    }
     // FE bending: the node average of the third pass's divergence is Lap K
     double lap = 0.0;
     const bool fe = fe_on(m);
@@ -1402,7 +1427,9 @@ hipError_t launch_membrane_rest(const ib_membrane* m, const double* X_rest, hipS
         const int64_t nnz = 6 * m->ne;
         k_fe_slots<<<dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s>>>(*m, nnz);
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_adhesion_setup(m, s);
+    return e;
 }
 
 // The second and third FE bending passes (the first shares a launch or runs before them).

@@ -256,6 +256,11 @@ hipError_t launch_ib_advance(hipStream_t s, int64_t n, double* X, const float* U
 hipError_t launch_membrane_rest(const ib_membrane* m, const double* X_rest, hipStream_t s);
 hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* F, hipStream_t s);
 hipError_t launch_forces_scatter(lbm_ctx* c, const ib_membrane* m, const double* X, float* F, IbArgs& a);
+// adhesion (adhesion.hip)
+bool adhesion_on(const ib_membrane& m);
+int64_t adhesion_work_ints(int64_t nl, double nx, double nz, double capture);
+hipError_t launch_adhesion_setup(const ib_membrane* m, hipStream_t s);
+hipError_t launch_adhesion_step(const ib_membrane* m, const double* X, uint32_t* flags, hipStream_t s);
 hipError_t launch_spread_far(lbm_ctx* c, const IbArgs& a, const LatArgs& la);
 
 // closure.hip

@@ -164,6 +164,18 @@ def csr_elements(n, E6):
     return np.cumsum(ptr).astype(np.int32), code.astype(np.int32)
 
 
+def csr_receptors(n, rec_tri):
+    """CSR incidence node -> (receptor << 2 | corner), corner 0..2; per node in receptor order."""
+    nr = len(rec_tri)
+    node = np.asarray(rec_tri, np.int64).reshape(-1)
+    code = (np.repeat(np.arange(nr, dtype=np.int64), 3) << 2) | np.tile(np.arange(3), nr)
+    order = np.lexsort((code, node))
+    node, code = node[order], code[order]
+    ptr = np.zeros(n + 1, np.int64)
+    np.add.at(ptr, node + 1, 1)
+    return np.cumsum(ptr).astype(np.int32), code.astype(np.int32)
+
+
 def csr_triangles(n, tri):
     """CSR incidence node -> (triangle << 2 | corner), corner 0..2 = position in the triangle."""
     nt = len(tri)

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblbmib.so")
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 KERNEL = {"cos": 0, "peskin4": 1}
 FLAG_NODE_OUTSIDE, FLAG_LIST_OVERFLOW, FLAG_FORCE_NONFINITE, FLAG_CLOSURE_FALLBACK = 1, 2, 4, 8
+FLAG_ADHESION_BIDS = 16
 
 EXPORTS = [
     "lbm_workspace_bytes", "lbm_create", "lbm_destroy", "lbm_init", "lbm_step", "ib_set_nodes",
@@ -28,11 +29,12 @@ EXPORTS = [
     "lbm_stream_copy", "mlp_pack", "lbm_set_closure", "lbm_closure_guarded", "mlp_forward",
     "mlp_grad_workspace_bytes", "mlp_grad", "mlp_adam", "mlp_norm_workspace_bytes", "mlp_norm",
     "lbm_restrict", "closure_targets", "lbm_launch_timer", "lbm_launch_timer_read", "mlp_grad_noalloc",
+    "ib_adhesion_step", "ib_adhesion_work_ints",
 ]
 
 MLP_PARAMS, MLP_NORM, MLP_PACKED_BYTES = 6288, 48, 23360
 _SIZE_FNS = ("lbm_workspace_bytes", "lbm_state_bytes", "lbm_status_string", "mlp_grad_workspace_bytes",
-             "mlp_norm_workspace_bytes")
+             "mlp_norm_workspace_bytes", "ib_adhesion_work_ints")
 
 
 class LbmParams(C.Structure):
@@ -58,7 +60,16 @@ class IbMembrane(C.Structure):
                 ("rest_area", C.c_void_p), ("rest_body", C.c_void_p), ("body_now", C.c_void_p),
                 ("k_area_global", C.c_double), ("k_area_local", C.c_double), ("k_volume", C.c_double),
                 ("elem6", C.c_void_p), ("ne", C.c_int64), ("elem_ptr", C.c_void_p), ("elem_inc", C.c_void_p),
-                ("elem_slot", C.c_void_p), ("fe_work", C.c_void_p), ("k_fe", C.c_double)]
+                ("elem_slot", C.c_void_p), ("fe_work", C.c_void_p), ("k_fe", C.c_double),
+                ("adh_nr", C.c_int64), ("rec_tri", C.c_void_p), ("rec_bary", C.c_void_p), ("rec_ptr", C.c_void_p),
+                ("rec_inc", C.c_void_p), ("adh_nl", C.c_int64), ("lig_xz", C.c_void_p), ("bond", C.c_void_p),
+                ("lig_count", C.c_void_p), ("adh_work", C.c_void_p), ("adh_wall_y", C.c_double),
+                ("adh_nx", C.c_double), ("adh_nz", C.c_double), ("adh_capture", C.c_double),
+                ("adh_sigma", C.c_double), ("adh_lb", C.c_double), ("adh_gamma", C.c_double), ("adh_kT", C.c_double),
+                ("adh_kon0", C.c_double), ("adh_koff0", C.c_double), ("adh_seed", C.c_uint64)]
+
+
+ADH_MAX_BIDS = 32
 
 
 _lib = None
@@ -97,6 +108,9 @@ def lib():
         M = C.POINTER(IbMembrane)
         L.ib_membrane_rest.argtypes = [M, vp, vp]
         L.ib_membrane_forces.argtypes = [M, vp, vp, vp]
+        L.ib_adhesion_step.argtypes = [M, vp, vp]
+        L.ib_adhesion_work_ints.argtypes = [i64, C.c_double, C.c_double, C.c_double]
+        L.ib_adhesion_work_ints.restype = C.c_int64
         L.lbm_coupled_steps.argtypes = [vp, M, i32, vp, vp, vp]
         L.lbm_graph_capture.argtypes = [vp, M, i32, vp, vp, vp]
         L.lbm_graph_launch.argtypes = [vp, i32]
@@ -478,9 +492,12 @@ def closure_targets(coarse, g0, F, g1, out=None):
 
 class Membrane:
     """Device copy of a spring / hinge / tether network (inputs.Bodies) for
-    ib_membrane_rest / ib_membrane_forces (run on torch's current stream)."""
+    ib_membrane_rest / ib_membrane_forces (run on torch's current stream).  `adhesion`: a dict
+    with rec_tri [nr, 3], rec_bary [nr, 3], ligands [nl, 2] and the scalars wall_y, nx, nz,
+    capture, sigma, l_b, gamma, kT, k_on0, k_off0, seed (and optionally bond [nr], lig_count [nl]
+    as the initial state) turns on the adhesion of section 3.2."""
 
-    def __init__(self, bodies, device="cuda:0", stream=None):
+    def __init__(self, bodies, device="cuda:0", stream=None, adhesion=None):
         import torch
 
         from . import inputs
@@ -548,6 +565,36 @@ class Membrane:
             s.elem6, s.ne, s.elem_ptr, s.elem_inc = e_d.data_ptr(), len(e6), ep_d.data_ptr(), ei_d.data_ptr()
             s.elem_slot, s.fe_work, s.k_fe = es.data_ptr(), fw.data_ptr(), float(bodies.k_fe)
             self.fe_work = fw
+        if adhesion is not None:
+            a = adhesion
+            rt = np.ascontiguousarray(a["rec_tri"], dtype=np.int32).reshape(-1, 3)
+            nr = len(rt)
+            rp, rinc = inputs.csr_receptors(n, rt)
+            lig = np.ascontiguousarray(a["ligands"], dtype=np.float64).reshape(-1, 2)
+            nl = len(lig)
+            rt_d, rp_d, ri_d = dev_i32(rt.reshape(-1)), dev_i32(rp), dev_i32(rinc)
+            rb_d = torch.from_numpy(np.ascontiguousarray(a["rec_bary"], dtype=np.float64).reshape(-1)).to(dev)
+            lg_d = torch.from_numpy(lig.reshape(-1)).to(dev)
+            bond0 = a.get("bond")
+            self.bond = (torch.full((nr,), -1, dtype=torch.int32, device=dev) if bond0 is None
+                         else torch.from_numpy(np.ascontiguousarray(bond0, dtype=np.int32)).to(dev))
+            cnt0 = a.get("lig_count")
+            self.lig_count = (torch.zeros(nl, dtype=torch.int32, device=dev) if cnt0 is None
+                              else torch.from_numpy(np.ascontiguousarray(cnt0, dtype=np.int32)).to(dev))
+            words = lib().ib_adhesion_work_ints(nl, float(a["nx"]), float(a["nz"]), float(a["capture"]))
+            if words <= 0:
+                raise LbmError("ib_adhesion_work_ints: invalid adhesion geometry")
+            self.adh_work = torch.zeros(words, dtype=torch.int32, device=dev)
+            self._keep += [rb_d, lg_d, self.bond, self.lig_count, self.adh_work]
+            s.adh_nr, s.rec_tri, s.rec_bary, s.rec_ptr, s.rec_inc = nr, rt_d.data_ptr(), rb_d.data_ptr(), \
+                rp_d.data_ptr(), ri_d.data_ptr()
+            s.adh_nl, s.lig_xz, s.bond, s.lig_count = nl, lg_d.data_ptr(), self.bond.data_ptr(), \
+                self.lig_count.data_ptr()
+            s.adh_work = self.adh_work.data_ptr()
+            for k in ("wall_y", "nx", "nz", "capture", "sigma", "gamma", "kT", "kon0", "koff0"):
+                setattr(s, "adh_" + k, float(a[{"kon0": "k_on0", "koff0": "k_off0"}.get(k, k)]))
+            s.adh_lb = float(a["l_b"])
+            s.adh_seed = int(a["seed"])
         self.struct = s
         self.n = n
         st = stream if stream is not None else _stream_ptr(torch, dev)
@@ -563,3 +610,7 @@ class Membrane:
             F = torch.empty((3, self.n), dtype=torch.float32, device=X.device)
         _check(lib().ib_membrane_forces(C.byref(self.struct), _ptr(X), _ptr(F), self.stream), "ib_membrane_forces")
         return F
+
+    def adhesion_step(self, X):
+        """One Monte-Carlo step of the adhesion at positions X (device [3, n] float64)."""
+        _check(lib().ib_adhesion_step(C.byref(self.struct), _ptr(X), self.stream), "ib_adhesion_step")

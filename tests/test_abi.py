@@ -150,6 +150,11 @@ def test_bench_workloads_build():
     b = chans[0].bodies
     assert b.elements6 is not None and b.elements6.shape == (16 * 1280, 6) and b.k_bend == 0.0
     assert abs(b.k_fe / 2.53e-4 - 1) < 1e-2 and "Eq. 6-10" in desc
+    chans, desc = bench.make_workload("shear_adhesion")
+    a = bench.adhesion_of("shear_adhesion", chans)
+    assert len(a["rec_tri"]) == 16 * 5344 and len(a["ligands"]) == 256 * 128 and abs(a["capture"] - 0.64) < 1e-12
+    assert chans[0].bodies.X[1].min() > -0.5 and chans[0].bodies.X[1].min() < -0.5 + a["capture"]
+    assert bench.adhesion_of("shear", chans) is None
     chans, desc = bench.make_workload("batched")
     assert len(chans) == 64
     chans, desc = bench.make_workload("coarse")
