@@ -271,21 +271,23 @@ def main():
     X.copy_(torch.from_numpy(b.X))
     F.zero_()
     U.zero_()
-    # the graph replays two steps from the buffer parities current at capture: an odd warm-up
-    # step runs eagerly before the capture, an odd timed step after the last replay
-    if args.warmup % 2:
-        lat.coupled_steps(mem, 1, X, F, U)
-    lat.graph_capture(mem, 2, X, F, U)
+    # the graph replays G steps (2, or 2 rebin when the nodes are binned every `rebin` steps)
+    # from the buffer parities and binning phase current at capture: the warm-up steps beyond a
+    # multiple of G run eagerly before the capture, the timed ones after the last replay
+    G = tune.graph_steps(lat.get_launch())
+    if args.warmup % G:
+        lat.coupled_steps(mem, args.warmup % G, X, F, U)
+    lat.graph_capture(mem, G, X, F, U)
     stream = lat.stream  # the library's stream: events are recorded on it
-    if args.warmup // 2:
-        lat.graph_launch(args.warmup // 2)
+    if args.warmup // G:
+        lat.graph_launch(args.warmup // G)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    if args.steps // 2:
-        lat.graph_launch(args.steps // 2)
-    if args.steps % 2:
-        lat.coupled_steps(mem, 1, X, F, U)
+    if args.steps // G:
+        lat.graph_launch(args.steps // G)
+    if args.steps % G:
+        lat.coupled_steps(mem, args.steps % G, X, F, U)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
@@ -326,7 +328,7 @@ def main():
         "dtype": DTYPE[args.storage] + ("+bf16-mlp" if args.closure else ""),
         "data": "synthetic",
         "config": {"workload": desc, "cells": cells, "ib_nodes": nodes, "storage": args.storage,
-                   "delta_kernel": args.kernel, "launch": lat.get_launch(), "graph": "2-step HIP graph replay",
+                   "delta_kernel": args.kernel, "launch": lat.get_launch(), "graph": "%d-step HIP graph replay" % G,
                    "closure": "seeded 16-64-64-16 network (throughput run)" if args.closure else None},
         "ib_nodes_per_s": round(nodes / (ms * 1e-3), 1),
         "mlups_fine_equivalent": round(16 * cells / (ms * 1e-3) / 1e6, 2) if args.workload == "coarse" else None,

@@ -72,6 +72,8 @@ typedef enum { IB_PHI_COS4 = 0, IB_PHI_PESKIN4 = 1 } ib_kernel;
 #define LBM_FLAG_LIST_OVERFLOW 0x2u /* IB tile lists exceeded their capacity (contributions lost) */
 #define LBM_FLAG_FORCE_NONFINITE 0x4u /* a Lagrangian force was Inf/NaN (force field set to NaN) */
 #define LBM_FLAG_CLOSURE_FALLBACK 0x8u /* the learned closure fell back to plain BGK at some node */
+#define LBM_FLAG_REBIN_MARGIN 0x20u /* with lbm_launch.rebin > 1, a node left the margin it was
+                                        binned with before the next binning */
 #define LBM_FLAG_ADHESION_BIDS 0x10u /* a ligand received more adhesion bids in one step than its bid
                                         list holds (ADH_MAX_BIDS): some were dropped */
 
@@ -177,9 +179,9 @@ const char* lbm_status_string(lbm_status s);
  *   bending  stand-in for Eq. (6)-(10): E = k_bend sum_hinges (1 - cos(theta - theta0)),
  *            theta the signed dihedral angle of the two triangles of a hinge;
  *   tethers  U = k_tether/2 |X - A|^2.
- * Connectivity is CSR so that every node gathers its own force (no atomics): a first pass
- * evaluates every hinge once into hinge_force, a second gathers per node.  All arrays are
- * device memory; rest_len / rest_cs are filled by ib_membrane_rest(). */
+ * Connectivity is CSR so that every node gathers its own force (no atomics): a node evaluates
+ * each hinge it belongs to for its own vertex.  All arrays are device memory; rest_len /
+ * rest_cs are filled by ib_membrane_rest(). */
 typedef struct {
     int64_t n;                 /* nodes */
     const int32_t* nbr_ptr;    /* [n+1] CSR over spring neighbours (both directions) */
@@ -190,10 +192,6 @@ typedef struct {
     const int32_t* hinge_inc;  /* [nnz_h] (hinge id << 2) | role, role = slot 0..3 in the hinge */
     const int32_t* hinges;     /* [nh][4] (x0, x1, x2, x3): triangles (x0,x1,x2), (x3,x2,x1) */
     double* rest_cs;           /* [nh][2] cos and sin of the rest dihedral angle */
-    int32_t* hinge_slot;       /* [nh][4] scratch: position of (hinge, role) in hinge_inc (set by
-                                  ib_membrane_rest) */
-    float* hinge_force;        /* [nh*4][3] scratch: bending force of each incidence, CSR order
-                                  (FP64 arithmetic, stored as FP32; the node sum is FP64) */
     int64_t nh;
     double k_bend;
     const double* anchors;     /* [3][n] tether anchors, or NULL */
@@ -276,8 +274,8 @@ typedef struct {
 int64_t ib_adhesion_work_ints(int64_t nl, double nx, double nz, double capture);
 
 /* Measure rest lengths, rest dihedral angles and (with triangles) the rest areas and volumes
- * on X_rest ([3][n] float64); build hinge_slot (and elem_slot).  Requires every hinge vertex's
- * incidences in hinge_ptr / hinge_inc (every element node's in elem_ptr / elem_inc). */
+ * on X_rest ([3][n] float64); build elem_slot, and the ligand table of the adhesion.  Requires
+ * every element node's incidences in elem_ptr / elem_inc. */
 lbm_status ib_membrane_rest(const ib_membrane* m /*host*/, const double* X_rest, void* stream);
 /* F = -grad(E)(X), float64 arithmetic, float32 output [3][n]. */
 lbm_status ib_membrane_forces(const ib_membrane* m /*host*/, const double* X, float* F, void* stream);
@@ -293,14 +291,16 @@ lbm_status ib_adhesion_step(const ib_membrane* m /*host*/, const double* X, void
 lbm_status lbm_coupled_steps(lbm_ctx* ctx, const ib_membrane* m /*host*/, int32_t nsteps, double* X,
                              float* F, float* U);
 
-/* Capture `nsteps` coupled steps (even, >= 2) into a HIP graph held by the context, then
+/* Capture `nsteps` coupled steps (even, >= 2, a multiple of 2 lbm_launch.rebin) into a HIP
+ * graph held by the context, then
  * replay it `repeats` times per lbm_graph_launch.  The captured pointers must stay valid.
  * The context's stream must not be the legacy default (NULL) stream: LBM_ERR_UNSUPPORTED.
  * The graph reads and writes the population buffer and IB tile set that were current at
  * capture; a replay leaves them current again.  lbm_graph_launch returns LBM_ERR_STATE
  * (and launches nothing) when other calls since the capture left a different buffer or
- * tile set current: an odd number of eager coupled steps, a lone lbm_step or ib_spread.
- * Even numbers of eager steps between replays are fine. */
+ * tile set current, or a different point in the binning cycle: an odd number of eager coupled
+ * steps (with rebin > 1: a number that is not a multiple of 2 rebin), a lone lbm_step or
+ * ib_spread, a change of the launch configuration. */
 lbm_status lbm_graph_capture(lbm_ctx* ctx, const ib_membrane* m /*host*/, int32_t nsteps, double* X,
                              float* F, float* U);
 lbm_status lbm_graph_launch(lbm_ctx* ctx, int32_t repeats);
@@ -419,6 +419,16 @@ typedef struct {
                             same results.  It pays when the flagged tiles are a few percent of the
                             lattice (one channel with 16 platelets: 2.7%, 195 -> 190 us per step)
                             and loses when they are many (the 64-channel batch: 10%). */
+    int32_t rebin;       /* coupled steps with a membrane: the nodes are binned into the IB tile
+                            lists every `rebin` steps (1..64; 1 = every step, the default).  With
+                            rebin > 1 a node is listed in every tile its stencil can reach while it
+                            stays within half a lattice spacing of where it was binned; the steps
+                            in between recompute only the nodes' stencil weights (in the force
+                            kernel) and reuse the lists.  The spread sums exact integers over
+                            the tiles' cells, so the results are bitwise those of rebin = 1; a node
+                            that moves further sets LBM_FLAG_REBIN_MARGIN (its contributions to
+                            unlisted tiles are lost).  A captured graph must then hold a multiple
+                            of 2 rebin steps. */
 } lbm_launch;
 
 lbm_status lbm_set_launch(lbm_ctx* ctx, const lbm_launch* cfg /*host*/);

@@ -236,18 +236,22 @@ def _patch_mean(w, patches=(16, 32)):
 
 
 def _graph_rate(lat, mem, X, F, U, steps=200, warmup=10):
-    """Coupled steps per second of the 2-step HIP graph replay (the benchmark's schedule)."""
+    """Coupled steps per second of the HIP graph replay (the benchmark's schedule)."""
     import torch
 
-    lat.graph_capture(mem, 2, X, F, U)
-    lat.graph_launch(warmup // 2)
+    from . import tune
+
+    G = tune.graph_steps(lat.get_launch())
+    lat.graph_capture(mem, G, X, F, U)
+    lat.graph_launch(max(1, warmup // G))
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(1, steps // G)
     ev0.record(lat.stream)
-    lat.graph_launch(steps // 2)
+    lat.graph_launch(reps)
     ev1.record(lat.stream)
     torch.cuda.synchronize()
-    return (steps // 2) * 2 / (ev0.elapsed_time(ev1) * 1e-3)
+    return reps * G / (ev0.elapsed_time(ev1) * 1e-3)
 
 
 def _interp_log(xs, ys, y):

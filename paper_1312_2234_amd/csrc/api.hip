@@ -83,8 +83,9 @@ Layout layout_of(const lbm_params* p, int32_t nch, lbm_storage st, int64_t max_n
         L.rec = take(sizeof(float) * 20 * max_nodes);
         L.rank = take(sizeof(int32_t) * 27 * max_nodes);
         L.blkbase = take(sizeof(int32_t) * HS * ((max_nodes + 255) / 256));
-        L.blkmax = take(sizeof(uint32_t) * ((8 * max_nodes + 255) / 256));  // bin blocks or force workgroups
-        L.nbase = take(sizeof(int4) * max_nodes);
+        // one entry per bin block (256 nodes) or per force workgroup (FS_THREADS / NODE_LANES = 32 nodes)
+        L.blkmax = take(sizeof(uint32_t) * ((NODE_LANES * max_nodes + 255) / 256 + 1));
+        L.nbase = take(2 * sizeof(int4) * max_nodes);
         for (int k = 0; k < 2; ++k) {
             L.sets[k][0] = take(sizeof(int32_t) * sz.tiles);           // cnt
             L.sets[k][1] = take(sizeof(int32_t) * sz.tiles);           // tile_slot
@@ -156,7 +157,7 @@ IbArgs ib_args(lbm_ctx* c, int set) {
     a.nch = c->nch;
     a.rank = c->d_rank;
     a.blkbase = c->d_blkbase;
-    a.nbase = c->d_nbase;
+    a.nbin = c->d_nbin;
     a.part = c->d_part;
     a.part_cap = c->part_cap;
     a.item_slot = c->d_item_slot;
@@ -256,7 +257,7 @@ lbm_status lbm_create(const lbm_params* ch, int32_t nch, lbm_storage storage, ib
         c->d_list = (int32_t*)(c->ws + L.list);
         c->d_rank = (int32_t*)(c->ws + L.rank);
         c->d_blkbase = (int32_t*)(c->ws + L.blkbase);
-        c->d_nbase = (int4*)(c->ws + L.nbase);
+        c->d_nbin = (int4*)(c->ws + L.nbase);
         c->d_force = (float*)(c->ws + L.force);
         c->d_vel = (float*)(c->ws + L.vel);
         c->d_part = (unsigned long long*)(c->ws + L.part);
@@ -356,6 +357,7 @@ lbm_status lbm_destroy(lbm_ctx* c) {
 
 lbm_status lbm_init(lbm_ctx* c, const float* rho, const float* u) {
     if (!c) return LBM_ERR_ARG;
+    c->bin_age = 0;  // a restart usually puts the nodes back too: bin at the next coupled step
     LatArgs a = lat_args(c);
     a.dst = c->pop[c->cur];
     a.in_rho = rho;
@@ -461,6 +463,7 @@ lbm_status ib_set_nodes(lbm_ctx* c, int64_t n, const int64_t* node_offsets) {
     if (st != LBM_OK) return st;
     c->n_nodes = n;
     c->nodes_set = true;
+    c->bin_age = 0;
     return LBM_OK;
 }
 
@@ -470,6 +473,7 @@ lbm_status ib_spread(lbm_ctx* c, int64_t n, const double* X, const float* F) {
     if (st != LBM_OK) return st;
     if (n > 0 && (!X || !F)) return LBM_ERR_ARG;
     c->ibset ^= 1;
+    c->bin_age = 0;  // the coupled steps' lists are replaced
     IbArgs a = ib_args(c, c->ibset);
     a.X = X;
     a.F = F;
@@ -519,7 +523,7 @@ lbm_status ib_membrane_rest(const ib_membrane* m, const double* X_rest, void* st
     if (!constraints_ok(m)) return LBM_ERR_ARG;
     if (m->nbr_ptr && (!m->nbr_idx || !m->rest_len)) return LBM_ERR_ARG;
     if (m->nh > 0 && (!m->hinges || !m->rest_cs)) return LBM_ERR_ARG;
-    if (m->hinge_ptr && m->nh > 0 && (!m->hinge_inc || !m->hinge_slot)) return LBM_ERR_ARG;
+    if (m->hinge_ptr && m->nh > 0 && !m->hinge_inc) return LBM_ERR_ARG;
     return hip_ok(launch_membrane_rest(m, X_rest, (hipStream_t)stream));
 }
 
@@ -527,9 +531,7 @@ lbm_status ib_membrane_forces(const ib_membrane* m, const double* X, float* F, v
     if (!m || m->n < 0 || (m->n > 0 && (!X || !F))) return LBM_ERR_ARG;
     if (!constraints_ok(m)) return LBM_ERR_ARG;
     if (m->nbr_ptr && (!m->nbr_idx || !m->rest_len)) return LBM_ERR_ARG;
-    if (m->hinge_ptr && (!m->hinge_inc || !m->hinges || !m->rest_cs ||
-                         (m->nh > 0 && (!m->hinge_force || !m->hinge_slot))))
-        return LBM_ERR_ARG;
+    if (m->hinge_ptr && (!m->hinge_inc || !m->hinges || !m->rest_cs)) return LBM_ERR_ARG;
     return hip_ok(launch_membrane_forces(m, X, F, (hipStream_t)stream));
 }
 
@@ -569,11 +571,18 @@ static hipError_t far_update(lbm_ctx* c) {
 static lbm_status coupled(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, double* X, float* F, float* U) {
     const bool ov = c->launch.overlap && c->side && !c->closure && nsteps > 0;
     if (ov && far_update(c) != hipSuccess) return LBM_ERR_HIP;
+    // with a membrane and rebin > 1 the nodes are binned (with a margin) every `rebin` steps
+    const int rebin = m ? c->launch.rebin : 1;
     for (int s = 0; s < nsteps; ++s) {
-        c->ibset ^= 1;
+        const bool bin = rebin <= 1 || c->bin_age == 0;
+        if (bin) c->ibset ^= 1;
         IbArgs a = ib_args(c, c->ibset);
         a.X = X;
         a.F = F;
+        if (rebin > 1) {
+            a.margin = REBIN_MARGIN;
+            a.scale_local = 1;
+        }
         // Without the closure or the second stream, the lattice update away from the IB tiles
         // (body force only) runs in the spread's launch, and the flagged tiles' cells are then
         // updated with their force (merging split tiles' partial sums on the way): bitwise the
@@ -585,7 +594,7 @@ static lbm_status coupled(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, doub
         if (m) {
             // the binning and the scan need only X: they run beside the hinge and node forces,
             // and the force kernel fills in what the spread needs of F
-            if (launch_forces_scatter(c, m, X, F, a) != hipSuccess) return LBM_ERR_HIP;
+            if (launch_forces_scatter(c, m, X, F, a, bin) != hipSuccess) return LBM_ERR_HIP;
             if (!split_update && launch_ib_spread_items(c, a) != hipSuccess) return LBM_ERR_HIP;
         } else if (launch_ib_spread(c, a) != hipSuccess) {
             return LBM_ERR_HIP;
@@ -621,6 +630,7 @@ static lbm_status coupled(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, doub
         if (launch_ib_interp(c, b) != hipSuccess) return LBM_ERR_HIP;
         // the adhesion's Monte-Carlo step at the moved positions (the last box of Fig. 1)
         if (m && launch_adhesion_step(m, X, (uint32_t*)c->d_flags, c->stream) != hipSuccess) return LBM_ERR_HIP;
+        c->bin_age = rebin > 1 ? (c->bin_age + 1) % rebin : 0;
     }
     return LBM_OK;
 }
@@ -636,13 +646,15 @@ lbm_status lbm_coupled_steps(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, d
 
 lbm_status lbm_graph_capture(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, double* X, float* F, float* U) {
     if (!c || nsteps < 2 || (nsteps & 1)) return LBM_ERR_ARG;
+    // a replay must end at the binning phase and tile set it started from
+    if (m && c->launch.rebin > 1 && nsteps % (2 * c->launch.rebin)) return LBM_ERR_ARG;
     lbm_status st = check_ib(c, c->n_nodes);
     if (st != LBM_OK) return st;
     if (c->n_nodes > 0 && (!X || !F || !U)) return LBM_ERR_ARG;
     if (m && (m->n != c->n_nodes || !constraints_ok(m))) return LBM_ERR_ARG;
     if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
     if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
-    const int cur0 = c->cur, set0 = c->ibset;
+    const int cur0 = c->cur, set0 = c->ibset, age0 = c->bin_age;
     if (c->stream == nullptr) return LBM_ERR_UNSUPPORTED;  // the legacy default stream cannot be captured
     if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LBM_ERR_HIP;
     c->capturing = true;
@@ -654,6 +666,7 @@ lbm_status lbm_graph_capture(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, d
     // parities are back where they started when a replay ends
     c->cur = cur0;
     c->ibset = set0;
+    c->bin_age = age0;
     if (st != LBM_OK || e != hipSuccess) {
         if (g) hipGraphDestroy(g);
         return st != LBM_OK ? st : LBM_ERR_HIP;
@@ -666,6 +679,7 @@ lbm_status lbm_graph_capture(lbm_ctx* c, const ib_membrane* m, int32_t nsteps, d
     c->graph = g;
     c->graph_cur = cur0;
     c->graph_set = set0;
+    c->graph_age = age0;
     return LBM_OK;
 }
 
@@ -675,7 +689,7 @@ lbm_status lbm_graph_launch(lbm_ctx* c, int32_t repeats) {
     // the graph's kernels read and write the buffers and tile sets of the parities it was
     // captured at: an odd number of eager steps (or a lone lbm_step / ib_spread) since then
     // would make it replay from stale state
-    if (c->cur != c->graph_cur || c->ibset != c->graph_set) return LBM_ERR_STATE;
+    if (c->cur != c->graph_cur || c->ibset != c->graph_set || c->bin_age != c->graph_age) return LBM_ERR_STATE;
     for (int r = 0; r < repeats; ++r)
         if (hipGraphLaunch(c->gexec, c->stream) != hipSuccess) return LBM_ERR_HIP;
     return LBM_OK;
@@ -687,9 +701,11 @@ lbm_status lbm_set_launch(lbm_ctx* c, const lbm_launch* cfg) {
     if (b != 64 && b != 128 && b != 256 && b != 512 && b != 1024) return LBM_ERR_ARG;
     if (cfg->persistent < 0 || (cfg->xcd_remap != 0 && cfg->xcd_remap != 1) ||
         (cfg->nontemporal != 0 && cfg->nontemporal != 1) || cfg->vec < 0 || cfg->vec > 4 || cfg->vec == 3 ||
-        (cfg->overlap != 0 && cfg->overlap != 1) || cfg->split < -1 || cfg->split > 1)
+        (cfg->overlap != 0 && cfg->overlap != 1) || cfg->split < -1 || cfg->split > 1 || cfg->rebin < 1 ||
+        cfg->rebin > 64)
         return LBM_ERR_ARG;
     c->launch = *cfg;
+    c->bin_age = 0;  // bin at the next coupled step
     return LBM_OK;
 }
 

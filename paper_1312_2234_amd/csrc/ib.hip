@@ -137,6 +137,102 @@ __device__ __forceinline__ void for_tiles(const Chan& ch, int bx, int by, int bz
                 f(q++, ch.tile_off + tx[i] + (int64_t)ch.tnx * (ty[j] + (int64_t)ch.tny * tz[k]));
 }
 
+// Distinct tiles of `cnt` (4 or 5) consecutive cells from `start` along an axis of `dim` cells
+// (periodic, or cut at the walls when `bounded`): at most three.
+__device__ __forceinline__ int axis_tiles(int start, int cnt, int dim, bool bounded, int out[3]) {
+    int k = 0;
+    for (int a = 0; a < cnt; ++a) {
+        int c = start + a;
+        if (bounded) {
+            if (c < 0 || c >= dim) continue;
+        } else {
+            c = c >= dim ? c - dim : c;
+        }
+        const int t = c >> 3;
+        bool seen = false;
+        for (int j = 0; j < k; ++j) seen |= (out[j] == t);
+        if (!seen && k < 3) out[k++] = t;
+    }
+    return k;
+}
+
+// Tiles reachable by a node binned with a margin: the stencils of every base from lo to hi
+// (per axis, unwrapped), i.e. the cells lo - 1 .. hi + 2.  Same order as for_tiles.
+template <class F>
+__device__ __forceinline__ void for_tiles_margin(const Chan& ch, const int4 lo, const int4 hi, F f) {
+    int tx[3], ty[3], tz[3];
+    const int nxt = axis_tiles(wrapi((int64_t)lo.x - 1, ch.nx), hi.x - lo.x + 4, ch.nx, false, tx);
+    const int nyt = ch.walls ? axis_tiles(lo.y - 1, hi.y - lo.y + 4, ch.ny, true, ty)
+                             : axis_tiles(wrapi((int64_t)lo.y - 1, ch.ny), hi.y - lo.y + 4, ch.ny, false, ty);
+    const int nzt = axis_tiles(wrapi((int64_t)lo.z - 1, ch.nz), hi.z - lo.z + 4, ch.nz, false, tz);
+    int q = 0;
+    for (int k = 0; k < nzt; ++k)
+        for (int j = 0; j < nyt; ++j)
+            for (int i = 0; i < nxt; ++i)
+                f(q++, ch.tile_off + tx[i] + (int64_t)ch.tnx * (ty[j] + (int64_t)ch.tny * tz[k]));
+}
+
+// floor(X - margin) and floor(X + margin) per axis, the y range clamped like the stencil base
+// of a node outside the channel.
+__device__ __forceinline__ void margin_range(const Chan& ch, const double* X, int64_t n, int64_t m, double margin,
+                                             int4& lo, int4& hi) {
+    int l[3], h[3];
+    for (int d = 0; d < 3; ++d) {
+        const double x = X[d * n + m];
+        const bool finite = isfinite(x) && fabs(x) < 1e9;
+        int64_t a = finite ? (int64_t)floor(x - margin) : 0, b = finite ? (int64_t)floor(x + margin) : 0;
+        if (d == 1 && ch.walls) {
+            a = a < -3 ? -3 : (a > ch.ny + 1 ? ch.ny + 1 : a);
+            b = b < -3 ? -3 : (b > ch.ny + 1 ? ch.ny + 1 : b);
+        }
+        if (b - a > 1) b = a + 1;  // margin < 1/2 keeps b - a <= 1
+        l[d] = (int)a;
+        h[d] = (int)b;
+    }
+    lo = make_int4(l[0], l[1], l[2], 0);
+    hi = make_int4(h[0], h[1], h[2], 0);
+}
+
+// Axis d of node m's record: the stencil base floor(X) - 1 (x, z wrapped; y clamped for a node
+// outside the channel) and the four kernel weights; returns the base and whether the node lies
+// outside the channel (or is not finite) along this axis.
+__device__ __forceinline__ int record_axis(const IbArgs& a, int64_t m, const Chan& ch, int d, bool& bad) {
+    float* r = a.rec + m * REC;
+    float w[4];
+    const double X = a.X[d * a.n + m];
+    const int dim = d == 0 ? ch.nx : (d == 1 ? ch.ny : ch.nz);
+    const bool finite = isfinite(X) && fabs(X) < 1e9;
+    int64_t base = finite ? ib_weights(a.kernel, X, w) : 0;
+    bad = !finite;
+    if (!finite) w[0] = w[1] = w[2] = w[3] = 0.0f;
+    int b;
+    if (d == 1 && ch.walls) {
+        // node outside the channel: y outside [-1, ny), or [0, ny-1] with on-site walls
+        if (ch.walls == 2 ? (X < 0.0 || X > ch.ny - 1.0) : (base < -2 || base > ch.ny - 2)) bad = true;
+        if (base < -4) base = -4;
+        if (base > ch.ny) base = ch.ny;
+        b = (int)base;
+    } else {
+        b = wrapi(base, dim);
+    }
+    r[d] = __int_as_float(b);
+    for (int k = 0; k < 4; ++k) r[4 + 4 * d + k] = w[k];
+    return b;
+}
+
+// The whole record of node m (channel c): the three axes and the channel; sets
+// LBM_FLAG_NODE_OUTSIDE for a node outside the channel or not finite.
+__device__ __forceinline__ void node_record(const IbArgs& a, int64_t m, int c, const Chan& ch, int b[3]) {
+    bool bad = false;
+    for (int d = 0; d < 3; ++d) {
+        bool bd;
+        b[d] = record_axis(a, m, ch, d, bd);
+        bad |= bd;
+    }
+    if (bad) atomicOr(a.flags, LBM_FLAG_NODE_OUTSIDE);
+    a.rec[m * REC + 3] = __int_as_float(c);
+}
+
 // One block of the binning (256 nodes; `blk` is its index among the bin blocks).  With
 // `with_f` it also copies F into the node records and reduces max |F| for the scan; without,
 // the membrane-force kernel that runs after it does both (the coupled step).
@@ -155,39 +251,8 @@ __device__ __forceinline__ void bin_block(const IbArgs& a, int64_t blk, bool wit
         const int c = a.node_ch[m];
         const Chan& ch = a.chan[c];
         float* r = a.rec + m * REC;
-        float w[3][4];
         int b[3];
-        bool bad = false;
-        for (int d = 0; d < 3; ++d) {
-            const double X = a.X[d * a.n + m];
-            const int dim = d == 0 ? ch.nx : (d == 1 ? ch.ny : ch.nz);
-            const bool finite = isfinite(X) && fabs(X) < 1e9;
-            int64_t base = finite ? ib_weights(a.kernel, X, w[d]) : 0;
-            if (!finite) {
-                bad = true;
-                w[d][0] = w[d][1] = w[d][2] = w[d][3] = 0.0f;
-            }
-            if (d == 1 && ch.walls) {
-                // node outside the channel: y outside [-1, ny), or [0, ny-1] with on-site walls
-                if (ch.walls == 2 ? (X < 0.0 || X > ch.ny - 1.0) : (base < -2 || base > ch.ny - 2)) bad = true;
-                if (base < -4) base = -4;
-                if (base > ch.ny) base = ch.ny;
-                b[d] = (int)base;
-            } else {
-                b[d] = wrapi(base, dim);
-            }
-        }
-        if (bad) atomicOr(a.flags, LBM_FLAG_NODE_OUTSIDE);
-        a.nbase[m] = make_int4(b[0], b[1], b[2], c);
-        r[0] = __int_as_float(b[0]);
-        r[1] = __int_as_float(b[1]);
-        r[2] = __int_as_float(b[2]);
-        r[3] = __int_as_float(c);
-        for (int k = 0; k < 4; ++k) {
-            r[4 + k] = w[0][k];
-            r[8 + k] = w[1][k];
-            r[12 + k] = w[2][k];
-        }
+        node_record(a, m, c, ch, b);
         if (with_f)
             for (int d = 0; d < 3; ++d) {
                 const float F = a.F[d * a.n + m];
@@ -196,7 +261,7 @@ __device__ __forceinline__ void bin_block(const IbArgs& a, int64_t blk, bool wit
                 if (!isfinite(F)) fm = __uint_as_float(0x7f800000u);
             }
         int32_t* rk = a.rank + m * MAXT;
-        for_tiles(ch, b[0], b[1], b[2], [&](int q, int64_t T) {
+        auto hash_tile = [&](int q, int64_t T) {
             int h = (int)(((uint32_t)T * 2654435761u) >> (32 - HS_BITS)) & (HS - 1);
             int packed = INT32_MIN;
             for (int probe = 0; probe < 64; ++probe) {
@@ -213,7 +278,16 @@ __device__ __forceinline__ void bin_block(const IbArgs& a, int64_t blk, bool wit
                 packed = -(rr + 1);
             }
             rk[q] = packed;
-        });
+        };
+        if (a.margin > 0.0) {
+            int4 lo, hi;
+            margin_range(ch, a.X, a.n, m, a.margin, lo, hi);
+            a.nbin[2 * m] = lo;
+            a.nbin[2 * m + 1] = hi;
+            for_tiles_margin(ch, lo, hi, hash_tile);
+        } else {
+            for_tiles(ch, b[0], b[1], b[2], hash_tile);
+        }
     }
     // block maximum of |F| (NaN/Inf bits compare above all finite values)
     uint32_t ub = __float_as_uint(fm);
@@ -258,51 +332,68 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 
 // max |F| over the per-workgroup maxima in blkmax and the spread's fixed-point scale from it
 // (set.hdr: fmax_bits, nonfinite, scale_exp).  Every thread of one workgroup calls it.
-__device__ __forceinline__ void spread_scale(const IbArgs& a) {
-    __shared__ uint32_t fmx[16];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    {
-        const int nbk = (int)a.blkmax_n;
-        uint32_t mx = 0;
-        for (int k = tid; k < nbk; k += blockDim.x) {
-            const uint32_t v = a.blkmax[k];
-            mx = v > mx ? v : mx;
-        }
-        for (int d = 32; d >= 1; d >>= 1) {
-            const uint32_t o = __shfl_xor(mx, d, 64);
-            mx = o > mx ? o : mx;
-        }
-        if (lane == 0) fmx[wave] = mx;
-        __syncthreads();
+__device__ __forceinline__ int scale_exponent(float fm, int64_t n) {
+    // fixed-point scale: |contribution| <= max|F|/8 and at most n contributions per
+    // cell, so |sum| < n * 2^e / 8 with max|F| < 2^e; keep sums below 2^62.
+    int s = 0;
+    if (isfinite(fm) && fm > 0.0f) {
+        int e;
+        const float m = frexpf(fm, &e);  // fm = m 2^e, 1/2 <= m < 1
+        // a force within 2^-16 of the next power of two takes the next exponent: the margin
+        // absorbs the float rounding of the weights (each 1/2 at most, up to an ulp)
+        if (m > 1.0f - 0x1p-16f) ++e;
+        int L = 1;
+        while ((1ll << L) < n) ++L;
+        // one contribution |w_x w_y w_z F| <= (1 + 2^-20) max|F|/8 < (1 - 2^-17) 2^(e-3)
+        // stays below 2^23 - 64 at the spread's per-batch scale 2^(s-8), also once rounded
+        // to an integer, so a batch of <= 256 of them sums to less than 2^31 and converts
+        // exactly through int32; a sum of <= n of them stays below 2^62; the quantum of a
+        // contribution is 2^-26 max|F| or finer (2^-25 in the margin)
+        s = 34 - e;
+        if (s > 65 - e - L) s = 65 - e - L;
     }
+    return s;
+}
+
+// max |F| over the per-workgroup maxima in blkmax (float bits; NaN/Inf above every finite
+// value), reduced by the calling workgroup; every thread gets it.
+__device__ __forceinline__ uint32_t force_max_bits(const IbArgs& a) {
+    __shared__ uint32_t fmx[16];
+    __shared__ uint32_t all;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nbk = (int)a.blkmax_n;
+    uint32_t mx = 0;
+    for (int k = tid; k < nbk; k += blockDim.x) {
+        const uint32_t v = a.blkmax[k];
+        mx = v > mx ? v : mx;
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = __shfl_xor(mx, d, 64);
+        mx = o > mx ? o : mx;
+    }
+    if (lane == 0) fmx[wave] = mx;
+    __syncthreads();
     if (tid == 0) {
         uint32_t mxall = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mxall = fmx[w] > mxall ? fmx[w] : mxall;
-        a.set.hdr->fmax_bits = mxall;
-        // fixed-point scale: |contribution| <= max|F|/8 and at most n contributions per
-        // cell, so |sum| < n * 2^e / 8 with max|F| < 2^e; keep sums below 2^62.
+        all = mxall;
+    }
+    __syncthreads();
+    return all;
+}
+
+// max |F| and the spread's fixed-point scale from it into set.hdr (fmax_bits, nonfinite,
+// scale_exp).  Every thread of one workgroup calls it.
+__device__ __forceinline__ void spread_scale(const IbArgs& a) {
+    const uint32_t mxall = force_max_bits(a);
+    if (threadIdx.x == 0) {
         const float fm = __uint_as_float(mxall);
-        int s = 0;
+        a.set.hdr->fmax_bits = mxall;
         if (!isfinite(fm)) {
             a.set.hdr->nonfinite = 1;
             atomicOr(a.flags, LBM_FLAG_FORCE_NONFINITE);
-        } else if (fm > 0.0f) {
-            int e;
-            const float m = frexpf(fm, &e);  // fm = m 2^e, 1/2 <= m < 1
-            // a force within 2^-16 of the next power of two takes the next exponent: the margin
-            // absorbs the float rounding of the weights (each 1/2 at most, up to an ulp)
-            if (m > 1.0f - 0x1p-16f) ++e;
-            int L = 1;
-            while ((1ll << L) < a.n) ++L;
-            // one contribution |w_x w_y w_z F| <= (1 + 2^-20) max|F|/8 < (1 - 2^-17) 2^(e-3)
-            // stays below 2^23 - 64 at the spread's per-batch scale 2^(s-8), also once rounded
-            // to an integer, so a batch of <= 256 of them sums to less than 2^31 and converts
-            // exactly through int32; a sum of <= n of them stays below 2^62; the quantum of a
-            // contribution is 2^-26 max|F| or finer (2^-25 in the margin)
-            s = 34 - e;
-            if (s > 65 - e - L) s = 65 - e - L;
         }
-        a.set.hdr->scale_exp = s;
+        a.set.hdr->scale_exp = scale_exponent(fm, a.n);
     }
 }
 
@@ -389,13 +480,17 @@ __global__ void __launch_bounds__(256) k_ib_scatter(IbArgs a) {
     const Chan& ch = a.chan[__float_as_int(r[3])];
     const int32_t* rk = a.rank + m * MAXT;
     const int32_t* bb = a.blkbase + (m >> 8) * HS;
-    for_tiles(ch, __float_as_int(r[0]), __float_as_int(r[1]), __float_as_int(r[2]), [&](int q, int64_t T) {
+    auto place = [&](int q, int64_t T) {
         const int packed = rk[q];
         const int rr = packed >= 0 ? bb[packed >> 16] + (packed & 0xffff) : -packed - 1;
         const int slot = a.set.tile_slot[T];
         const int64_t pos = (int64_t)a.set.slot_off[slot] + rr;
         if (pos < a.list_cap) a.list[pos] = (int32_t)m;
-    });
+    };
+    if (a.margin > 0.0)
+        for_tiles_margin(ch, a.nbin[2 * m], a.nbin[2 * m + 1], place);
+    else
+        for_tiles(ch, __float_as_int(r[0]), __float_as_int(r[1]), __float_as_int(r[2]), place);
 }
 
 // ---------------------------------------------------------------- spread (LDS, fixed point)
@@ -430,8 +525,25 @@ __device__ __forceinline__ void spread_items(const IbArgs& a, int64_t first, int
     __shared__ int4 base[SP_BATCH];         // stencil base x, y, z of each staged node
     __shared__ float4 wrec[SP_BATCH][4];    // w_x[4], w_y[4], w_z[4], (F, pad)
     const int nwork = a.set.hdr->nchunk;
-    const int sexp = a.set.hdr->scale_exp;
-    const bool nonfinite = a.set.hdr->nonfinite != 0;
+    int sexp;
+    bool nonfinite;
+    if (a.scale_local) {
+        // between binnings no launch before the spread reduces the force maximum: every work
+        // item reduces it itself, and the first one records it for the later readers
+        const uint32_t mb = force_max_bits(a);
+        const float fm = __uint_as_float(mb);
+        nonfinite = !isfinite(fm);
+        sexp = scale_exponent(fm, a.n);
+        if (first == 0 && threadIdx.x == 0) {
+            a.set.hdr->fmax_bits = mb;
+            a.set.hdr->nonfinite = nonfinite ? 1 : 0;
+            a.set.hdr->scale_exp = sexp;
+            if (nonfinite) atomicOr(a.flags, LBM_FLAG_FORCE_NONFINITE);
+        }
+    } else {
+        sexp = a.set.hdr->scale_exp;
+        nonfinite = a.set.hdr->nonfinite != 0;
+    }
     const float scale = ldexpf(1.0f, sexp - SP_BATCH_SHIFT);
     const double inv = ldexp(1.0, -sexp);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -903,22 +1015,39 @@ __global__ void k_mem_rest(ib_membrane m, const double* X) {
     }
 }
 
-// Bending forces of hinge h on its four vertices: -k_b sin(theta - theta0) grad(theta).
-__device__ __forceinline__ void hinge_one(const ib_membrane& m, const double* X, int64_t h) {
-    double x[4][3], gr[4][3];
-    for (int k = 0; k < 4; ++k) ld3(X, m.n, m.hinges[4 * h + k], x[k]);
-    double c, sn;
-    hinge(x, gr, true, c, sn);
-    const double dE = m.k_bend * (sn * m.rest_cs[2 * h] - c * m.rest_cs[2 * h + 1]);
-    for (int k = 0; k < 4; ++k) {
-        float* out = m.hinge_force + 3 * (int64_t)m.hinge_slot[4 * h + k];
-        for (int d = 0; d < 3; ++d) out[d] = -dE * gr[k][d];
+// Bending force of a hinge on one of its vertices (role 0..3): -k_b sin(theta - theta0) times
+// that vertex's row of grad(theta) (the rows of `hinge`), computed for that row alone.
+__device__ __forceinline__ void hinge_role_force(const double x[4][3], int role, double c0, double s0, double kb,
+                                                 double out[3]) {
+    double a[3], b[3], nA[3], nB[3], e[3], cr[3];
+    sub(x[1], x[0], a); sub(x[2], x[0], b); crs(a, b, nA);
+    sub(x[2], x[3], a); sub(x[1], x[3], b); crs(a, b, nB);
+    sub(x[2], x[1], e);
+    const double AA = dt3(nA, nA), BB = dt3(nB, nB), L = sqrt(dt3(e, e));
+    const double iab = 1.0 / sqrt(AA * BB), iL = 1.0 / L;
+    crs(nA, nB, cr);
+    const double cth = dt3(nA, nB) * iab;
+    const double sth = dt3(cr, e) * iab * iL;
+    const double dE = kb * (sth * c0 - cth * s0);
+    double cA, cB;
+    if (role == 0) {
+        cA = -L;
+        cB = 0.0;
+    } else if (role == 3) {
+        cA = 0.0;
+        cB = -L;
+    } else {
+        // role 1: -((x0 - x2).e, (x3 - x2).e)/|e|; role 2: ((x0 - x1).e, (x3 - x1).e)/|e|
+        const int o = role == 1 ? 2 : 1;
+        const double sg = role == 1 ? -iL : iL;
+        double t0[3], t3[3];
+        sub(x[0], x[o], t0);
+        sub(x[3], x[o], t3);
+        cA = sg * dt3(t0, e);
+        cB = sg * dt3(t3, e);
     }
-}
-
-__global__ void __launch_bounds__(256) k_mem_hinges(ib_membrane m, const double* X) {
-    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (h < m.nh) hinge_one(m, X, h);
+    const double qa = cA / AA, qb = cB / BB;
+    for (int d = 0; d < 3; ++d) out[d] = -dE * (qa * nA[d] + qb * nB[d]);
 }
 
 // ---------------------------------------------------------------- area and volume (Eq. (4)-(5))
@@ -1233,14 +1362,9 @@ __global__ void k_fe_slots(ib_membrane m, int64_t nnz) {
     }
 }
 
-// Inverse of the node -> hinge incidence CSR: position of (hinge, role) in hinge_inc.
-__global__ void k_mem_hinge_slots(ib_membrane m, int64_t nnz) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < nnz) m.hinge_slot[m.hinge_inc[e]] = (int32_t)e;
-}
-
-// Per node (8 lanes each, partial sums combined by a fixed butterfly): springs (CSR), the
-// hinge forces of its incidences, the area and volume constraints of its triangles, tether.
+// Per node (NODE_LANES lanes each, partial sums combined by a fixed butterfly): springs (CSR), the
+// bending forces of the hinges it belongs to, the area and volume constraints of its
+// triangles, tether.
 // For the corner a of triangle (a, b, c) (any cyclic order), with n = (b - a) x (c - a):
 //   dS/da = n_hat x (c - b) / 2,  dV/da = (b x c) / 6,
 //   F_a -= [k_s (S^total - S_0^total)/S_0^total + k_t (S - S_0)/S_0] dS/da + k_v (V - V_0)/V_0 dV/da.  In the coupled step (rec != NULL) it also puts F
@@ -1250,14 +1374,14 @@ __global__ void k_mem_hinge_slots(ib_membrane m, int64_t nnz) {
 // plain membrane keeps the smaller register footprint.
 template <bool CONS>
 __device__ __forceinline__ void forces_block(const ib_membrane& m, const double* X, float* Fout, float* rec,
-                                             uint32_t* bmax, int64_t blk) {
-    const int64_t i = (blk * blockDim.x + threadIdx.x) >> 3;
-    const int sl = threadIdx.x & 7;
+                                             uint32_t* bmax, int64_t blk, const IbArgs* ia = nullptr) {
+    const int64_t i = (blk * blockDim.x + threadIdx.x) / NODE_LANES;
+    const int sl = threadIdx.x & (NODE_LANES - 1);
     const bool valid = i < m.n;
     double xi[3] = {0.0, 0.0, 0.0}, xj[3], r[3], F[3] = {0.0, 0.0, 0.0};
     if (valid) ld3(X, m.n, i, xi);
     if (valid && m.nbr_ptr) {
-        for (int e = m.nbr_ptr[i] + sl; e < m.nbr_ptr[i + 1]; e += 8) {
+        for (int e = m.nbr_ptr[i] + sl; e < m.nbr_ptr[i + 1]; e += NODE_LANES) {
             ld3(X, m.n, m.nbr_idx[e], xj);
             sub(xj, xi, r);
             const double len = sqrt(dt3(r, r));
@@ -1266,13 +1390,18 @@ __device__ __forceinline__ void forces_block(const ib_membrane& m, const double*
         }
     }
     if (valid && m.hinge_ptr && m.k_bend != 0.0) {
-        for (int e = m.hinge_ptr[i] + sl; e < m.hinge_ptr[i + 1]; e += 8) {
-            const float* hf = m.hinge_force + 3 * (int64_t)e;
-            F[0] += hf[0]; F[1] += hf[1]; F[2] += hf[2];
+        // the node evaluates each hinge it belongs to for its own role
+        for (int e = m.hinge_ptr[i] + sl; e < m.hinge_ptr[i + 1]; e += NODE_LANES) {
+            const int32_t code = m.hinge_inc[e];
+            const int64_t h = code >> 2;
+            double x[4][3], g[3];
+            for (int k = 0; k < 4; ++k) ld3(X, m.n, m.hinges[4 * h + k], x[k]);
+            hinge_role_force(x, code & 3, m.rest_cs[2 * h], m.rest_cs[2 * h + 1], m.k_bend, g);
+            F[0] += g[0]; F[1] += g[1]; F[2] += g[2];
         }
     }
     if (CONS && valid) {
-        for (int e = m.tri_ptr[i] + sl; e < m.tri_ptr[i + 1]; e += 8) {
+        for (int e = m.tri_ptr[i] + sl; e < m.tri_ptr[i + 1]; e += NODE_LANES) {
             const int32_t code = m.tri_inc[e];
             const int64_t t = code >> 2;
             const int k = code & 3;
@@ -1298,7 +1427,7 @@ __device__ __forceinline__ void forces_block(const ib_membrane& m, const double*
     // adhesion bonds (Eq. (14)): each bonded receptor of the node's incidences pulls with the
     // spring force times the node's barycentric weight
     if (m.adh_nr > 0 && valid) {
-        for (int e = m.rec_ptr[i] + sl; e < m.rec_ptr[i + 1]; e += 8) {
+        for (int e = m.rec_ptr[i] + sl; e < m.rec_ptr[i + 1]; e += NODE_LANES) {
             const int32_t code = m.rec_inc[e];
             const int64_t rr = code >> 2;
             const int32_t l = m.bond[rr];
@@ -1324,9 +1453,9 @@ __device__ __forceinline__ void forces_block(const ib_membrane& m, const double*
     double lap = 0.0;
     const bool fe = fe_on(m);
     if (fe && valid)
-        for (int e = m.elem_ptr[i] + sl; e < m.elem_ptr[i + 1]; e += 8) lap += fe_work(m).div[e];
+        for (int e = m.elem_ptr[i] + sl; e < m.elem_ptr[i + 1]; e += NODE_LANES) lap += fe_work(m).div[e];
 #pragma unroll
-    for (int d = 1; d < 8; d <<= 1) {
+    for (int d = 1; d < NODE_LANES; d <<= 1) {
         F[0] += __shfl_xor(F[0], d, 64);
         F[1] += __shfl_xor(F[1], d, 64);
         F[2] += __shfl_xor(F[2], d, 64);
@@ -1346,6 +1475,18 @@ __device__ __forceinline__ void forces_block(const ib_membrane& m, const double*
         for (int d = 0; d < 3; ++d) Fout[d * m.n + i] = Ff[d];
         if (rec)
             for (int d = 0; d < 3; ++d) rec[i * REC + 16 + d] = Ff[d];
+    }
+    if (ia && ia->rec_in_forces && valid && sl < 3) {
+        // a step between binnings: lane d writes axis d of the node's stencil base and weights
+        // at X, and checks that the stencil is still inside the tiles the node was listed in
+        const Chan& ch = ia->chan[ia->node_ch[i]];
+        bool bad;
+        record_axis(*ia, i, ch, sl, bad);
+        const int4 lo = ia->nbin[2 * i], hi = ia->nbin[2 * i + 1];
+        const int f = (int)floor(xi[sl]);
+        const int l = sl == 0 ? lo.x : (sl == 1 ? lo.y : lo.z), h = sl == 0 ? hi.x : (sl == 1 ? hi.y : hi.z);
+        if (bad) atomicOr(ia->flags, LBM_FLAG_NODE_OUTSIDE);
+        if (f < l || f > h) atomicOr(ia->flags, LBM_FLAG_REBIN_MARGIN);
     }
     if (bmax) {
         // workgroup max |F| as float bits (NaN/Inf above every finite value), as the binning does
@@ -1376,38 +1517,37 @@ __global__ void __launch_bounds__(256) k_mem_forces(ib_membrane m, const double*
     forces_block<CONS>(m, X, Fout, nullptr, nullptr, blockIdx.x);
 }
 
-// The coupled step's second launch: the scan of the tile lists (workgroup 0; it needs only
-// the binning) and the membrane forces (the rest, FS_THREADS / 8 nodes each), which also fill
-// in the records' F and max |F| per workgroup.
-// 512 threads: node-force workgroups of 64 nodes spread over more CUs (shear channel, 41 k
-// nodes: launch 8.4 -> 7.7 us against 1024 threads), while the scan workgroup still covers a
-// few hundred flagged tiles per pass (on the 3,600-tile batch 1024 is 0.4% faster per step)
+// The coupled step's second launch: the scan of the tile lists (workgroup 0, on binning steps;
+// it needs only the binning) and the membrane forces (the rest, FS_THREADS / NODE_LANES nodes each),
+// which also fill in the records' F and max |F| per workgroup, and between binnings the records'
+// stencil bases and weights.
+// 512 threads: node-force workgroups of 32 nodes spread over more CUs, while the scan
+// workgroup still covers a few hundred flagged tiles per pass (on the 3,600-tile batch 1024 is
+// 0.4% faster per step)
 constexpr int FS_THREADS = 512;
 template <bool CONS>
 __global__ void __launch_bounds__(FS_THREADS) k_forces_scan(ib_membrane m, const double* X, float* F, IbArgs a) {
-    if (blockIdx.x == 0)
-        scan_block(a, false);
-    else
-        forces_block<CONS>(m, X, F, a.rec, a.blkmax, (int64_t)blockIdx.x - 1);
+    if (blockIdx.x == 0) {
+        if (a.do_scan) scan_block(a, false);
+    } else {
+        forces_block<CONS>(m, X, F, a.rec, a.blkmax, (int64_t)blockIdx.x - 1, &a);
+    }
 }
 
 // The coupled step's first launch: the binning of the nodes by position (workgroups
 // [0, nbb), dispatched first: theirs is the longer dependent chain), the bodies' areas and
-// volumes for the constraints (the next nbd, one per body), the hinge forces (the next nbh)
-// and the first pass of the FE bending (the rest); the binning depends on none of them.
+// volumes for the constraints (the next nbd, one per body) and the first pass of the FE bending
+// (the rest); the binning depends on neither.
 template <bool CONS>
-__global__ void __launch_bounds__(256) k_hinges_bin(ib_membrane m, const double* X, IbArgs a, int64_t nbb,
-                                                    int64_t nbd, int64_t nbh) {
+__global__ void __launch_bounds__(256) k_bin_first(ib_membrane m, const double* X, IbArgs a, int64_t nbb,
+                                                   int64_t nbd) {
     const int64_t blk = blockIdx.x;
     if (blk < nbb) {
         bin_block(a, blk, false);
     } else if (CONS && blk < nbb + nbd) {
         body_block(m, X, m.body_now, blk - nbb, true);
-    } else if (blk < nbb + nbd + nbh) {
-        const int64_t h = (blk - nbb - nbd) * blockDim.x + threadIdx.x;
-        if (h < m.nh) hinge_one(m, X, h);
     } else {
-        fe_kappa_one(m, X, (blk - nbb - nbd - nbh) * blockDim.x + threadIdx.x);
+        fe_kappa_one(m, X, (blk - nbb - nbd) * blockDim.x + threadIdx.x);
     }
 }
 
@@ -1418,10 +1558,6 @@ hipError_t launch_membrane_rest(const ib_membrane* m, const double* X_rest, hipS
     if (m->tri && m->nt > 0 && m->nb > 0) {
         k_tri_rest<<<dim3((unsigned)((m->nt + 255) / 256)), dim3(256), 0, s>>>(*m, X_rest);
         k_mem_bodies<<<dim3((unsigned)m->nb), dim3(BODY_THREADS), 0, s>>>(*m, X_rest, m->rest_body, false);
-    }
-    if (m->hinge_ptr && m->nh > 0) {
-        const int64_t nnz = 4 * m->nh;
-        k_mem_hinge_slots<<<dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s>>>(*m, nnz);
     }
     if (fe_on(*m)) {
         const int64_t nnz = 6 * m->ne;
@@ -1441,13 +1577,11 @@ static void launch_fe_passes(const ib_membrane* m, const double* X, hipStream_t 
 
 hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* F, hipStream_t s) {
     if (m->n <= 0) return hipSuccess;
-    if (m->hinge_ptr && m->k_bend != 0.0 && m->nh > 0)
-        k_mem_hinges<<<dim3((unsigned)((m->nh + 255) / 256)), dim3(256), 0, s>>>(*m, X);
     if (fe_on(*m)) {
         k_fe_kappa<<<dim3((unsigned)((8 * m->ne + 255) / 256)), dim3(256), 0, s>>>(*m, X);
         launch_fe_passes(m, X, s);
     }
-    const dim3 gf((unsigned)((8 * m->n + 255) / 256)), bf(256);
+    const dim3 gf((unsigned)((NODE_LANES * m->n + 255) / 256)), bf(256);
     if (constraints_on(*m)) {
         k_mem_bodies<<<dim3((unsigned)m->nb), dim3(BODY_THREADS), 0, s>>>(*m, X, m->body_now, true);
         k_mem_forces<true><<<gf, bf, 0, s>>>(*m, X, F);
@@ -1457,29 +1591,31 @@ hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* 
     return hipGetLastError();
 }
 
-// Coupled step, forces to node lists: [binning | hinges] -> [scan | membrane forces] ->
+// Coupled step, forces to node lists: [binning | body sums | FE first pass] -> [scan | membrane forces] ->
 // scatter (whose first workgroup sets the spread's scale from the forces).
-hipError_t launch_forces_scatter(lbm_ctx* c, const ib_membrane* m, const double* X, float* F, IbArgs& a) {
-    const bool hinges = m->hinge_ptr && m->k_bend != 0.0 && m->nh > 0;
-    const int64_t nbh = hinges ? (m->nh + 255) / 256 : 0;
-    const int64_t nbb = (a.n + 255) / 256;
+hipError_t launch_forces_scatter(lbm_ctx* c, const ib_membrane* m, const double* X, float* F, IbArgs& a, bool bin) {
+    const int64_t nbb = bin ? (a.n + 255) / 256 : 0;
     const int64_t nbd = constraints_on(*m) ? m->nb : 0;
     const int64_t nbe = fe_on(*m) ? (8 * m->ne + 255) / 256 : 0;
-    const dim3 g1((unsigned)(nbh + nbb + nbd + nbe));
+    const dim3 g1((unsigned)(nbb + nbd + nbe));
     if (nbd > 0)
-        k_hinges_bin<true><<<g1, dim3(256), 0, c->stream>>>(*m, X, a, nbb, nbd, nbh);
-    else if (nbh + nbb + nbe > 0)
-        k_hinges_bin<false><<<g1, dim3(256), 0, c->stream>>>(*m, X, a, nbb, 0, nbh);
+        k_bin_first<true><<<g1, dim3(256), 0, c->stream>>>(*m, X, a, nbb, nbd);
+    else if (nbb + nbe > 0)
+        k_bin_first<false><<<g1, dim3(256), 0, c->stream>>>(*m, X, a, nbb, 0);
     if (nbe > 0) launch_fe_passes(m, X, c->stream);
-    const int64_t nbf = (8 * m->n + FS_THREADS - 1) / FS_THREADS;
+    const int64_t nbf = (NODE_LANES * m->n + FS_THREADS - 1) / FS_THREADS;
     a.blkmax_n = nbf;
-    a.scale_in_scatter = 1;
+    a.scale_in_scatter = a.scale_local ? 0 : 1;
+    a.do_scan = bin ? 1 : 0;
+    a.rec_in_forces = bin ? 0 : 1;
     if (nbd > 0)
         k_forces_scan<true><<<dim3((unsigned)(1 + nbf)), dim3(FS_THREADS), 0, c->stream>>>(*m, X, F, a);
     else
         k_forces_scan<false><<<dim3((unsigned)(1 + nbf)), dim3(FS_THREADS), 0, c->stream>>>(*m, X, F, a);
-    const int64_t nbs = nbb > 0 ? nbb : 1;  // the first workgroup sets the scale, also with no nodes
-    k_ib_scatter<<<dim3((unsigned)nbs), dim3(256), 0, c->stream>>>(a);
+    if (bin) {
+        const int64_t nbs = nbb > 0 ? nbb : 1;  // the first workgroup sets the scale, also with no nodes
+        k_ib_scatter<<<dim3((unsigned)nbs), dim3(256), 0, c->stream>>>(a);
+    }
     return hipGetLastError();
 }
 

@@ -109,7 +109,12 @@ struct IbArgs {
     int32_t nch;
     int32_t* rank;          // [n][27] packed rank of a node in each tile list it joins
     int32_t* blkbase;       // [ceil(n/256)][HS] per-block base of each hashed tile
-    int4* nbase;            // [n] stencil base (x, y, z) and channel of every node
+    int4* nbin;             // [n][2] with a binning margin: floor(X - margin) and floor(X + margin)
+                            // per axis at the node's last binning (x, y, z; w unused)
+    double margin;          // binning margin (lattice units); 0 = the exact stencil
+    int32_t scale_local;    // the spread's work items reduce the force maximum themselves
+    int32_t rec_in_forces;  // the membrane-force kernel writes the nodes' stencil bases and weights
+    int32_t do_scan;        // the scan workgroup of the force launch runs (binning steps)
     unsigned long long* part;  // [part_cap][3][512] fixed-point partial sums of split tiles' chunks
     int64_t part_cap;
     uint32_t* blkmax;       // max |F| (float bits) per bin block, or per membrane-force workgroup
@@ -209,7 +214,7 @@ struct lbm_ctx {
     int32_t* d_list = nullptr;
     int32_t* d_rank = nullptr;
     int32_t* d_blkbase = nullptr;
-    int4* d_nbase = nullptr;
+    int4* d_nbin = nullptr;
     unsigned long long* d_part = nullptr;
     int64_t part_cap = 0;
     int32_t* d_item_slot = nullptr;
@@ -218,7 +223,8 @@ struct lbm_ctx {
     int64_t ib_grid = 1024;  // workgroups of the grid-stride IB kernels (set from the CU count)
     float* d_force = nullptr;
     float* d_vel = nullptr;
-    lbm_launch launch{256, 1, 0, 1, 0, 0, -1};
+    lbm_launch launch{256, 1, 0, 1, 0, 0, -1, 1};
+    int bin_age = 0;  // coupled steps since the last binning (rebin > 1); 0 = bin at the next step
     hipStream_t side = nullptr;         // second stream of the overlapped coupled step
     hipEvent_t ev_state = nullptr, ev_far = nullptr;
     lbmib::MlpPacked* d_mlp = nullptr;
@@ -227,7 +233,7 @@ struct lbm_ctx {
     hipGraphExec_t gexec = nullptr;
     // buffer and tile-set parities the captured graph was recorded at (it reads and writes
     // fixed buffers, so it may only be replayed from the same parities)
-    int graph_cur = 0, graph_set = 0;
+    int graph_cur = 0, graph_set = 0, graph_age = 0;
     bool capturing = false;  // inside lbm_graph_capture
     // launch timer (measurement helper): event pairs around the lattice-update launches of eager
     // coupled steps
@@ -255,7 +261,12 @@ hipError_t launch_ib_interp(lbm_ctx* c, const IbArgs& a);
 hipError_t launch_ib_advance(hipStream_t s, int64_t n, double* X, const float* U);
 hipError_t launch_membrane_rest(const ib_membrane* m, const double* X_rest, hipStream_t s);
 hipError_t launch_membrane_forces(const ib_membrane* m, const double* X, float* F, hipStream_t s);
-hipError_t launch_forces_scatter(lbm_ctx* c, const ib_membrane* m, const double* X, float* F, IbArgs& a);
+hipError_t launch_forces_scatter(lbm_ctx* c, const ib_membrane* m, const double* X, float* F, IbArgs& a, bool bin);
+// binning margin of the rebin mode (lattice units)
+constexpr double REBIN_MARGIN = 0.5;
+// Lanes per node of the membrane-force kernels (measured on the shear channel, force launch
+// with node-centric hinges: 8 lanes 16.4 us, 16 lanes 26 us).
+constexpr int NODE_LANES = 8;
 // adhesion (adhesion.hip)
 bool adhesion_on(const ib_membrane& m);
 int64_t adhesion_work_ints(int64_t nl, double nx, double nz, double capture);

@@ -19,6 +19,7 @@ STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 KERNEL = {"cos": 0, "peskin4": 1}
 FLAG_NODE_OUTSIDE, FLAG_LIST_OVERFLOW, FLAG_FORCE_NONFINITE, FLAG_CLOSURE_FALLBACK = 1, 2, 4, 8
 FLAG_ADHESION_BIDS = 16
+FLAG_REBIN_MARGIN = 32
 
 EXPORTS = [
     "lbm_workspace_bytes", "lbm_create", "lbm_destroy", "lbm_init", "lbm_step", "ib_set_nodes",
@@ -45,14 +46,14 @@ class LbmParams(C.Structure):
 
 class LbmLaunch(C.Structure):
     _fields_ = [("block", C.c_int32), ("xcd_remap", C.c_int32), ("persistent", C.c_int32),
-                ("nontemporal", C.c_int32), ("vec", C.c_int32), ("overlap", C.c_int32), ("split", C.c_int32)]
+                ("nontemporal", C.c_int32), ("vec", C.c_int32), ("overlap", C.c_int32), ("split", C.c_int32),
+                ("rebin", C.c_int32)]
 
 
 class IbMembrane(C.Structure):
     _fields_ = [("n", C.c_int64), ("nbr_ptr", C.c_void_p), ("nbr_idx", C.c_void_p), ("rest_len", C.c_void_p),
                 ("k_spring", C.c_double), ("hinge_ptr", C.c_void_p), ("hinge_inc", C.c_void_p),
-                ("hinges", C.c_void_p), ("rest_cs", C.c_void_p), ("hinge_slot", C.c_void_p),
-                ("hinge_force", C.c_void_p),
+                ("hinges", C.c_void_p), ("rest_cs", C.c_void_p),
                 ("nh", C.c_int64), ("k_bend", C.c_double),
                 ("anchors", C.c_void_p), ("k_tether", C.c_double),
                 ("tri", C.c_void_p), ("nt", C.c_int64), ("tri_ptr", C.c_void_p), ("tri_inc", C.c_void_p),
@@ -380,15 +381,16 @@ class Lattice:
                    "lbm_launch_timer_read")
         return n.value, us.value, kind.value
 
-    def set_launch(self, block=256, xcd_remap=1, persistent=0, nontemporal=0, vec=0, overlap=0, split=-1):
-        cfg = LbmLaunch(block, xcd_remap, persistent, nontemporal, vec, overlap, split)
+    def set_launch(self, block=256, xcd_remap=1, persistent=0, nontemporal=0, vec=0, overlap=0, split=-1, rebin=1):
+        cfg = LbmLaunch(block, xcd_remap, persistent, nontemporal, vec, overlap, split, rebin)
         _check(lib().lbm_set_launch(self.h, C.byref(cfg)), "lbm_set_launch")
 
     def get_launch(self):
         cfg = LbmLaunch()
         _check(lib().lbm_get_launch(self.h, C.byref(cfg)), "lbm_get_launch")
         return dict(block=cfg.block, xcd_remap=cfg.xcd_remap, persistent=cfg.persistent,
-                    nontemporal=cfg.nontemporal, vec=cfg.vec, overlap=cfg.overlap, split=cfg.split)
+                    nontemporal=cfg.nontemporal, vec=cfg.vec, overlap=cfg.overlap, split=cfg.split,
+                    rebin=cfg.rebin)
 
 
 def stream_copy(src, dst, variant=0, grid=0):
@@ -524,11 +526,8 @@ class Membrane:
             hp, hi = inputs.csr_hinges(n, bodies.hinges)
             hpt, hit, ht = dev_i32(hp), dev_i32(hi), dev_i32(bodies.hinges.reshape(-1))
             rt = torch.zeros(2 * len(bodies.hinges), dtype=torch.float64, device=dev)
-            hf = torch.zeros(12 * len(bodies.hinges), dtype=torch.float32, device=dev)
-            hs = torch.zeros(4 * len(bodies.hinges), dtype=torch.int32, device=dev)
-            self._keep += [rt, hf, hs]
+            self._keep += [rt]
             s.hinge_ptr, s.hinge_inc, s.hinges, s.rest_cs = hpt.data_ptr(), hit.data_ptr(), ht.data_ptr(), rt.data_ptr()
-            s.hinge_force, s.hinge_slot = hf.data_ptr(), hs.data_ptr()
             s.nh = len(bodies.hinges)
         s.k_bend = float(bodies.k_bend)
         if bodies.anchors is not None:

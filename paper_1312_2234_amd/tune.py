@@ -3,10 +3,11 @@
 Times each candidate `lbm_launch` on the caller's own context with HIP events and keeps the
 fastest.  With the Lagrangian nodes and membrane of a workload it times what the benchmark
 runs: the whole coupled step (forces -> spread -> lattice update -> interpolation -> move),
-replayed from a captured 2-step HIP graph, over the lattice kernel's launch shapes (workgroup
-size, XCD-aware order, persistent grid, non-temporal stores, cells per lane) and the two
+replayed from a captured HIP graph, over the lattice kernel's launch shapes (workgroup
+size, XCD-aware order, persistent grid, non-temporal stores, cells per lane), the two
 coupled-step schedules (one fused update after the spread, or the body-force update in the
-spread's launch followed by the flagged tiles).  Without nodes it times back-to-back lattice
+spread's launch followed by the flagged tiles) and the binning interval (every step, or every
+2, 4 or 8 steps with a margin).  Without nodes it times back-to-back lattice
 steps.  Results are cached in a JSON file keyed by GPU architecture, storage form, size class
 (total cells rounded to a power of two, number of channels) and what was timed, so later runs
 reuse them without re-timing.
@@ -20,7 +21,12 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(_HERE, "tuned_launch.json")
 
-DEFAULT = dict(block=256, xcd_remap=1, persistent=0, nontemporal=1, vec=0, overlap=0, split=-1)
+DEFAULT = dict(block=256, xcd_remap=1, persistent=0, nontemporal=1, vec=0, overlap=0, split=-1, rebin=1)
+
+
+def graph_steps(cfg):
+    """Steps of a captured coupled-step graph for the launch cfg (a multiple of 2 rebin)."""
+    return 2 * max(1, int(cfg.get("rebin", 1)))
 
 
 def lattice_candidates(n_cu=256):
@@ -43,8 +49,12 @@ def coupled_candidates(n_cu=256):
     update (its body-force launch has a fixed shape; only the store kind and the flagged-tile
     launch vary)."""
     out = [dict(c, split=0) for c in lattice_candidates(n_cu)]
+    # binning every 2, 4 or 8 steps: 8 keeps the half-cell margin for nodes up to 1/16 cell per step
     for nt in (0, 1):
-        out.append(dict(block=256, xcd_remap=1, persistent=0, nontemporal=nt, vec=0, split=1))
+        for rebin in (1, 2, 4, 8):
+            out.append(dict(block=256, xcd_remap=1, persistent=0, nontemporal=nt, vec=0, split=1, rebin=rebin))
+    for rebin in (2, 4, 8):
+        out.append(dict(block=128, xcd_remap=0, persistent=0, nontemporal=1, vec=0, split=0, rebin=rebin))
     return out
 
 
@@ -78,20 +88,23 @@ def time_launch(lat, cfg, steps=20, warmup=3):
 
 
 def time_coupled(lat, cfg, coupled, steps=20, warmup=4):
-    """Average time (ms) of one coupled step with launch `cfg`, replayed from a captured 2-step
-    graph (the state and the nodes advance).  coupled = (membrane, X, F, U)."""
+    """Average time (ms) of one coupled step with launch `cfg`, replayed from a captured graph of
+    graph_steps(cfg) steps (the state and the nodes advance).  coupled = (membrane, X, F, U)."""
     torch = lat.torch
     mem, X, F, U = coupled
-    lat.set_launch(**dict(DEFAULT, **cfg))
-    lat.graph_capture(mem, 2, X, F, U)
-    lat.graph_launch(warmup // 2)
+    full = dict(DEFAULT, **cfg)
+    lat.set_launch(**full)
+    G = graph_steps(full)
+    lat.graph_capture(mem, G, X, F, U)
+    lat.graph_launch(max(1, warmup // G))
+    reps = max(1, steps // G)
     e0, e1 = _events(torch)
     torch.cuda.synchronize()
     e0.record(lat.stream)
-    lat.graph_launch(steps // 2)
+    lat.graph_launch(reps)
     e1.record(lat.stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / (2 * (steps // 2))
+    return e0.elapsed_time(e1) / (G * reps)
 
 
 def tune(lat, steps=20, cands=None, verbose=False, coupled=None):
@@ -133,7 +146,7 @@ def save(lat, best, ms, what="coupled"):
             data = json.load(open(CACHE))
         except (OSError, ValueError):
             data = {}
-    timed = ("coupled step, 2-step HIP graph replay" if what == "coupled" else "lattice step, back-to-back launches")
+    timed = ("coupled step, HIP graph replay" if what == "coupled" else "lattice step, back-to-back launches")
     data[_key(lat, what)] = {"launch": best, "ms_per_step": ms, "timed": timed}
     tmp = CACHE + ".tmp%d" % os.getpid()
     with open(tmp, "w") as f:

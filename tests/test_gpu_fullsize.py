@@ -18,7 +18,8 @@ pytestmark = pytest.mark.gpu
 
 
 def gpu_bench_config(gpu, channels, steps):
-    """The benchmark's launch configuration: tuned launch shape and schedule, 2-step graph replay."""
+    """The benchmark's launch configuration: tuned launch shape, schedule and binning interval,
+    graph replay (the steps beyond a multiple of the graph's length eagerly)."""
     import torch
 
     from paper_1312_2234_amd import tune
@@ -34,8 +35,11 @@ def gpu_bench_config(gpu, channels, steps):
     tune.apply_cached_or_tune(g, coupled=(mem, X, F, U))
     g.init()
     X.copy_(T(b.X))
-    g.graph_capture(mem, 2, X, F, U)
-    g.graph_launch(steps // 2)
+    G = tune.graph_steps(g.get_launch())
+    g.graph_capture(mem, G, X, F, U)
+    g.graph_launch(steps // G)
+    if steps % G:
+        g.coupled_steps(mem, steps % G, X, F, U)
     torch.cuda.synchronize()
     return g, N(X), N(U), offs
 
