@@ -43,6 +43,12 @@ def make_workload(name):
         desc = ("shear channel 256x128x128, top wall u=0.05, tau=1.0, 16 oblate platelets "
                 "(6,2,6) x 2562 IB nodes, spring k=0.005 + bending 1e-4")
         return [ch], desc
+    if name == "shear_large":
+        ch = inputs.shear_platelets(seed=0, nx=512, ny=256, nz=128, count=64)
+        desc = ("shear channel 512x256x128 (populations too large for the 256 MB Infinity Cache in every storage "
+                "form), top wall u=0.05, tau=1.0, 64 oblate platelets (6,2,6) x 2562 IB nodes, spring k=0.005 + "
+                "bending 1e-4")
+        return [ch], desc
     if name == "shear_onsite":
         ch = dataclasses.replace(inputs.shear_platelets(seed=0), walls="onsite")
         desc = ("shear channel 256x128x128 with on-site velocity walls (Eq. 23-30) on rows 0 and 127, "

@@ -141,6 +141,8 @@ def test_bench_workloads_build():
     chans, desc = bench.make_workload("shear")
     assert (chans[0].nx, chans[0].ny, chans[0].nz) == (256, 128, 128) and chans[0].bodies.n == 16 * 2562
     assert chans[0].walls is True and chans[0].bodies.triangles is None
+    chans, desc = bench.make_workload("shear_large")
+    assert (chans[0].nx, chans[0].ny, chans[0].nz) == (512, 256, 128) and chans[0].bodies.n == 64 * 2562
     chans, desc = bench.make_workload("shear_onsite")
     assert chans[0].walls == "onsite" and "on-site" in desc
     chans, desc = bench.make_workload("shear_constrained")
