@@ -331,12 +331,12 @@ __global__ void __launch_bounds__(256, 3) k_step_cl(LatArgs a, const MlpPacked* 
             n = (int32_t)((seg - chp->seg_off) * 64 + lane);
             valid = n < chp->ncell;
         }
-        float g[Q];
+        float gn[Q];  // the plain step's post-collision values
         float in[16], mm = 0.0f;
-        CellState cs{};
         if (valid) {
             const Chan& ch = *chp;
             int x, y, z;
+            float g[Q];
             cell_xyz(ch, (uint32_t)n, x, y, z);
             pull<St>((const T*)a.src + ch.pop_off, ch, ch.ncell, n, x, y, z, g);
             float drho, jx, jy, jz, Fx, Fy, Fz;
@@ -346,10 +346,14 @@ __global__ void __launch_bounds__(256, 3) k_step_cl(LatArgs a, const MlpPacked* 
                 onsite_wall(ch, y, g, Fx, Fy, Fz);
                 moments(g, drho, jx, jy, jz);
             }
-            cs = cell_state(drho, jx, jy, jz, Fx, Fy, Fz);
+            const CellState cs = cell_state(drho, jx, jy, jz, Fx, Fy, Fz);
+            // g - g^eq feeds both the moments and the collision: one equilibrium per direction
             float d[Q], m[MLP_NNC];
 #pragma unroll
-            for (int i = 0; i < Q; ++i) d[i] = g[i] - geq_c(i, cs);
+            for (int i = 0; i < Q; ++i) {
+                d[i] = g[i] - geq_c(i, cs);
+                gn[i] = bgk_from_neq(i, g[i], d[i], cs, ch.omega, ch.guo);
+            }
             to_moments(d, m);
 #pragma unroll
             for (int k = 0; k < MLP_NNC; ++k) {
@@ -375,17 +379,15 @@ __global__ void __launch_bounds__(256, 3) k_step_cl(LatArgs a, const MlpPacked* 
             // reject non-finite corrections and |dm| > c |m| (NaN compares false)
             const bool ok = dd <= cg * cg * mm;
             T* dst = (T*)a.dst + ch.pop_off;
-            const float om = ch.omega, guo = ch.guo;
             float df[Q];
             from_moments(dm, df);
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                float gn = bgk_c(i, g[i], cs, om, guo);  // the plain step's value
-                if (ok) gn += df[i];
+                const float v = ok ? gn[i] + df[i] : gn[i];
                 if (NT)
-                    St::st_nt(dst + pidx(i, n), gn);
+                    St::st_nt(dst + pidx(i, n), v);
                 else
-                    St::st(dst + pidx(i, n), gn);
+                    St::st(dst + pidx(i, n), v);
             }
             const uint64_t bad = __ballot(!ok);
             if (bad && lane == __ffsll((unsigned long long)bad) - 1) atomicAdd(&blk_bad, (unsigned)__popcll(bad));

@@ -327,6 +327,15 @@ __device__ __forceinline__ float bgk_c(int i, float g, const CellState& s, float
     return fmaf(-om, g - geq, g) + S;
 }
 
+// The same with g - geq already at hand (the same bits as bgk_c)
+__device__ __forceinline__ float bgk_from_neq(int i, float g, float neq, const CellState& s, float om, float guo) {
+#pragma clang fp contract(off)
+    const float cu = cdot(i, s.vx, s.vy, s.vz);
+    const float cF = cdot(i, s.Fx, s.Fy, s.Fz);
+    const float S = (wgt(i) * guo) * fmaf(fmaf(9.0f, cu, 3.0f), cF, -s.vF3);
+    return fmaf(-om, neq, g) + S;
+}
+
 // IB force-field lookup: tile of the cell -> slot (or -1) -> [3][512] block.
 __device__ __forceinline__ int64_t tile_of(const Chan& ch, int x, int y, int z) {
     return ch.tile_off + (x >> 3) + (int64_t)ch.tnx * ((y >> 3) + (int64_t)ch.tny * (z >> 3));
