@@ -718,9 +718,11 @@ lbm_status lbm_get_launch(const lbm_ctx* c, lbm_launch* cfg) {
 lbm_status lbm_launch_timer(lbm_ctx* c, int32_t enable) {
     if (!c || (enable != 0 && enable != 1)) return LBM_ERR_ARG;
     if (enable && c->tev.empty()) {
+        // timing-only events: without the system-scope fence at each record, which would add
+        // the writeback of the L2 that the timed launch left dirty to its measured time
         std::vector<hipEvent_t> evs(2 * LBM_TIMER_PAIRS, nullptr);
         for (hipEvent_t& ev : evs)
-            if (hipEventCreate(&ev) != hipSuccess) {
+            if (hipEventCreateWithFlags(&ev, hipEventDisableSystemFence) != hipSuccess) {
                 for (hipEvent_t made : evs)
                     if (made) hipEventDestroy(made);
                 return LBM_ERR_HIP;
