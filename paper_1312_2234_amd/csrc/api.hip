@@ -125,6 +125,9 @@ LatArgs lat_args(lbm_ctx* c) {
     a.nseg = c->total_segs;
     a.src = c->pop[c->cur];
     a.dst = c->pop[c->cur ^ 1];
+    // every other step walks the lattice backwards: it first reads the cells the previous
+    // step wrote last, which the Infinity Cache may still hold
+    a.reverse = c->cur & 1;
     if (c->max_nodes > 0) {
         a.tile_slot = c->set[c->ibset].tile_slot;
         a.force = c->d_force;

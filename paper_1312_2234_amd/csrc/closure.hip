@@ -322,11 +322,12 @@ __global__ void __launch_bounds__(256, 3) k_step_cl(LatArgs a, const MlpPacked* 
     const float* nrm = P->norm;
     const float cg = P->c_guard;
     for (int64_t base = (int64_t)blockIdx.x * 4; base < a.nseg; base += (int64_t)gridDim.x * 4) {
-        const int64_t seg = base + wave;
+        const int64_t sw = base + wave;
+        const int64_t seg = a.reverse ? a.nseg - 1 - sw : sw;
         bool valid = false;
         const Chan* chp = nullptr;
         int32_t n = 0;
-        if (seg < a.nseg) {
+        if (sw < a.nseg) {
             chp = &a.chan[a.seg_ch[seg]];
             n = (int32_t)((seg - chp->seg_off) * 64 + lane);
             valid = n < chp->ncell;

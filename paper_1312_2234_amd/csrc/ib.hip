@@ -645,8 +645,9 @@ __global__ void __launch_bounds__(SP_THREADS) k_spread_far(IbArgs a, LatArgs la,
     }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int64_t seg = ((int64_t)blockIdx.x - gs) * (SP_THREADS / 64) + wave;
-    if (seg >= la.nseg) return;
+    const int64_t sw = ((int64_t)blockIdx.x - gs) * (SP_THREADS / 64) + wave;
+    if (sw >= la.nseg) return;
+    const int64_t seg = la.reverse ? la.nseg - 1 - sw : sw;
     const Chan& ch = la.chan[la.seg_ch[seg]];
     const int64_t n64 = (seg - ch.seg_off) * 64 + lane;
     if (n64 >= ch.ncell) return;

@@ -129,8 +129,9 @@ __global__ void __launch_bounds__(256) k_step_v(LatArgs a) {
     const int64_t G = gridDim.x;
     int64_t L = a.remap ? xcd_remap(blockIdx.x, G) : (int64_t)blockIdx.x;
     for (;; L += G) {
-        const int64_t seg = (L * wpb + wave) * V;
-        if (seg >= a.nseg) break;
+        const int64_t sw = (L * wpb + wave) * V;
+        if (sw >= a.nseg) break;
+        const int64_t seg = a.reverse ? a.nseg - V - sw : sw;  // nseg is a multiple of V
         const Chan& ch = a.chan[a.seg_ch[seg]];
         const int32_t n0 = (int32_t)((seg - ch.seg_off) * 64) + lane * V;
         int x0, y, z;

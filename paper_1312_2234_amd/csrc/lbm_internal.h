@@ -76,6 +76,7 @@ struct LatArgs {
     float* force_w;            // force blocks, written by the merging tile update
     int32_t remap;          // XCD-aware block order
     int32_t persistent;     // loop over blocks
+    int32_t reverse;        // walk the segments from the last one (every other step)
     // auxiliary inputs / outputs of the non-step kernels
     const float* in_rho;
     const float* in_u;
@@ -139,8 +140,9 @@ __device__ __forceinline__ void for_cells(const LatArgs& a, Body body) {
     const int64_t G = gridDim.x;
     int64_t L = a.remap ? xcd_remap(blockIdx.x, G) : (int64_t)blockIdx.x;
     for (;; L += G) {
-        const int64_t seg = L * wpb + wave;
-        if (seg >= a.nseg) break;
+        const int64_t sw = L * wpb + wave;
+        if (sw >= a.nseg) break;
+        const int64_t seg = a.reverse ? a.nseg - 1 - sw : sw;
         const int c = a.seg_ch[seg];
         const Chan& ch = a.chan[c];
         const int64_t n = (seg - ch.seg_off) * 64 + lane;
