@@ -183,6 +183,18 @@ __device__ __forceinline__ acc4 mfma(bf4 a, bf4 b, acc4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// Two K = 16 steps in one gfx950 K = 32 instruction: A = (a0 | a1), B = (b0 | b1) per lane.
+// The contraction pairs the same slot of A and B, so a0 meets b0 and a1 meets b1 whatever the
+// instruction's order of k within a lane.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ acc4 mfma2(bf4 a0, bf4 a1, bf4 b0, bf4 b1, acc4 c) {
+    typedef short s8v __attribute__((ext_vector_type(8)));
+    const s8v a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+    const s8v b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0,
+                                                   0);
+}
+
 // ---------------------------------------------------------------- packing
 // Fragment f, lane L, element r (q = L / 16, p = L % 16):
 //   forward  0..3   W1 tile o:        A[i=p][k=4q+r] = W1[4q+r][16o+p]
@@ -228,17 +240,26 @@ __global__ void __launch_bounds__(64) k_mlp_pack(const float* __restrict__ param
 struct FwdW {
     bf4 a1[4], a2[16], a3[4];
     acc4 b1[4], b2[4], b3;
+    __device__ __forceinline__ acc4 bias1(int o) const { return b1[o]; }
+    __device__ __forceinline__ acc4 bias2(int o) const { return b2[o]; }
+    __device__ __forceinline__ acc4 bias3() const { return b3; }
+    __device__ __forceinline__ void next_tile() {}
 };
 
-__device__ __forceinline__ void load_fwd(const MlpPacked* __restrict__ P, FwdW& W) {
-    const int lane = threadIdx.x & 63, q = lane >> 4;
+__device__ __forceinline__ void load_frags(const MlpPacked* __restrict__ P, bf4 a1[4], bf4 a2[16], bf4 a3[4]) {
+    const int lane = threadIdx.x & 63;
     const bf4* fr = (const bf4*)P->frag;
 #pragma unroll
-    for (int o = 0; o < 4; ++o) W.a1[o] = fr[(0 + o) * 64 + lane];
+    for (int o = 0; o < 4; ++o) a1[o] = fr[(0 + o) * 64 + lane];
 #pragma unroll
-    for (int o = 0; o < 16; ++o) W.a2[o] = fr[(4 + o) * 64 + lane];
+    for (int o = 0; o < 16; ++o) a2[o] = fr[(4 + o) * 64 + lane];
 #pragma unroll
-    for (int o = 0; o < 4; ++o) W.a3[o] = fr[(20 + o) * 64 + lane];
+    for (int o = 0; o < 4; ++o) a3[o] = fr[(20 + o) * 64 + lane];
+}
+
+__device__ __forceinline__ void load_fwd(const MlpPacked* __restrict__ P, FwdW& W) {
+    const int q = (threadIdx.x & 63) >> 4;
+    load_frags(P, W.a1, W.a2, W.a3);
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
         W.b1[o] = *(const acc4*)(P->bias + 16 * o + 4 * q);
@@ -247,22 +268,37 @@ __device__ __forceinline__ void load_fwd(const MlpPacked* __restrict__ P, FwdW& 
     W.b3 = *(const acc4*)(P->bias + 2 * MLP_NH + 4 * q);
 }
 
+// The same network with the biases read at each use from a workgroup's LDS copy
+// (2 * MLP_NH + MLP_NOUT floats; `sb` points at this lane's row group 4q): 36 registers fewer
+// per lane.  The pointer is passed through an empty asm statement for every tile, so that the
+// compiler reads the biases again instead of keeping them in registers across the tiles.
+typedef __attribute__((address_space(3))) const float* lds_cfp;
+struct FwdL {
+    bf4 a1[4], a2[16], a3[4];
+    lds_cfp sb;
+    __device__ __forceinline__ acc4 bias1(int o) const { return *(const acc4*)(sb + 16 * o); }
+    __device__ __forceinline__ acc4 bias2(int o) const { return *(const acc4*)(sb + MLP_NH + 16 * o); }
+    __device__ __forceinline__ acc4 bias3() const { return *(const acc4*)(sb + 2 * MLP_NH); }
+    __device__ __forceinline__ void next_tile() { asm volatile("" : "+v"(sb)); }
+};
+
 // One 16-cell tile: xb = inputs in B layout (k = feature 4q+r, column = cell p); returns
 // the 16 outputs in accumulator layout (row = output 4q+r, column = cell p) and, when
 // asked, the two hidden activations in B layout.
-__device__ __forceinline__ acc4 mlp_tile(const FwdW& W, bf4 xb, bf4 h1[4], bf4 h2[4]) {
+template <class W_>
+__device__ __forceinline__ acc4 mlp_tile(const W_& W, bf4 xb, bf4 h1[4], bf4 h2[4]) {
 #pragma unroll
-    for (int o = 0; o < 4; ++o) h1[o] = relu_bf16(mfma(W.a1[o], xb, W.b1[o]));
+    for (int o = 0; o < 4; ++o) h1[o] = relu_bf16(mfma(W.a1[o], xb, W.bias1(o)));
 #pragma unroll
     for (int o2 = 0; o2 < 4; ++o2) {
-        acc4 a = W.b2[o2];
-#pragma unroll
-        for (int o = 0; o < 4; ++o) a = mfma(W.a2[4 * o2 + o], h1[o], a);
+        acc4 a = W.bias2(o2);
+        a = mfma2(W.a2[4 * o2 + 0], W.a2[4 * o2 + 1], h1[0], h1[1], a);
+        a = mfma2(W.a2[4 * o2 + 2], W.a2[4 * o2 + 3], h1[2], h1[3], a);
         h2[o2] = relu_bf16(a);
     }
-    acc4 y = W.b3;
-#pragma unroll
-    for (int o = 0; o < 4; ++o) y = mfma(W.a3[o], h2[o], y);
+    acc4 y = W.bias3();
+    y = mfma2(W.a3[0], W.a3[1], h2[0], h2[1], y);
+    y = mfma2(W.a3[2], W.a3[3], h2[2], h2[3], y);
     return y;
 }
 
@@ -274,7 +310,8 @@ struct WaveStage {
 
 // Run the network on the 64 cells of this wavefront: in[16] per lane (standardised) ->
 // out[16] per lane.  Every lane of the wavefront must call it (matrix cores use all 64).
-__device__ __forceinline__ void mlp_wave(const FwdW& W, WaveStage& S, const float in[16], float out[16]) {
+template <class W_>
+__device__ __forceinline__ void mlp_wave(W_& W, WaveStage& S, const float in[16], float out[16]) {
     const int lane = threadIdx.x & 63, q = lane >> 4, p = lane & 15;
     typedef unsigned u4v __attribute__((ext_vector_type(4)));
     u4v lo, hi;
@@ -289,6 +326,7 @@ __device__ __forceinline__ void mlp_wave(const FwdW& W, WaveStage& S, const floa
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const bf4 xb = *(const bf4*)&S.x[(16 * t + p) * 16 + 4 * q];
+        W.next_tile();
         bf4 h1[4], h2[4];
         const acc4 y = mlp_tile(W, xb, h1, h2);
         *(acc4*)&S.y[(16 * t + p) * 16 + 4 * q] = y;
@@ -305,44 +343,114 @@ __device__ __forceinline__ void mlp_wave(const FwdW& W, WaveStage& S, const floa
 }
 
 // ---------------------------------------------------------------- closure step
+// A channel descriptor read through the constant address space: with a wavefront-uniform
+// address the compiler reads it with scalar loads (the descriptors are not written while a
+// kernel runs).  Fields that are not used are not loaded.
+__device__ __forceinline__ Chan chan_const(const Chan* p) {
+    typedef __attribute__((address_space(4))) const uint32_t* cu32_p;
+    static_assert(sizeof(Chan) % 4 == 0, "descriptor of whole words");
+    Chan c;
+    uint32_t* d = (uint32_t*)&c;
+    const cu32_p s = (cu32_p)p;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(Chan) / 4); ++k) d[k] = s[k];
+    return c;
+}
+
 // The lattice step of k_step (pull, moments, Guo-forced BGK, aligned store) with the
 // learned correction added before the store.  Workgroups of 256 threads walk the
 // segments four at a time with a uniform trip count (the LDS transposes use barriers).
-// (at most 168 registers: three wavefronts per SIMD hide more of the population loads)
+// At most 168 registers: three wavefronts per SIMD.
 template <class St, bool NT>
 __global__ void __launch_bounds__(256, 3) k_step_cl(LatArgs a, const MlpPacked* __restrict__ P, uint32_t* flags,
                                                  unsigned long long* guarded) {
     using T = typename St::T;
     __shared__ WaveStage stage[4];
+    __shared__ float sbias[2 * MLP_NH + MLP_NOUT];
     __shared__ unsigned int blk_bad;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wavefront index as a scalar: segment, channel and its fields then live in scalar
+    // registers and are read with scalar loads, which do not wait behind the prefetch
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (threadIdx.x == 0) blk_bad = 0u;  // first read after the barriers of the first pass
-    FwdW W;
-    load_fwd(P, W);
+    if (threadIdx.x < 2 * MLP_NH + MLP_NOUT) sbias[threadIdx.x] = P->bias[threadIdx.x];  // read after them too
+    FwdL W;
+    load_frags(P, W.a1, W.a2, W.a3);
+    W.sb = (lds_cfp)(sbias + 4 * (lane >> 4));
+    // Wait for the weights here: otherwise the first use of each fragment, inside the loop,
+    // carries a wait that in later iterations also waits for the prefetch.
+#pragma unroll
+    for (int o = 0; o < 4; ++o) asm volatile("" ::"v"(W.a1[o]), "v"(W.a3[o]));
+#pragma unroll
+    for (int o = 0; o < 16; ++o) asm volatile("" ::"v"(W.a2[o]));
     const float* nrm = P->norm;
     const float cg = P->c_guard;
-    for (int64_t base = (int64_t)blockIdx.x * 4; base < a.nseg; base += (int64_t)gridDim.x * 4) {
-        const int64_t sw = base + wave;
+    // The next segment's populations and IB force are loaded one iteration ahead, so that
+    // their latency overlaps this segment's network: its populations and the force slot of
+    // each cell's tile early in the iteration, the force itself before this segment's stores
+    // (a wait for a load issued after the stores would wait for the stores as well).  The
+    // segment and channel are wavefront-uniform and read through the constant address space,
+    // i.e. with scalar loads, which do not wait behind the vector loads in flight.
+    typedef __attribute__((address_space(4))) const int32_t* cint_p;
+    // segment of wavefront step sw: its channel and this lane's cell (false past the end)
+    auto locate = [&](int64_t sw, int32_t& ci, int32_t& n) -> bool {
+        if (sw >= a.nseg) return false;
         const int64_t seg = a.reverse ? a.nseg - 1 - sw : sw;
-        bool valid = false;
-        const Chan* chp = nullptr;
-        int32_t n = 0;
-        if (sw < a.nseg) {
-            chp = &a.chan[a.seg_ch[seg]];
-            n = (int32_t)((seg - chp->seg_off) * 64 + lane);
-            valid = n < chp->ncell;
+        ci = ((cint_p)a.seg_ch)[seg];
+        const Chan ch = chan_const(a.chan + ci);
+        n = (int32_t)((seg - ch.seg_off) * 64 + lane);
+        return n < ch.ncell;
+    };
+    auto load_pops = [&](int32_t ci, int32_t n, int32_t& slot, float r[Q]) {
+        const Chan ch = chan_const(a.chan + ci);
+        int x, y, z;
+        cell_xyz(ch, (uint32_t)n, x, y, z);
+        if (a.tile_slot) slot = a.tile_slot[tile_of(ch, x, y, z)];
+        pull_loads<St>((const T*)a.src + ch.pop_off, ch, n, x, y, z, r);
+    };
+    auto load_force = [&](int32_t ci, int32_t n, int32_t slot, float f[3]) {
+        if (slot >= 0) {
+            const Chan ch = chan_const(a.chan + ci);
+            int x, y, z;
+            cell_xyz(ch, (uint32_t)n, x, y, z);
+            const float* fb = a.force + (int64_t)slot * (3 * TILE_CELLS) + tile_local(x, y, z);
+            f[0] = fb[0];
+            f[1] = fb[TILE_CELLS];
+            f[2] = fb[2 * TILE_CELLS];
         }
+    };
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    int32_t ci_nx = 0, n_nx = 0, slot_nx = -1;
+    float r[Q], f_nx[3] = {0.0f, 0.0f, 0.0f};
+    bool valid_nx = locate((int64_t)blockIdx.x * 4 + wave, ci_nx, n_nx);
+    if (valid_nx) {
+        load_pops(ci_nx, n_nx, slot_nx, r);
+        load_force(ci_nx, n_nx, slot_nx, f_nx);
+    }
+    for (int64_t base = (int64_t)blockIdx.x * 4; base < a.nseg; base += stride) {
+        const bool valid = valid_nx;
+        const int32_t n = n_nx, slot = slot_nx;
+        const Chan ch = chan_const(a.chan + ci_nx);
+        float g[Q];
+        float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
+        int x = 0, y = 0, z = 0;
+        if (valid) {
+            cell_xyz(ch, (uint32_t)n, x, y, z);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) g[i] = r[i];
+            pull_walls(ch, y, g);
+            // the channel's force plus the tile's (as ib_force adds them)
+            Fx = slot >= 0 ? ch.body[0] + f_nx[0] : ch.body[0];
+            Fy = slot >= 0 ? ch.body[1] + f_nx[1] : ch.body[1];
+            Fz = slot >= 0 ? ch.body[2] + f_nx[2] : ch.body[2];
+        }
+        valid_nx = locate(base + stride + wave, ci_nx, n_nx);
+        slot_nx = -1;
+        if (valid_nx) load_pops(ci_nx, n_nx, slot_nx, r);
         float gn[Q];  // the plain step's post-collision values
         float in[16], mm = 0.0f;
         if (valid) {
-            const Chan& ch = *chp;
-            int x, y, z;
-            float g[Q];
-            cell_xyz(ch, (uint32_t)n, x, y, z);
-            pull<St>((const T*)a.src + ch.pop_off, ch, ch.ncell, n, x, y, z, g);
-            float drho, jx, jy, jz, Fx, Fy, Fz;
+            float drho, jx, jy, jz;
             moments(g, drho, jx, jy, jz);
-            ib_force(a, ch, x, y, z, Fx, Fy, Fz);
             if (St::onsite && onsite_row(ch, y)) {
                 onsite_wall(ch, y, g, Fx, Fy, Fz);
                 moments(g, drho, jx, jy, jz);
@@ -370,7 +478,6 @@ __global__ void __launch_bounds__(256, 3) k_step_cl(LatArgs a, const MlpPacked* 
         float out[16];
         mlp_wave(W, stage[wave], in, out);
         if (valid) {
-            const Chan& ch = *chp;
             float dm[MLP_NNC], dd = 0.0f;
 #pragma unroll
             for (int k = 0; k < MLP_NNC; ++k) {
@@ -382,6 +489,7 @@ __global__ void __launch_bounds__(256, 3) k_step_cl(LatArgs a, const MlpPacked* 
             T* dst = (T*)a.dst + ch.pop_off;
             float df[Q];
             from_moments(dm, df);
+            if (valid_nx) load_force(ci_nx, n_nx, slot_nx, f_nx);
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const float v = ok ? gn[i] + df[i] : gn[i];
@@ -392,6 +500,8 @@ __global__ void __launch_bounds__(256, 3) k_step_cl(LatArgs a, const MlpPacked* 
             }
             const uint64_t bad = __ballot(!ok);
             if (bad && lane == __ffsll((unsigned long long)bad) - 1) atomicAdd(&blk_bad, (unsigned)__popcll(bad));
+        } else if (valid_nx) {
+            load_force(ci_nx, n_nx, slot_nx, f_nx);
         }
     }
     // one global update per workgroup for the fallback count (the loop is uniform)

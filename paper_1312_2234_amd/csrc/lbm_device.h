@@ -144,10 +144,12 @@ __device__ __forceinline__ void stv(typename St::T* p, const float in[V]) {
 // f_i(x) = f*_opp(i)(x) + 6 w_i c_i.u_w.  In the shifted variables the same relation
 // holds for g = f - w because w_i = w_opp(i).  `s` points at the channel's block.  With
 // on-site walls the entering populations of a wall row are loaded the same way and then
-// replaced by onsite_wall().
+// replaced by onsite_wall().  pull = pull_loads (the stored values, the bounce-back source
+// chosen) then pull_walls (the moving-wall term), which a kernel may also call apart, with
+// the loads issued ahead of their use.
 template <class St>
-__device__ __forceinline__ void pull(const typename St::T* __restrict__ s, const Chan& ch, int64_t N,
-                                     int32_t n, int x, int y, int z, float g[Q]) {
+__device__ __forceinline__ void pull_loads(const typename St::T* __restrict__ s, const Chan& ch, int32_t n, int x,
+                                           int y, int z, float g[Q]) {
     const int nx = ch.nx, ny = ch.ny, nz = ch.nz;
     const int32_t sxy = nx * ny;
     const int32_t ox_p = (x == 0) ? (nx - 1) : -1;          // c_x = +1 comes from x-1
@@ -165,14 +167,29 @@ __device__ __forceinline__ void pull(const typename St::T* __restrict__ s, const
                       (cz(i) == 1 ? oz_p : (cz(i) == -1 ? oz_m : 0));
         const bool bb = (cy(i) == 1 && wlo) || (cy(i) == -1 && whi);
         const typename St::T* p = bb ? (s + pidx(opp(i), n)) : (s + pidx(i, n + off));
-        float v = St::ld(p);
+        g[i] = St::ld(p);
+    }
+}
+
+// The moving-wall term of the bounced-back populations, added to the loaded values.
+__device__ __forceinline__ void pull_walls(const Chan& ch, int y, float g[Q]) {
+    const bool wlo = ch.walls && y == 0;
+    const bool whi = ch.walls && y == ch.ny - 1;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
         if (cy(i) != 0) {
+            const bool bb = (cy(i) == 1 && wlo) || (cy(i) == -1 && whi);
             const float* u = cy(i) == 1 ? ch.uw_lo : ch.uw_hi;
             float corr = 6.0f * wgt(i) * (cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2]);
-            v += bb ? corr : 0.0f;
+            g[i] += bb ? corr : 0.0f;
         }
-        g[i] = v;
-    }
+}
+
+template <class St>
+__device__ __forceinline__ void pull(const typename St::T* __restrict__ s, const Chan& ch, int64_t N,
+                                     int32_t n, int x, int y, int z, float g[Q]) {
+    pull_loads<St>(s, ch, n, x, y, z, g);
+    pull_walls(ch, y, g);
 }
 
 // On-site velocity walls (Chan::walls == 2; Eq. (23)-(30), turned to a y-normal wall).  The
