@@ -150,6 +150,84 @@ def test_closure_step_matches_oracle(orc, gpu, seed):
     assert g.error_flags() == 0
 
 
+def big_channel():
+    """A walled channel larger than one pass of the closure launch's workgroups, so that each
+    workgroup walks several segments, the next one's loads in flight while it evaluates the
+    network on the current one; its cell count is not a multiple of 64 (a partial last
+    segment)."""
+    import torch
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    nx, ny = 135, 67
+    nz = int(np.ceil(1.2 * 32 * cus * 64 / (nx * ny)))
+    if (nx * ny * nz) % 64 == 0:
+        nz += 1
+    return inputs.Channel(nx, ny, nz, 0.75, body=(2e-6, 0, 0), u_wall_hi=(0.04, 0, 0.01))
+
+
+def test_closure_step_matches_oracle_over_many_segments(orc, gpu):
+    """Two closure steps, each from the same float32 state on both sides: the first walks the
+    segments forwards, the second (odd buffer parity) backwards; each is held to the bounds of
+    the small channel's test."""
+    ch = big_channel()
+    o = make_state(orc, ch, 7, warm=2)
+    th = theta_bf16(np.random.default_rng(107))
+    nrm, flat = norm_for(o, 0.2)
+    g = gpu_lattice(gpu, ch, o)
+    g.set_closure(T(th), T(flat), 1e30)
+    for k in range(2):
+        if k:
+            o.f[...] = o.f.astype(np.float32).astype(np.float64)
+            g.set_populations(T(o.f.reshape(-1)))
+        dF, _ = co.correction(o.f, o.g, np.array(o.p.body[:]), th, nrm, c_guard=1e30, bf16=True)
+        size = np.abs(dF).max()
+        co.closure_step(o, th, nrm, c_guard=1e30, bf16=True)
+        g.step(1)
+        cell_err = np.abs(shifted(N(g.populations()), ch) - shifted(o.f, ch)).max(axis=0)
+        med, err = np.median(cell_err), cell_err.max()
+        print("closure step %d, %d cells: max|dF| %.3e, median cell err %.3e, max err %.3e"
+              % (k, ch.nx * ch.ny * ch.nz, size, med, err))
+        assert size > 1e-6
+        assert med <= 1e-4 * size + 6e-8
+        assert err <= 4e-3 * size + 6e-8
+    assert g.error_flags() == 0
+
+
+def test_zero_last_layer_is_bitwise_plain_coupled_step_over_many_segments(gpu):
+    """Coupled steps with platelets on a channel where every closure workgroup walks several
+    segments: with a zeroed last layer the closure step (whose IB force is loaded an iteration
+    ahead) gives the plain coupled step's populations and node positions bit for bit."""
+    import torch
+
+    big = big_channel()
+    ch = inputs.shear_platelets(seed=5, nx=big.nx, ny=big.ny, nz=big.nz, count=3, nodes=642, tau=0.75,
+                                u_top=0.04)
+    b = ch.bodies
+    th = theta_bf16(np.random.default_rng(9), zero_last=True)
+    flat = np.concatenate([np.zeros(16), np.ones(16), np.full(16, 0.1)])
+
+    def run(closure):
+        g = gpu.Lattice([ch], max_nodes=b.n, device=DEV)
+        g.init()
+        g.set_nodes(b.n)
+        gm = gpu.Membrane(b, device=DEV)
+        X = T(b.X, np.float64)
+        F = torch.zeros((3, b.n), dtype=torch.float32, device=DEV)
+        U = torch.zeros_like(F)
+        if closure:
+            g.set_closure(T(th), T(flat), 1.0)
+        g.coupled_steps(gm, 3, X, F, U)
+        assert g.error_flags() == 0
+        if closure:
+            assert g.closure_guarded() == 0
+        return N(g.populations()), N(X)
+
+    pa, Xa = run(False)
+    pb, Xb = run(True)
+    assert np.array_equal(pa, pb)
+    assert np.array_equal(Xa, Xb)
+
+
 def test_guard_falls_back_to_plain_step(orc, gpu):
     o = make_state(orc, CH, 4)
     th = theta_bf16(np.random.default_rng(5))
