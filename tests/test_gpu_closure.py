@@ -193,10 +193,12 @@ def test_closure_step_matches_oracle_over_many_segments(orc, gpu):
     assert g.error_flags() == 0
 
 
-def test_zero_last_layer_is_bitwise_plain_coupled_step_over_many_segments(gpu):
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_zero_last_layer_is_bitwise_plain_coupled_step_over_many_segments(gpu, storage):
     """Coupled steps with platelets on a channel where every closure workgroup walks several
     segments: with a zeroed last layer the closure step (whose IB force is loaded an iteration
-    ahead) gives the plain coupled step's populations and node positions bit for bit."""
+    ahead) gives the plain coupled step's populations and node positions bit for bit, in each
+    storage form."""
     import torch
 
     big = big_channel()
@@ -207,7 +209,7 @@ def test_zero_last_layer_is_bitwise_plain_coupled_step_over_many_segments(gpu):
     flat = np.concatenate([np.zeros(16), np.ones(16), np.full(16, 0.1)])
 
     def run(closure):
-        g = gpu.Lattice([ch], max_nodes=b.n, device=DEV)
+        g = gpu.Lattice([ch], storage=storage, max_nodes=b.n, device=DEV)
         g.init()
         g.set_nodes(b.n)
         gm = gpu.Membrane(b, device=DEV)
