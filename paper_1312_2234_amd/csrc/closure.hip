@@ -908,8 +908,12 @@ hipError_t launch_mlp_pack(hipStream_t s, const float* params, const float* norm
 
 template <class St>
 static hipError_t step_cl_typed(lbm_ctx* c, const LatArgs& a) {
+    // 8 workgroups per CU (three of them resident at a time); where that would leave each
+    // workgroup fewer than two passes over its four segments, 3 per CU, so that the loads of a
+    // next segment issued during each pass find one
     const int64_t units = (c->total_segs + 3) / 4;
-    int64_t grid = c->ib_grid * 2;  // resident workgroups (8 per CU)
+    const int64_t wide = c->ib_grid * 2, resident = c->ib_grid * 3 / 4;
+    int64_t grid = units >= 2 * wide ? wide : resident;
     if (grid > units) grid = units;
     unsigned long long* cnt = (unsigned long long*)(c->d_flags + 2);
     if (c->launch.nontemporal)
